@@ -1,0 +1,190 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module draws random numbers and lays them out; it holds none of the
+method's arithmetic (no gradient, Gram, multiplier, step or
+orthonormalization).  Both the CPU oracle and the GPU path consume exactly the
+arrays produced here, so their results can be compared element by element.
+
+Recipes follow the problems of Section 5.2 of the paper (Problem 1: the
+simplified Kohn-Sham energy with a Hartree-like term; Problem 3: Rayleigh-Ritz
+trace minimization) with the operators made explicit:
+
+* ``stencil1d``: L = tridiag(-1, 2, -1) (1D Dirichlet Laplacian, unscaled),
+  plus an optional diagonal potential ``v``;
+* ``stencil3d``: L = the 7-point Dirichlet Laplacian on an (nx, ny, nz) grid
+  (6 on the diagonal, -1 to each of the 6 neighbours), plus ``v``;
+* ``dense``: a dense symmetric A = (B + B^T) / (2 sqrt(n)) + 4 I, B ~ N(0, 1).
+
+The objective for every kind is
+    f(X) = 1/2 tr(X^T (L + Diag v) X) + alpha/4 rho^T L^{-1} rho,
+    rho = diag(X X^T),
+with ``alpha = 0`` giving the quadratic problems (dense: L replaced by A).
+
+Initial points are X0 = Q from the QR factorization of an n x p N(0,1)
+matrix with diag(R) > 0, as in the experiments of Section 5.5.
+
+Seeds: workload ``c`` (1..5) draws from ``numpy.random.default_rng(20181009 + c)``
+in the fixed order operator data, then X0, then any auxiliary weights.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Tuple, List
+
+import numpy as np
+
+SEED_BASE = 20181009
+
+KIND_STENCIL1D = "stencil1d"
+KIND_STENCIL3D = "stencil3d"
+KIND_DENSE = "dense"
+
+
+@dataclass
+class Problem:
+    """Description of one instance of min f(X) s.t. X^T X = I_p."""
+
+    name: str
+    kind: str
+    n: int
+    p: int
+    alpha: float = 0.0
+    v: Optional[np.ndarray] = None          # diagonal potential, float64, length n
+    grid: Tuple[int, int, int] = (0, 1, 1)  # (nx, ny, nz), x fastest in the row index
+    A: Optional[np.ndarray] = None          # dense operator (row-major n x n)
+    s_bound: float = 0.0                    # upper bound of ||Hess f(0)||_2 (Section 5.1)
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.kind == KIND_STENCIL1D and self.grid[0] == 0:
+            self.grid = (self.n, 1, 1)
+        if self.n < 2 * self.p:
+            raise ValueError("the problem needs 2p <= n (Section 1)")
+
+
+def rng_for(config: int) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + config)
+
+
+def orthonormal_start(rng: np.random.Generator, n: int, p: int) -> np.ndarray:
+    """X0 = Q of QR(N(0,1) n x p) with diag(R) > 0, float64, C-contiguous."""
+    z = rng.standard_normal((n, p))
+    q, r = np.linalg.qr(z)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return np.ascontiguousarray(q * s[None, :])
+
+
+def quad_tridiag(n: int = 2000, p: int = 20, config: int = 1):
+    """Quadratic f = 1/2 tr(X^T A X), A = tridiag(-1,2,-1) + Diag(u), u ~ U(0,1)."""
+    rng = rng_for(config)
+    u = rng.uniform(0.0, 1.0, n)
+    x0 = orthonormal_start(rng, n, p)
+    prob = Problem(name=f"quad_tridiag_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p,
+                   alpha=0.0, v=u, grid=(n, 1, 1), s_bound=4.0 + float(u.max()))
+    return prob, x0
+
+
+def ks1d(n: int = 20000, p: int = 100, alpha: float = 1.0, config: int = 2,
+         with_potential: bool = False):
+    """1D Kohn-Sham-shaped f with the unscaled 1D Dirichlet Laplacian."""
+    rng = rng_for(config)
+    v = rng.uniform(0.0, 1.0, n) if with_potential else None
+    x0 = orthonormal_start(rng, n, p)
+    sb = 4.0 + (float(v.max()) if v is not None else 0.0)
+    prob = Problem(name=f"ks1d_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p,
+                   alpha=float(alpha), v=v, grid=(n, 1, 1), s_bound=sb)
+    return prob, x0
+
+
+def ks3d(grid=(64, 64, 64), p: int = 256, alpha: float = 1.0, config: int = 5):
+    """3D Kohn-Sham-shaped f: 7-point Laplacian + Diag(V), V ~ U(0,1).
+
+    Returns (problem, X0, w) where w ~ U(0,1) are the weights of the loss
+    ||X^T Diag(w) X||_F^2 used by the adjoint.
+    """
+    rng = rng_for(config)
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    v = rng.uniform(0.0, 1.0, n)
+    x0 = orthonormal_start(rng, n, p)
+    w = rng.uniform(0.0, 1.0, n)
+    prob = Problem(name=f"ks3d_{nx}x{ny}x{nz}_p{p}", kind=KIND_STENCIL3D, n=n, p=p,
+                   alpha=float(alpha), v=v, grid=(nx, ny, nz),
+                   s_bound=12.0 + float(v.max()))
+    return prob, x0, w
+
+
+def dense_quadratic(n: int = 32768, p: int = 512, config: int = 3,
+                    dtype=np.float32, power_iters: int = 30):
+    """Dense Rayleigh-Ritz instance A = (B + B^T)/(2 sqrt n) + 4 I, B ~ N(0,1).
+
+    A is returned in ``dtype`` (float32 by default); the oracle and the GPU
+    both consume exactly these values.  The returned ``s_bound`` is a power
+    iteration estimate of ||A||_2 with a 5% margin (it only sets beta/eta0).
+    """
+    rng = rng_for(config)
+    b = rng.standard_normal((n, n), dtype=np.float32)
+    a = np.empty((n, n), dtype=dtype)
+    scale = 1.0 / (2.0 * np.sqrt(n))
+    blk = 2048
+    for i0 in range(0, n, blk):
+        i1 = min(n, i0 + blk)
+        a[i0:i1, :] = ((b[i0:i1, :] + b[:, i0:i1].T) * scale).astype(dtype)
+    del b
+    a[np.arange(n), np.arange(n)] += dtype(4.0)
+    x0 = orthonormal_start(rng, n, p)
+    # spectral-norm estimate for the parameter rule (not part of the method)
+    t = np.ones(n, dtype=np.float64) / np.sqrt(n)
+    lam = 0.0
+    for _ in range(power_iters):
+        y = a @ t.astype(dtype)
+        lam = float(np.linalg.norm(y))
+        t = (y / lam).astype(np.float64)
+    prob = Problem(name=f"dense_n{n}_p{p}", kind=KIND_DENSE, n=n, p=p, alpha=0.0,
+                   A=a, grid=(n, 1, 1), s_bound=1.05 * lam)
+    return prob, x0
+
+
+def batched_ks1d(nprob: int = 256, config: int = 4, n_range=(1000, 20000),
+                 p_range=(8, 128), alpha_range=(0.5, 2.0)):
+    """Many independent 1D KS problems of uneven n and p.
+
+    Operator data for all problems is drawn first (n, p, alpha per problem),
+    then the X0 of each problem in order.
+    """
+    rng = rng_for(config)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=nprob)
+    ps = rng.integers(p_range[0], p_range[1] + 1, size=nprob)
+    alphas = rng.uniform(alpha_range[0], alpha_range[1], size=nprob)
+    probs: List[Problem] = []
+    x0s: List[np.ndarray] = []
+    for b in range(nprob):
+        n, p = int(ns[b]), int(ps[b])
+        probs.append(Problem(name=f"batch{b}_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p,
+                             alpha=float(alphas[b]), v=None, grid=(n, 1, 1),
+                             s_bound=4.0))
+    for b in range(nprob):
+        x0s.append(orthonormal_start(rng, probs[b].n, probs[b].p))
+    return probs, x0s
+
+
+def random_matrix(config: int, shape, salt: int = 0) -> np.ndarray:
+    """A seeded N(0,1) matrix for unit tests of individual steps."""
+    rng = np.random.default_rng([SEED_BASE + config, salt])
+    return rng.standard_normal(shape)
+
+
+def random_uniform(config: int, shape, lo=0.0, hi=1.0, salt: int = 0) -> np.ndarray:
+    rng = np.random.default_rng([SEED_BASE + config, salt])
+    return rng.uniform(lo, hi, shape)
+
+
+# Named workloads with the sizes of the benchmark configurations.
+FULL_SIZES = {
+    1: dict(kind="quad_tridiag", n=2000, p=20),
+    2: dict(kind="ks1d", n=20000, p=100),
+    3: dict(kind="dense", n=32768, p=512),
+    4: dict(kind="batched_ks1d", nprob=256),
+    5: dict(kind="ks3d", grid=(64, 64, 64), p=256),
+}
