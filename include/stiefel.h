@@ -1,0 +1,256 @@
+/*
+ * stiefel.h - C ABI of the MI355X (gfx950) PLAM / PCAL solver library.
+ *
+ * Solves  min f(X)  s.t.  X^T X = I_p,  X in R^{n x p}, 2p <= n  (Section 1 of
+ * Gao, Liu, Yuan, "Parallelizable Algorithms for Optimization Problems with
+ * Orthogonality Constraints") with
+ *   PLAM (Algorithm 2): X <- X - grad_X L_beta(X, Lam) / eta,
+ *                       Lam = Psi(grad f(X)^T X)        (Section 3.1)
+ *   PCAL (Algorithm 3): the same point with every column scaled to unit
+ *                       2-norm, Lam optionally corrected by
+ *                       Phi(X^T grad_X L_beta(X, Psi(.)))  (Section 3.2)
+ * and one CholeskyQR2 orthonormalization of the last iterate (the
+ * post-process of Section 5.3 / Table 2).
+ *
+ * Objective families (the test problems of Section 5.2):
+ *   f(X) = 1/2 tr(X^T (L + Diag v) X) + alpha/4 rho^T L^{-1} rho,
+ *   rho  = diag(X X^T),
+ * with L the unscaled 1D Dirichlet Laplacian tridiag(-1,2,-1)
+ * (STF_KIND_STENCIL1D) or the 7-point Dirichlet Laplacian on an nx*ny*nz grid
+ * (STF_KIND_STENCIL3D), or the quadratic f(X) = 1/2 tr(X^T A X) with a dense
+ * symmetric A (STF_KIND_DENSE).
+ *
+ * Conventions for every entry point
+ *   - Matrices are row-major.  X is n x p with row r holding grid point r;
+ *     for 3D grids r = x + nx*(y + ny*z).
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller owns all
+ *     memory; the library never allocates or frees device memory and keeps no
+ *     global state, so calls on different streams with different workspaces
+ *     are independent.
+ *   - All device work is enqueued on `stream`; the solve entry points return
+ *     after the final status has been read back (host-synchronous).
+ *   - Return codes: STF_OK (0), STF_MAX_ITER (1, a result is still filled),
+ *     or a negative STF_E_* code; stf_strerror() names them.  No C++
+ *     exception crosses this boundary.
+ */
+#ifndef STIEFEL_H
+#define STIEFEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enums ------------------------------------------------------------- */
+#define STF_KIND_STENCIL1D 0
+#define STF_KIND_STENCIL3D 1
+#define STF_KIND_DENSE     2
+
+#define STF_F64 0
+#define STF_F32 1
+
+#define STF_PLAM 0
+#define STF_PCAL 1
+
+/* multiplier: eq. (Lambda1) Psi(G^T X); eq. (lambda2) adds the Phi term (PCAL) */
+#define STF_MULT_PSI     0
+#define STF_MULT_PSI_PHI 1
+
+/* proximal parameter eta (Section 5.1): constant, differential, BB1, BB2,
+ * alternating BB (BB1 at odd k, BB2 at even k) */
+#define STF_ETA_CONST 0
+#define STF_ETA_DIFF  1
+#define STF_ETA_BB1   2
+#define STF_ETA_BB2   3
+#define STF_ETA_ABB   4
+
+/* BB pair: STANDARD uses S = X^k - X^{k-1}, Y = gradL^k - gradL^{k-1} for
+ * eta^k; LAGGED uses S^{k-1}, Y^{k-1} as printed in Section 5.1. */
+#define STF_BB_STANDARD 0
+#define STF_BB_LAGGED   1
+
+/* arithmetic of the iteration:
+ *   FP64  - X, G in float64, float64 MFMA / VALU everywhere;
+ *   FP32  - X, G in float32, float32 MFMA products, float64 accumulation of
+ *           every reduction over n, float64 p x p stage;
+ *   MIXED - as FP32, but the Gram products use split-bf16 (three bf16 MFMA
+ *           products, float32 tile accumulation) and the row-block products
+ *           use split-fp16 with a power-of-two scale.
+ * The p x p multiplier stage, the KKT test and CholeskyQR2 are float64 in
+ * every mode. */
+#define STF_PREC_FP64  0
+#define STF_PREC_FP32  1
+#define STF_PREC_MIXED 2
+
+/* ---- return codes -------------------------------------------------------- */
+#define STF_OK               0
+#define STF_MAX_ITER         1
+#define STF_E_INVALID       -1   /* bad argument: p <= 0, n < 2p, NULL, dtype, sizes */
+#define STF_E_DIVERGED      -2   /* non-finite values or ||X^T X - I||_F above feas_blowup */
+#define STF_E_HIP           -3   /* a HIP runtime call failed */
+#define STF_E_UNSUPPORTED   -4   /* option combination not supported */
+#define STF_E_WORKSPACE     -5   /* workspace smaller than stf_workspace_size() */
+#define STF_E_CHOLESKY      -6   /* CholeskyQR2 met a non-positive pivot (rank-deficient X) */
+
+/* ---- problem descriptor ---------------------------------------------------
+ * kind   : STF_KIND_*
+ * n, p   : sizes, 1 <= p, 2p <= n (Section 1); p <= 1024
+ * grid   : (nx, ny, nz); STENCIL1D requires (n, 1, 1); STENCIL3D nx*ny*nz == n
+ * alpha  : weight of the Hartree-like term alpha/4 rho^T L^{-1} rho (stencil kinds)
+ * v      : device, float64, length n: diagonal potential added to L; may be NULL
+ * A      : device, dense symmetric n x n (STF_KIND_DENSE), dtype A_dtype
+ *          (STF_F64 or STF_F32); its symmetry is assumed, not checked.       */
+typedef struct stf_problem {
+    int32_t kind;
+    int32_t p;
+    int64_t n;
+    int32_t grid[3];
+    int32_t A_dtype;
+    double alpha;
+    const double* v;
+    const void* A;
+} stf_problem;
+
+/* ---- options --------------------------------------------------------------
+ * beta        : penalty parameter of L_beta (Section 5.1)
+ * eta0        : eta at k = 0 (the paper leaves it open; an input here)
+ * eta_const   : gamma of STF_ETA_CONST
+ * tol         : stop when ||G - X Psi(G^T X)||_F <= tol * (same at X^0)
+ *               (Section 5.1; 0 runs exactly max_iter updates)
+ * max_iter    : number of updates at most
+ * kkt_every   : evaluate the stop test every kkt_every iterations (>= 1)
+ * orth_final  : 1 = CholeskyQR2 of the returned iterate (float64)
+ * check_every : the host reads the device "done" flag every check_every
+ *               iterations (>= 1); iterations after "done" are no-ops
+ * use_graph   : 1 = replay the iteration chunk as a captured HIP graph
+ *               (ignored on the legacy default stream, which cannot be captured)
+ * profile     : 1 = bracket every kernel group of every iteration with HIP
+ *               events (no graph) and report per-group times in
+ *               stf_result.kernel_ms / prof_iters
+ * feas_blowup : divergence threshold on ||X^T X - I||_F (e.g. 1e3)          */
+typedef struct stf_options {
+    int32_t variant;
+    int32_t mult_rule;
+    int32_t eta_rule;
+    int32_t bb_index;
+    int32_t precision;
+    int32_t max_iter;
+    int32_t kkt_every;
+    int32_t orth_final;
+    int32_t check_every;
+    int32_t use_graph;
+    int32_t profile;
+    int32_t reserved;
+    double beta;
+    double eta0;
+    double eta_const;
+    double tol;
+    double feas_blowup;
+} stf_options;
+
+/* ---- result (host struct) -------------------------------------------------
+ * status  : STF_OK / STF_MAX_ITER / STF_E_DIVERGED
+ * iters   : index k of the returned iterate X^k (number of updates made)
+ * kkt0    : ||G - X Psi(G^T X)||_F at X^0 (iteration precision)
+ * kkt_abs : the same at the returned point, float64 (after CholeskyQR2 if
+ *           orth_final), kkt_rel = kkt_abs / kkt0
+ * feas    : ||X^T X - I||_F at the returned point, float64
+ * fval    : f at the returned point, float64
+ * eta_last: the last eta used
+ * ms_loop : wall time of the iteration loop (device events)
+ * ms_orth : wall time of CholeskyQR2 + the float64 final evaluation
+ * kernel_ms[STF_NPROF] : with opt->profile, summed device time of each
+ *           kernel group (STF_PROF_*) over prof_iters iterations          */
+#define STF_PROF_HARTREE  0
+#define STF_PROF_GRAD     1
+#define STF_PROF_GRAM     2
+#define STF_PROF_STAGE1   3
+#define STF_PROF_RESIDUAL 4
+#define STF_PROF_STAGE2   5
+#define STF_PROF_UPDATE   6
+#define STF_NPROF         7
+typedef struct stf_result {
+    int32_t status;
+    int32_t iters;
+    double kkt0;
+    double kkt_abs;
+    double kkt_rel;
+    double feas;
+    double fval;
+    double eta_last;
+    double ms_loop;
+    double ms_orth;
+    double kernel_ms[8];
+    int32_t prof_iters;
+    int32_t reserved;
+} stf_result;
+
+/* Bytes of device workspace needed by stf_solve / plam_solve / pcal_solve and
+ * by every step-level entry point for this problem (opt may be NULL: then the
+ * largest requirement over the precision modes is returned). */
+size_t stf_workspace_size(const stf_problem* prob, const stf_options* opt);
+
+/* Run PLAM or PCAL (opt->variant) from X^0.
+ *   X       : device, n x p, float64 (precision FP64) or float32 (FP32 and
+ *             MIXED); in: X^0, out: the returned iterate (after CholeskyQR2
+ *             when orth_final, rounded to X's dtype)
+ *   X64_out : device, n x p float64, may be NULL: the float64 result
+ *   Lam_out : device, p x p float64, may be NULL: Psi(grad f(X)^T X) at the
+ *             returned point (the multiplier of eq. (closed-multi))
+ *   ws      : device workspace of ws_bytes >= stf_workspace_size(prob, opt)
+ *   res     : host, filled on return codes >= 0 and on STF_E_DIVERGED */
+int stf_solve(const stf_problem* prob, void* X, const stf_options* opt,
+              void* ws, size_t ws_bytes, double* X64_out, double* Lam_out,
+              stf_result* res, hipStream_t stream);
+
+/* stf_solve with opt->variant forced to STF_PLAM / STF_PCAL (Algorithms 2, 3). */
+int plam_solve(const stf_problem* prob, void* X, const stf_options* opt,
+               void* ws, size_t ws_bytes, double* X64_out, double* Lam_out,
+               stf_result* res, hipStream_t stream);
+int pcal_solve(const stf_problem* prob, void* X, const stf_options* opt,
+               void* ws, size_t ws_bytes, double* X64_out, double* Lam_out,
+               stf_result* res, hipStream_t stream);
+
+/* ---- step-level entry points (each is one step of the iteration) --------- */
+
+/* G = grad f(X) = (L + Diag v) X + alpha Diag(L^{-1} rho) X, or A X (dense).
+ * X, G: device n x p of dtype (STF_F64 / STF_F32); the dense kind requires
+ * dtype == A_dtype.  Computes rho and the Hartree solve internally. */
+int stf_gradient(const stf_problem* prob, const void* X, void* G, int32_t dtype,
+                 void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* phi = L^{-1} rho for the stencil kinds (the L^dagger of eq. (KS-energy));
+ * rho, phi: device float64 length n.  1D: closed-form Green's function by
+ * two scans; 3D: sine transforms along each axis. */
+int stf_hartree(const stf_problem* prob, const double* rho, double* phi,
+                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* S = X^T X and W = X^T G (both p x p float64, full), the Gram products of
+ * Table 1.  precision selects the product arithmetic (STF_PREC_*; FP64
+ * needs dtype F64, the others F32). */
+int stf_gram(const stf_problem* prob, const void* X, const void* G, int32_t dtype,
+             int32_t precision, double* S, double* W, void* ws, size_t ws_bytes,
+             hipStream_t stream);
+
+/* In-place CholeskyQR2 of a float64 n x p X (full column rank). */
+int stf_cholqr2(const stf_problem* prob, double* X, void* ws, size_t ws_bytes,
+                hipStream_t stream);
+
+/* out3 (host, 3 doubles) = { f(X), ||G - X Psi(G^T X)||_F, ||X^T X - I||_F }
+ * in float64 for a float64 X. */
+int stf_eval(const stf_problem* prob, const double* X, double* out3,
+             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Human-readable name of a return code (static string). */
+const char* stf_strerror(int code);
+
+/* Library version string. */
+const char* stf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STIEFEL_H */

@@ -1,0 +1,603 @@
+// C ABI and host driver of the PLAM / PCAL solver (declared in include/stiefel.h).
+//
+// The driver enqueues whole iterations without reading anything back; the
+// device state (stf::DevState) decides convergence.  Every `check_every`
+// iterations the host copies the state once and stops when it says "done".
+// With use_graph, a chunk of check_every iterations (an even count, so the
+// G double-buffer parity repeats) is captured once and replayed.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "stf_internal.h"
+
+namespace stf {
+
+int elem_size(int dtype) { return dtype == STF_F64 ? 8 : 4; }
+
+GramPlan make_gram_plan(int64_t n, int p) {
+    GramPlan g;
+    g.wm = (p <= 32) ? 1 : (p <= 64 ? 2 : 4);
+    g.bt = 32 * g.wm;
+    g.nb = (p + g.bt - 1) / g.bt;
+    g.n_s_tiles = g.nb * (g.nb + 1) / 2;
+    g.n_tiles = g.n_s_tiles + g.nb * g.nb;
+    const int64_t target_wg = 1024;
+    int64_t nch = (target_wg + g.n_tiles - 1) / g.n_tiles;
+    const int64_t max_ch = std::max<int64_t>(1, n / 256);
+    nch = std::min(nch, max_ch);
+    nch = std::max<int64_t>(nch, 1);
+    int64_t chunk = (n + nch - 1) / nch;
+    chunk = (chunk + 3) / 4 * 4;
+    g.chunk = chunk;
+    g.nchunks = (int)((n + chunk - 1) / chunk);
+    return g;
+}
+
+ResPlan make_res_plan(int64_t n, int p) {
+    ResPlan r;
+    r.ncb = (p + 63) / 64;
+    r.nrt = (n + 63) / 64;
+    int64_t nrb = (2048 + r.ncb - 1) / r.ncb;
+    nrb = std::min<int64_t>(nrb, r.nrt);
+    r.nrb = (int)std::max<int64_t>(nrb, 1);
+    return r;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(const stf_problem* prob, int precision) {
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    const int64_t n = prob->n;
+    const int p = prob->p;
+    const int dt = (precision == STF_PREC_FP64) ? STF_F64 : STF_F32;
+    const size_t np = (size_t)n * p;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.state = take(sizeof(DevState));
+    L.state_eval = take(sizeof(DevState));
+    L.params = take(sizeof(DevParams));
+    L.params_eval = take(sizeof(DevParams));
+    L.g[0] = take(np * elem_size(dt));
+    L.g[1] = take(np * elem_size(dt));
+    if (dt == STF_F64) {
+        L.x64 = (size_t)-1;  // X itself
+        L.g64 = L.g[0];
+    } else {
+        L.x64 = take(np * 8);
+        L.g64 = take(np * 8);
+    }
+    L.rho = take((size_t)n * 8);
+    L.phi = take((size_t)n * 8);
+    L.hscr = take((size_t)n * 8);
+    const size_t pp = (size_t)p * p * 8;
+    L.S = take(pp);
+    L.W = take(pp);
+    L.Psi = take(pp);
+    L.ML = take(pp);
+    L.Rm = take(pp);
+    L.Rinv = take(pp);
+    L.Lam = take(pp);
+    L.nu = take((size_t)p * 8);
+    L.colxg = take((size_t)p * 8);
+    L.colgg = take((size_t)p * 8);
+    L.gram = make_gram_plan(n, p);
+    L.gram64 = L.gram;
+    L.gram_part = take((size_t)L.gram.nchunks * L.gram.n_tiles * L.gram.bt * L.gram.bt * 8);
+    L.res = make_res_plan(n, p);
+    L.res_col = take((size_t)L.res.nrb * p * 2 * 8);
+    L.res_scal = take((size_t)L.res.nrb * L.res.ncb * 4 * 8);
+    L.dots = take(512 * 2 * 8);
+    if (prob->kind == STF_KIND_STENCIL3D) {
+        const size_t nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
+        L.dst = take((nx * nx + ny * ny + nz * nz + nx + ny + nz) * 8);
+    } else {
+        L.dst = take(8);
+    }
+    {
+        const size_t prow = (size_t)L.res.ncb * 64, pk = (size_t)(p + 31) / 32 * 32;
+        L.mix = take(2 * 3 * prow * pk * 2);
+    }
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------ helpers ----
+struct Ws {
+    char* base;
+    Layout L;
+    template <typename T> T* at(size_t o) const { return (T*)(base + o); }
+};
+
+static int check_problem(const stf_problem* prob) {
+    if (!prob) return STF_E_INVALID;
+    if (prob->p <= 0 || prob->p > 1024) return STF_E_INVALID;
+    if (prob->n < 2 * (int64_t)prob->p) return STF_E_INVALID;
+    if (prob->kind == STF_KIND_STENCIL1D) {
+        if (prob->grid[0] != prob->n || prob->grid[1] != 1 || prob->grid[2] != 1)
+            return STF_E_INVALID;
+    } else if (prob->kind == STF_KIND_STENCIL3D) {
+        if (prob->grid[0] <= 0 || prob->grid[1] <= 0 || prob->grid[2] <= 0) return STF_E_INVALID;
+        if ((int64_t)prob->grid[0] * prob->grid[1] * prob->grid[2] != prob->n)
+            return STF_E_INVALID;
+    } else if (prob->kind == STF_KIND_DENSE) {
+        if (!prob->A) return STF_E_INVALID;
+        if (prob->A_dtype != STF_F64 && prob->A_dtype != STF_F32) return STF_E_INVALID;
+        if (prob->n > 2147483647LL) return STF_E_INVALID;
+    } else {
+        return STF_E_INVALID;
+    }
+    if (!isfinite(prob->alpha)) return STF_E_INVALID;
+    return STF_OK;
+}
+
+static bool has_hartree(const stf_problem* prob) {
+    return prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return STF_E_HIP;   \
+    } while (0)
+
+static int last_launch() { return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP; }
+
+// G = grad f(X) using the workspace's rho / phi (no device state).
+static int enqueue_gradient(const stf_problem* prob, const Ws& w, int dtype, const void* X,
+                            void* G, const DevState* st, hipStream_t s) {
+    if (has_hartree(prob)) {
+        launch_rowsq(dtype, X, prob->n, prob->p, w.at<double>(w.L.rho), st, s);
+        launch_hartree(prob, w.at<double>(w.L.rho), w.at<double>(w.L.phi),
+                       w.at<double>(w.L.hscr), w.at<double>(w.L.dst), st, s);
+    }
+    launch_grad(prob, dtype, X, G, w.at<double>(w.L.phi), st, s);
+    return last_launch();
+}
+
+// In-place CholeskyQR2 of a float64 X using tmp (n x p float64).
+static int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp,
+                           DevState* st, hipStream_t s) {
+    const int64_t n = prob->n;
+    const int p = prob->p;
+    double* a = X;
+    double* b = tmp;
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, a, a, n, p, w.at<double>(w.L.gram_part),
+                    w.at<double>(w.L.S), nullptr, nullptr, s);
+        launch_chol_inv(w.at<double>(w.L.S), w.at<double>(w.L.Rm), w.at<double>(w.L.Rinv), p, st,
+                        s);
+        launch_apply(STF_F64, w.L.res, a, b, w.at<double>(w.L.Rinv), n, p, s);
+        std::swap(a, b);
+    }
+    return last_launch();
+}
+
+// f, KKT and feasibility of a float64 X in float64 (G64 is overwritten).
+static int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* G64,
+                        hipStream_t s) {
+    const int64_t n = prob->n;
+    const int p = prob->p;
+    DevState* st = w.at<DevState>(w.L.state_eval);
+    DevParams* prm = w.at<DevParams>(w.L.params_eval);
+    launch_init_state(st, s);
+    DevParams hp;
+    memset(&hp, 0, sizeof(hp));
+    hp.beta = 0.0;
+    hp.variant = STF_PLAM;
+    hp.mult_rule = STF_MULT_PSI;
+    hp.kkt_every = 1;
+    hp.max_iter = 0;
+    hp.feas_blowup = INFINITY;
+    HIPCHK(hipMemcpyAsync(prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    int rc = enqueue_gradient(prob, w, STF_F64, X, G64, nullptr, s);
+    if (rc) return rc;
+    launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, X, G64, n, p, w.at<double>(w.L.gram_part),
+                w.at<double>(w.L.S), w.at<double>(w.L.W), nullptr, s);
+    launch_stage1(prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
+                  w.at<double>(w.L.ML), p, st, s);
+    // the dot products read G before the KKT pass (which does not write in this mode)
+    launch_residual(STF_F64, STF_PREC_FP64, w.L.res, X, G64, nullptr, w.at<double>(w.L.ML),
+                    w.at<double>(w.L.Psi), nullptr, n, p, w.at<double>(w.L.res_col),
+                    w.at<double>(w.L.res_scal), prm, st, RES_KKT_ONLY, nullptr, s);
+    launch_eval_finish(prob, X, G64, w.at<double>(w.L.rho), w.at<double>(w.L.phi),
+                       w.at<double>(w.L.S), n, p, w.at<double>(w.L.dots),
+                       w.at<double>(w.L.res_scal), w.L.res.nrb * w.L.res.ncb, st, s);
+    return last_launch();
+}
+
+struct IterCtx {
+    const stf_problem* prob;
+    Ws w;
+    int dtype, precision;
+    void* X;
+    DevState* st;
+    DevParams* prm;
+};
+
+// ev (optional): STF_NPROF + 1 events bracketing the kernel groups.
+static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
+                              hipEvent_t* ev = nullptr) {
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    };
+    const stf_problem* prob = c.prob;
+    const Ws& w = c.w;
+    const int64_t n = prob->n;
+    const int p = prob->p;
+    void* Gc = w.base + w.L.g[parity];
+    void* Gp = w.base + w.L.g[parity ^ 1];
+    double* rho = has_hartree(prob) ? w.at<double>(w.L.rho) : nullptr;
+    mark(0);
+    if (has_hartree(prob))
+        launch_hartree(prob, rho, w.at<double>(w.L.phi), w.at<double>(w.L.hscr),
+                       w.at<double>(w.L.dst), c.st, s);
+    mark(1);
+    launch_grad(prob, c.dtype, c.X, Gc, w.at<double>(w.L.phi), c.st, s);
+    mark(2);
+    launch_gram(c.dtype, c.precision, w.L.gram, c.X, Gc, n, p, w.at<double>(w.L.gram_part),
+                w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s);
+    mark(3);
+    launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
+                  w.at<double>(w.L.ML), p, c.st, s);
+    mark(4);
+    launch_residual(c.dtype, c.precision, w.L.res, c.X, Gc, Gp, w.at<double>(w.L.ML),
+                    w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
+                    w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
+                    RES_ITERATE, w.base + w.L.mix, s);
+    mark(5);
+    launch_stage2(c.prm, w.L.res, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
+                  w.at<double>(w.L.S), w.at<double>(w.L.colxg), w.at<double>(w.L.colgg),
+                  w.at<double>(w.L.nu), p, c.st, s);
+    mark(6);
+    launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s);
+    mark(7);
+}
+
+static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, void* ws,
+                      size_t ws_bytes, double* X64_out, double* Lam_out, stf_result* res,
+                      hipStream_t s) {
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (!X || !opt || !ws || !res) return STF_E_INVALID;
+    if (opt->variant != STF_PLAM && opt->variant != STF_PCAL) return STF_E_INVALID;
+    if (opt->mult_rule != STF_MULT_PSI && opt->mult_rule != STF_MULT_PSI_PHI)
+        return STF_E_INVALID;
+    if (opt->mult_rule == STF_MULT_PSI_PHI && opt->variant != STF_PCAL) return STF_E_UNSUPPORTED;
+    if (opt->eta_rule < STF_ETA_CONST || opt->eta_rule > STF_ETA_ABB) return STF_E_INVALID;
+    if (opt->bb_index != STF_BB_STANDARD && opt->bb_index != STF_BB_LAGGED) return STF_E_INVALID;
+    if (opt->precision < STF_PREC_FP64 || opt->precision > STF_PREC_MIXED) return STF_E_INVALID;
+    if (opt->max_iter < 0 || opt->kkt_every < 1 || opt->check_every < 1) return STF_E_INVALID;
+    if (!(opt->eta0 > 0.0) || !(opt->tol >= 0.0) || !isfinite(opt->beta)) return STF_E_INVALID;
+    if (opt->eta_rule == STF_ETA_CONST && !(opt->eta_const > 0.0)) return STF_E_INVALID;
+    const int dtype = (opt->precision == STF_PREC_FP64) ? STF_F64 : STF_F32;
+    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != dtype) return STF_E_UNSUPPORTED;
+
+    Ws w;
+    w.base = (char*)ws;
+    w.L = make_layout(prob, opt->precision);
+    if (ws_bytes < w.L.total) return STF_E_WORKSPACE;
+    memset(res, 0, sizeof(*res));
+    const int64_t n = prob->n;
+    const int p = prob->p;
+
+    IterCtx c;
+    c.prob = prob;
+    c.w = w;
+    c.dtype = dtype;
+    c.precision = opt->precision;
+    c.X = X;
+    c.st = w.at<DevState>(w.L.state);
+    c.prm = w.at<DevParams>(w.L.params);
+
+    DevParams hp;
+    memset(&hp, 0, sizeof(hp));
+    hp.beta = opt->beta;
+    hp.eta0 = opt->eta0;
+    hp.eta_const = opt->eta_const;
+    hp.tol = opt->tol;
+    hp.feas_blowup = opt->feas_blowup > 0.0 ? opt->feas_blowup : INFINITY;
+    hp.variant = opt->variant;
+    hp.mult_rule = opt->mult_rule;
+    hp.eta_rule = opt->eta_rule;
+    hp.bb_index = opt->bb_index;
+    hp.max_iter = opt->max_iter;
+    hp.kkt_every = opt->kkt_every;
+    hp.n_scal_parts = w.L.res.nrb * w.L.res.ncb;
+    hp.n_col_parts = w.L.res.nrb;
+    HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    launch_init_state(c.st, s);
+    if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);
+    if (has_hartree(prob)) launch_rowsq(dtype, X, n, p, w.at<double>(w.L.rho), c.st, s);
+    if ((rc = last_launch())) return rc;
+
+    hipEvent_t e0, e1, e2;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventCreate(&e2));
+    HIPCHK(hipEventRecord(e0, s));
+
+    int chunk = std::max(1, opt->check_every);
+    if (opt->use_graph && (chunk & 1)) chunk += 1;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const bool prof = opt->profile != 0;
+    std::vector<hipEvent_t> pev;
+    if (prof) {
+        pev.resize((size_t)chunk * (STF_NPROF + 1));
+        for (auto& e : pev) HIPCHK(hipEventCreate(&e));
+    }
+    double kms[STF_NPROF] = {0};
+    int prof_iters = 0;
+    // the legacy default stream cannot be captured: run uncaptured there
+    if (opt->use_graph && !prof && s != nullptr) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < chunk; ++i) enqueue_iteration(c, i & 1, s);
+        if (hipStreamEndCapture(s, &graph) != hipSuccess) return STF_E_HIP;
+        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return STF_E_HIP;
+        }
+    }
+    DevState hs;
+    memset(&hs, 0, sizeof(hs));
+    const int64_t limit = (int64_t)opt->max_iter + 1;
+    int64_t enq = 0;
+    int hip_err = 0;
+    while (true) {
+        if (gexec) {
+            if (hipGraphLaunch(gexec, s) != hipSuccess) { hip_err = 1; break; }
+            enq += chunk;
+        } else {
+            for (int i = 0; i < chunk; ++i)
+                enqueue_iteration(c, (int)((enq + i) & 1), s,
+                                  prof ? &pev[(size_t)i * (STF_NPROF + 1)] : nullptr);
+            enq += chunk;
+            if (last_launch()) { hip_err = 1; break; }
+        }
+        if (hipMemcpyAsync(&hs, c.st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            hip_err = 1;
+            break;
+        }
+        if (prof) {
+            // iterations after "done" are no-ops; count only the ones that ran
+            const int64_t first = enq - chunk;
+            const int64_t last = hs.done ? (int64_t)hs.final_iter : enq - 1;
+            for (int i = 0; i < chunk && first + i <= last; ++i) {
+                hipEvent_t* e = &pev[(size_t)i * (STF_NPROF + 1)];
+                for (int g = 0; g < STF_NPROF; ++g) {
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e[g], e[g + 1]);
+                    kms[g] += ms;
+                }
+                ++prof_iters;
+            }
+        }
+        if (hs.done) break;
+        if (enq > limit + 2 * chunk) { hip_err = 1; break; }  // stage 2 ends every run by max_iter
+    }
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    for (auto& e : pev) (void)hipEventDestroy(e);
+    for (int g = 0; g < STF_NPROF; ++g) res->kernel_ms[g] = kms[g];
+    res->prof_iters = prof_iters;
+    if (hip_err) return STF_E_HIP;
+    HIPCHK(hipEventRecord(e1, s));
+
+    res->status = hs.status;
+    res->iters = hs.final_iter;
+    res->kkt0 = hs.kkt0;
+    res->eta_last = hs.eta;
+    if (hs.status == STF_E_DIVERGED) {
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        res->ms_loop = ms;
+        res->kkt_abs = res->kkt_rel = res->feas = res->fval = NAN;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipEventDestroy(e2);
+        return STF_E_DIVERGED;
+    }
+
+    // float64 copy of the returned iterate, CholeskyQR2, float64 evaluation
+    double* Xd;
+    double* tmp;
+    if (dtype == STF_F64) {
+        Xd = (double*)X;
+        tmp = w.at<double>(w.L.g[1]);
+    } else {
+        Xd = w.at<double>(w.L.x64);
+        tmp = w.at<double>(w.L.g64);
+        launch_convert(STF_F64, X, STF_F32, Xd, (size_t)n * p, s);
+    }
+    DevState* st_eval = w.at<DevState>(w.L.state_eval);
+    launch_init_state(st_eval, s);
+    if (opt->orth_final) {
+        if ((rc = enqueue_cholqr2(prob, w, Xd, tmp, st_eval, s))) return rc;
+    }
+    DevState he;
+    HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (opt->orth_final && he.info != 0) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipEventDestroy(e2);
+        return STF_E_CHOLESKY;
+    }
+    double* G64 = (dtype == STF_F64) ? w.at<double>(w.L.g[0]) : w.at<double>(w.L.g64);
+    if ((rc = enqueue_eval(prob, w, Xd, G64, s))) return rc;
+    if (Lam_out)
+        HIPCHK(hipMemcpyAsync(Lam_out, w.at<double>(w.L.Psi), (size_t)p * p * 8,
+                              hipMemcpyDeviceToDevice, s));
+    if (dtype == STF_F32) launch_convert(STF_F32, Xd, STF_F64, X, (size_t)n * p, s);
+    if (X64_out)
+        HIPCHK(hipMemcpyAsync(X64_out, Xd, (size_t)n * p * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(e2, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = last_launch())) return rc;
+    float ms1 = 0.f, ms2 = 0.f;
+    hipEventElapsedTime(&ms1, e0, e1);
+    hipEventElapsedTime(&ms2, e1, e2);
+    res->ms_loop = ms1;
+    res->ms_orth = ms2;
+    res->fval = he.red[0];
+    res->kkt_abs = he.red[1];
+    res->feas = he.red[2];
+    res->kkt_rel = (hs.kkt0 > 0.0) ? he.red[1] / hs.kkt0 : 0.0;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipEventDestroy(e2);
+    return hs.status;
+}
+
+}  // namespace stf
+
+using namespace stf;
+
+extern "C" {
+
+size_t stf_workspace_size(const stf_problem* prob, const stf_options* opt) {
+    if (check_problem(prob) != STF_OK) return 0;
+    if (opt) return make_layout(prob, opt->precision).total;
+    const size_t a = make_layout(prob, STF_PREC_FP64).total;
+    const size_t b = make_layout(prob, STF_PREC_FP32).total;
+    return a > b ? a : b;
+}
+
+int stf_solve(const stf_problem* prob, void* X, const stf_options* opt, void* ws,
+              size_t ws_bytes, double* X64_out, double* Lam_out, stf_result* res,
+              hipStream_t stream) {
+    return solve_impl(prob, X, opt, ws, ws_bytes, X64_out, Lam_out, res, stream);
+}
+
+int plam_solve(const stf_problem* prob, void* X, const stf_options* opt, void* ws,
+               size_t ws_bytes, double* X64_out, double* Lam_out, stf_result* res,
+               hipStream_t stream) {
+    if (!opt) return STF_E_INVALID;
+    stf_options o = *opt;
+    o.variant = STF_PLAM;
+    return solve_impl(prob, X, &o, ws, ws_bytes, X64_out, Lam_out, res, stream);
+}
+
+int pcal_solve(const stf_problem* prob, void* X, const stf_options* opt, void* ws,
+               size_t ws_bytes, double* X64_out, double* Lam_out, stf_result* res,
+               hipStream_t stream) {
+    if (!opt) return STF_E_INVALID;
+    stf_options o = *opt;
+    o.variant = STF_PCAL;
+    return solve_impl(prob, X, &o, ws, ws_bytes, X64_out, Lam_out, res, stream);
+}
+
+static int step_ws(const stf_problem* prob, void* ws, size_t ws_bytes, Ws& w) {
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (!ws) return STF_E_INVALID;
+    w.base = (char*)ws;
+    w.L = make_layout(prob, STF_PREC_FP32);  // the larger layout (has float64 scratch)
+    if (ws_bytes < w.L.total) return STF_E_WORKSPACE;
+    return STF_OK;
+}
+
+int stf_gradient(const stf_problem* prob, const void* X, void* G, int32_t dtype, void* ws,
+                 size_t ws_bytes, hipStream_t stream) {
+    Ws w;
+    int rc = step_ws(prob, ws, ws_bytes, w);
+    if (rc) return rc;
+    if (!X || !G || (dtype != STF_F64 && dtype != STF_F32)) return STF_E_INVALID;
+    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != dtype) return STF_E_UNSUPPORTED;
+    if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), stream);
+    rc = enqueue_gradient(prob, w, dtype, X, G, nullptr, stream);
+    if (rc) return rc;
+    return hipStreamSynchronize(stream) == hipSuccess ? last_launch() : STF_E_HIP;
+}
+
+int stf_hartree(const stf_problem* prob, const double* rho, double* phi, void* ws,
+                size_t ws_bytes, hipStream_t stream) {
+    Ws w;
+    int rc = step_ws(prob, ws, ws_bytes, w);
+    if (rc) return rc;
+    if (!rho || !phi || prob->kind == STF_KIND_DENSE) return STF_E_INVALID;
+    if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), stream);
+    launch_hartree(prob, rho, phi, w.at<double>(w.L.hscr), w.at<double>(w.L.dst), nullptr,
+                   stream);
+    return hipStreamSynchronize(stream) == hipSuccess ? last_launch() : STF_E_HIP;
+}
+
+int stf_gram(const stf_problem* prob, const void* X, const void* G, int32_t dtype,
+             int32_t precision, double* S, double* W, void* ws, size_t ws_bytes,
+             hipStream_t stream) {
+    Ws w;
+    int rc = step_ws(prob, ws, ws_bytes, w);
+    if (rc) return rc;
+    if (!X || !G || !S || !W) return STF_E_INVALID;
+    if (dtype != STF_F64 && dtype != STF_F32) return STF_E_INVALID;
+    if (precision < STF_PREC_FP64 || precision > STF_PREC_MIXED) return STF_E_INVALID;
+    if ((precision == STF_PREC_FP64) != (dtype == STF_F64)) return STF_E_UNSUPPORTED;
+    launch_gram(dtype, precision, w.L.gram, X, G, prob->n, prob->p,
+                w.at<double>(w.L.gram_part), S, W, nullptr, stream);
+    return hipStreamSynchronize(stream) == hipSuccess ? last_launch() : STF_E_HIP;
+}
+
+int stf_cholqr2(const stf_problem* prob, double* X, void* ws, size_t ws_bytes,
+                hipStream_t stream) {
+    Ws w;
+    int rc = step_ws(prob, ws, ws_bytes, w);
+    if (rc) return rc;
+    if (!X) return STF_E_INVALID;
+    DevState* st = w.at<DevState>(w.L.state_eval);
+    launch_init_state(st, stream);
+    rc = enqueue_cholqr2(prob, w, X, w.at<double>(w.L.g64), st, stream);
+    if (rc) return rc;
+    DevState he;
+    HIPCHK(hipMemcpyAsync(&he, st, sizeof(he), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (he.info != 0) return STF_E_CHOLESKY;
+    return last_launch();
+}
+
+int stf_eval(const stf_problem* prob, const double* X, double* out3, void* ws, size_t ws_bytes,
+             hipStream_t stream) {
+    Ws w;
+    int rc = step_ws(prob, ws, ws_bytes, w);
+    if (rc) return rc;
+    if (!X || !out3) return STF_E_INVALID;
+    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != STF_F64) return STF_E_UNSUPPORTED;
+    if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), stream);
+    rc = enqueue_eval(prob, w, X, w.at<double>(w.L.g64), stream);
+    if (rc) return rc;
+    DevState he;
+    HIPCHK(hipMemcpyAsync(&he, w.at<DevState>(w.L.state_eval), sizeof(he),
+                          hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    out3[0] = he.red[0];
+    out3[1] = he.red[1];
+    out3[2] = he.red[2];
+    return last_launch();
+}
+
+const char* stf_strerror(int code) {
+    switch (code) {
+        case STF_OK: return "converged";
+        case STF_MAX_ITER: return "maximum number of iterations reached";
+        case STF_E_INVALID: return "invalid argument";
+        case STF_E_DIVERGED: return "iteration diverged (non-finite values or infeasibility blow-up)";
+        case STF_E_HIP: return "HIP runtime error";
+        case STF_E_UNSUPPORTED: return "unsupported option combination";
+        case STF_E_WORKSPACE: return "workspace too small";
+        case STF_E_CHOLESKY: return "CholeskyQR2 met a non-positive pivot";
+        default: return "unknown status";
+    }
+}
+
+const char* stf_version(void) { return "stiefel-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations of the gfx950 PLAM / PCAL library: device-resident
+// iteration state, workspace layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/stiefel.h"
+
+namespace stf {
+
+// Iteration state kept in device memory so that no host round trip is needed
+// inside an iteration.  Written by the p x p stage kernels only.
+struct DevState {
+    double kkt0;          // ||G - X Psi||_F at X^0
+    double kkt;           // the last evaluated ||G - X Psi||_F
+    double feas;          // ||X^T X - I||_F of the current iterate
+    double eta;           // eta^k (valid after the stage-2 kernel of iteration k)
+    double ss, sy, yy;    // <S,S>, <S,Y>, <Y,Y> of the current iteration (standard pair)
+    double ss_l, sy_l, yy_l;  // the same from the previous iteration (lagged pair)
+    double fval;          // scratch for the evaluation kernels
+    double red[8];        // scratch for reductions
+    int32_t iter;         // k of the iteration being processed
+    int32_t done;         // 1 once converged / max_iter / diverged
+    int32_t status;       // STF_OK / STF_MAX_ITER / STF_E_DIVERGED
+    int32_t final_iter;   // index of the returned iterate
+    int32_t info;         // Cholesky failure pivot + 1, or 0
+    int32_t pad[3];
+};
+
+// Parameters the device kernels read (copied once per solve into the workspace).
+struct DevParams {
+    double beta, eta0, eta_const, tol, feas_blowup;
+    int32_t variant, mult_rule, eta_rule, bb_index, max_iter, kkt_every;
+    int32_t n_scal_parts;   // number of scalar partial slots written by the residual pass
+    int32_t n_col_parts;    // number of row-block column partials
+};
+
+// Tiling of the split-K Gram pass.
+struct GramPlan {
+    int wm;          // MFMA 16x16 tiles per wave per dimension (1, 2 or 4)
+    int bt;          // workgroup tile = 32 * wm
+    int nb;          // ceil(p / bt)
+    int n_s_tiles;   // upper-triangular blocks of S
+    int n_tiles;     // n_s_tiles + nb*nb (W blocks)
+    int nchunks;     // split-K chunks over the n rows
+    int64_t chunk;   // rows per chunk (multiple of 4)
+};
+
+// Tiling of the row-block x (p x p) product pass.
+struct ResPlan {
+    int nrb;         // row-block workgroups (each strides over 64-row tiles)
+    int ncb;         // ceil(p / 64) column blocks
+    int64_t nrt;     // ceil(n / 64) row tiles
+};
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+    size_t state, state_eval, params, params_eval;
+    size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
+    size_t x64, g64;      // float64 n*p buffers for CholeskyQR2 and the final evaluation
+    size_t rho, phi, hscr;
+    size_t S, W, Psi, ML, Rm, Rinv, Lam;
+    size_t nu, colxg, colgg;
+    size_t gram_part;
+    size_t res_col, res_scal, dots;
+    size_t dst;           // sine tables and 1D eigenvalues (3D Hartree solve)
+    size_t mix;           // split-bf16 copies of M_L^T and Psi^T (MIXED precision)
+    size_t total;
+    GramPlan gram;        // plan for the iteration dtype
+    GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)
+    ResPlan res;
+};
+
+int elem_size(int dtype);
+GramPlan make_gram_plan(int64_t n, int p);
+ResPlan make_res_plan(int64_t n, int p);
+Layout make_layout(const stf_problem* prob, int precision);
+
+// ---- launchers (stf_kernels.hip); all enqueue on `s` -----------------------
+void launch_rowsq(int dtype, const void* X, int64_t n, int p, double* rho,
+                  const DevState* st, hipStream_t s);
+void launch_hartree(const stf_problem* prob, const double* rho, double* phi,
+                    double* scratch, double* dst_tables, const DevState* st,
+                    hipStream_t s);
+void launch_dst_init(const stf_problem* prob, double* dst_tables, hipStream_t s);
+void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
+                 const double* phi, const DevState* st, hipStream_t s);
+void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
+                 const void* G, int64_t n, int p, double* part, double* S,
+                 double* W, const DevState* st, hipStream_t s);
+void launch_stage1(const DevParams* prm, const double* S, const double* W,
+                   double* Psi, double* ML, int p, DevState* st, hipStream_t s);
+void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
+                     void* G, const void* Gprev, const double* ML, const double* Psi,
+                     const double* nu, int64_t n, int p, double* part_col,
+                     double* part_scal, const DevParams* prm, DevState* st,
+                     int mode, void* mix, hipStream_t s);
+void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
+                   const double* part_scal, const double* S, double* colxg,
+                   double* colgg, double* nu, int p, DevState* st, hipStream_t s);
+void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
+                   const double* nu, double* rho, const DevState* st, hipStream_t s);
+void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out,
+                  const double* M, int64_t n, int p, hipStream_t s);
+void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,
+                     hipStream_t s);
+void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,
+                    hipStream_t s);
+void launch_eval_finish(const stf_problem* prob, const double* X, const double* G,
+                        const double* rho, const double* phi, const double* S,
+                        int64_t n, int p, double* dots, const double* part_scal, int nps,
+                        DevState* st, hipStream_t s);
+void launch_init_state(DevState* st, hipStream_t s);
+
+// residual modes
+enum { RES_ITERATE = 0, RES_KKT_ONLY = 1 };
+
+}  // namespace stf

@@ -1,0 +1,1470 @@
+// gfx950 kernels of the PLAM / PCAL iteration.
+//
+// One iteration k (Algorithms 2 and 3 of the paper) is the kernel sequence
+//   hartree  : phi = L^{-1} rho                       (stencil kinds with alpha != 0)
+//   grad     : G = (L + Diag v + alpha Diag phi) X   or   G = A X (dense)
+//   gram     : split-K partials of S = X^T X (upper blocks) and W = X^T G
+//   gram_red : deterministic sum of the partials
+//   stage1   : Psi = (W + W^T)/2, C = S - I, d (PCAL Phi term), M_L = Psi - beta C + Diag d
+//   residual : gradL = G - X M_L (written over G), optional KKT product G - X Psi,
+//              Barzilai-Borwein inner products, column dots for the PCAL norms
+//   colred   : deterministic sum of the column partials
+//   stage2   : KKT stop test, eta^k, column norms nu
+//   update   : X <- (X - gradL / eta) / nu, rho <- diag(X X^T)
+// All kernels read the device iteration state and return immediately once it
+// says "done", so a captured chunk of iterations can run past convergence
+// without touching the returned iterate.
+//
+// MFMA operand layout used throughout (v_mfma_f64_16x16x4f64 and
+// v_mfma_f32_16x16x4f32, one block): lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  Element v of the 16x16 result sits in column l%16 and row
+// Mma<T>::row(l/16, v): 4*(l/16)+v for float32, (l/16)+4*v for float64.
+#include "stf_internal.h"
+
+#include <math.h>
+
+namespace stf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ d4 run(double a, double b, d4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mma<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ f4 run(float a, float b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+// ---- split-bf16 helpers (MIXED precision) ---------------------------------
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8*(l/16)+e] and
+// B[8*(l/16)+e][l%16] for e = 0..7; the float32 result has the float32 layout
+// above.  A float32 x splits exactly as x = h + m + l with h = bf16(x),
+// m = bf16(x - h), l = bf16(x - h - m) (each difference is exact in float32 and
+// the last one has at most 8 significant bits).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mma_bf(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split2(const float (&x)[8], bf8& h, bf8& l) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 hb = (__bf16)x[e];
+        h[e] = hb;
+        l[e] = (__bf16)(x[e] - (float)hb);
+    }
+}
+
+__device__ __forceinline__ void split3(const float (&x)[8], bf8& h, bf8& m, bf8& l) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 hb = (__bf16)x[e];
+        const float r = x[e] - (float)hb;
+        const __bf16 mb = (__bf16)r;
+        h[e] = hb;
+        m[e] = mb;
+        l[e] = (__bf16)(r - (float)mb);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the 256 threads of a workgroup; the result is valid in thread 0.
+// `sh` must hold at least 4 doubles.
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+// Map a hardware workgroup id to a logical id so that consecutive logical ids
+// run on the same XCD (workgroups are dealt to the 8 XCDs round-robin).
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+    const int q = nwg / 8, r = nwg % 8;
+    const int x = b % 8, pos = b / 8;
+    const int start = (x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return start + pos;
+}
+
+// ---------------------------------------------------------------- state ----
+__global__ void k_init_state(DevState* st) {
+    if (threadIdx.x == 0) {
+        DevState z;
+        memset(&z, 0, sizeof(z));
+        *st = z;
+    }
+}
+
+// -------------------------------------------------------------- density ----
+// rho_r = sum_c X_rc^2 (float64 accumulation); one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowsq(const T* __restrict__ X, int64_t n, int p,
+                                               double* __restrict__ rho,
+                                               const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)gridDim.x * 4) {
+        const T* xr = X + (size_t)r * p;
+        double s = 0.0;
+        for (int c = lane; c < p; c += 64) {
+            double x = (double)xr[c];
+            s += x * x;
+        }
+        s = wave_sum(s);
+        if (lane == 0) rho[r] = s;
+    }
+}
+
+// ------------------------------------------------------------- Hartree ----
+// 1D: phi = T^{-1} rho with T = tridiag(-1,2,-1) of order n, through the
+// closed-form Green's function (T^{-1})_ij = min(i,j)(n+1-max(i,j))/(n+1)
+// (1-based), i.e. phi_i = ((n+1-i) A_i + i B_i) / (n+1) with the prefix sum
+// A_i = sum_{j<=i} j rho_j and the suffix sum B_i = sum_{j>i} (n+1-j) rho_j.
+// One workgroup of 1024 threads; each thread owns a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_hartree1d(const double* __restrict__ rho,
+                                                    double* __restrict__ phi, int64_t n,
+                                                    const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double sa[1024], sb[1024];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int64_t chunk = (n + nt - 1) / nt;
+    const int64_t i0 = (int64_t)t * chunk, i1 = min(n, i0 + chunk);
+    const double np1 = (double)(n + 1);
+    double a = 0.0, b = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double j = (double)(i + 1);
+        a += j * rho[i];
+        b += (np1 - j) * rho[i];
+    }
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    // inclusive scans: sa forward (prefix), sb backward (suffix)
+    for (int off = 1; off < nt; off <<= 1) {
+        double va = (t >= off) ? sa[t - off] : 0.0;
+        double vb = (t + off < nt) ? sb[t + off] : 0.0;
+        __syncthreads();
+        sa[t] += va;
+        sb[t] += vb;
+        __syncthreads();
+    }
+    const double a_excl = (t > 0) ? sa[t - 1] : 0.0;        // sum over chunks before t
+    const double b_excl = (t + 1 < nt) ? sb[t + 1] : 0.0;   // sum over chunks after t
+    double A = a_excl;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double j = (double)(i + 1);
+        A += j * rho[i];
+        phi[i] = (np1 - j) * A;
+    }
+    double B = b_excl;  // sum_{j > i}
+    for (int64_t i = i1 - 1; i >= i0; --i) {
+        const double j = (double)(i + 1);
+        phi[i] = (phi[i] + j * B) / np1;
+        B += (np1 - j) * rho[i];
+    }
+}
+
+// 3D: the orthonormal DST-I matrix S_m[k][j] = sqrt(2/(m+1)) sin(pi (k+1)(j+1)/(m+1))
+// diagonalizes tridiag(-1,2,-1) of order m with eigenvalues 4 sin^2(pi (k+1) / (2(m+1))).
+__global__ void k_dst_init(double* __restrict__ S, double* __restrict__ lam, int m) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const double sc = sqrt(2.0 / (double)(m + 1));
+    if (e < m * m) {
+        const int k = e / m, j = e % m;
+        const long q = ((long)(k + 1) * (long)(j + 1)) % (2L * (m + 1));
+        S[e] = sc * sin(M_PI * (double)q / (double)(m + 1));
+    }
+    if (e < m) {
+        const double s = sin(M_PI * (double)(e + 1) / (2.0 * (m + 1)));
+        lam[e] = 4.0 * s * s;
+    }
+}
+
+// out = (S_m applied along one axis) in; if lam3 is set, out is then divided
+// elementwise by lam_x + lam_y + lam_z.
+__global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
+                                                  double* __restrict__ out,
+                                                  const double* __restrict__ S, int m,
+                                                  int64_t stride, int64_t n,
+                                                  const double* __restrict__ lx,
+                                                  const double* __restrict__ ly,
+                                                  const double* __restrict__ lz, int nx,
+                                                  int ny, const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t k = (e / stride) % m;
+    const int64_t base = e - k * stride;
+    const double* srow = S + k * m;
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += srow[j] * in[base + (int64_t)j * stride];
+    if (lx) {
+        const int64_t x = e % nx, y = (e / nx) % ny, z = e / ((int64_t)nx * ny);
+        s /= (lx[x] + ly[y]) + lz[z];
+    }
+    out[e] = s;
+}
+
+// ------------------------------------------------------------ gradient ----
+// G = (L + Diag v + alpha Diag phi) X for the 1D / 3D Dirichlet stencils.
+// One wave per grid point (row), lanes stride over the p columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
+                                                      T* __restrict__ G, int64_t n, int p,
+                                                      int nx, int ny, int nz, int dim3d,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ phi,
+                                                      double alpha,
+                                                      const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)gridDim.x * 4) {
+        double dg = dim3d ? 6.0 : 2.0;
+        if (v) dg += v[r];
+        if (phi) dg += alpha * phi[r];
+        int64_t nb[6];
+        int nn = 0;
+        if (!dim3d) {
+            if (r > 0) nb[nn++] = r - 1;
+            if (r + 1 < n) nb[nn++] = r + 1;
+        } else {
+            const int64_t sxy = (int64_t)nx * ny;
+            const int64_t x = r % nx, y = (r / nx) % ny, z = r / sxy;
+            if (x > 0) nb[nn++] = r - 1;
+            if (x + 1 < nx) nb[nn++] = r + 1;
+            if (y > 0) nb[nn++] = r - nx;
+            if (y + 1 < ny) nb[nn++] = r + nx;
+            if (z > 0) nb[nn++] = r - sxy;
+            if (z + 1 < nz) nb[nn++] = r + sxy;
+        }
+        const T tdg = (T)dg;
+        const T* xr = X + (size_t)r * p;
+        T* gr = G + (size_t)r * p;
+        for (int c = lane; c < p; c += 64) {
+            T s = tdg * xr[c];
+            for (int q = 0; q < nn; ++q) s -= X[(size_t)nb[q] * p + c];
+            gr[c] = s;
+        }
+    }
+}
+
+// ------------------------------------------------- transposed products ----
+// acc[i][j] += sum_{k0 <= k < k1} Z[k][zc0 + 16 i + (row in tile)] * Y[k][yc0 + 16 j + ...]
+// i.e. one wave accumulates a (16 WM) x (16 WM) block of Z^T Y.  Fragments are
+// read straight from global memory: for a fixed k the 16 lanes of a quarter
+// wave read 16 consecutive elements of one row, so every load is coalesced
+// for row-major Z and Y.
+template <typename T, int WM>
+__device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int zc0, int zlim,
+                                       const T* __restrict__ Y, int64_t ldy, int yc0, int ylim,
+                                       int64_t k0, int64_t k1,
+                                       typename Mma<T>::acc (&acc)[WM][WM]) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    bool zok[WM], yok[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        zok[i] = (zc0 + i * 16 + lr) < zlim;
+        yok[i] = (yc0 + i * 16 + lr) < ylim;
+    }
+    const T* zp = Z + zc0 + lr;
+    const T* yp = Y + yc0 + lr;
+    constexpr int U = 4;
+    int64_t k = k0;
+    for (; k + 4 * U <= k1; k += 4 * U) {
+        T a[U][WM], b[U][WM];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = k + u * 4 + lk;
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                a[u][i] = zok[i] ? zp[row * ldz + i * 16] : (T)0;
+                b[u][i] = yok[i] ? yp[row * ldy + i * 16] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WM; ++j) acc[i][j] = Mma<T>::run(a[u][i], b[u][j], acc[i][j]);
+    }
+    for (; k < k1; k += 4) {
+        const int64_t row = k + lk;
+        const bool rok = row < k1;
+        T a[WM], b[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            a[i] = (rok && zok[i]) ? zp[row * ldz + i * 16] : (T)0;
+            b[i] = (rok && yok[i]) ? yp[row * ldy + i * 16] : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WM; ++j) acc[i][j] = Mma<T>::run(a[i], b[j], acc[i][j]);
+    }
+}
+
+// Decode tile index t of the Gram pass into (bi, bj, is_S).
+__device__ __forceinline__ void gram_tile(int t, int nb, int n_s_tiles, int& bi, int& bj,
+                                          bool& isS) {
+    if (t < n_s_tiles) {
+        isS = true;
+        int row = 0, rem = t;
+        while (rem >= nb - row) {
+            rem -= nb - row;
+            ++row;
+        }
+        bi = row;
+        bj = row + rem;
+    } else {
+        isS = false;
+        const int u = t - n_s_tiles;
+        bi = u / nb;
+        bj = u % nb;
+    }
+}
+
+// Split-K Gram pass: part[chunk][tile][bt][bt] (float64) holds the chunk's
+// contribution to the tile of S (upper blocks, Y = X) or W (Y = G).
+template <typename T, int WM>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* __restrict__ G,
+                                              int64_t n, int p, int nb, int n_s_tiles,
+                                              int n_tiles, int64_t chunk,
+                                              double* __restrict__ part,
+                                              const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int WT = 16 * WM, BT = 2 * WT;
+    const int nwg = gridDim.x;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    // consecutive logical ids share a chunk (same rows: L2 reuse inside one XCD)
+    const int tile = lid % n_tiles, c = lid / n_tiles;
+    int bi, bj;
+    bool isS;
+    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    const T* Y = isS ? X : G;
+    const int wave = threadIdx.x >> 6, wi = wave >> 1, wj = wave & 1;
+    const int zc0 = bi * BT + wi * WT, yc0 = bj * BT + wj * WT;
+    const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
+    typename Mma<T>::acc acc[WM][WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
+    if (zc0 < p && yc0 < p && k0 < k1) tn_mac<T, WM>(X, p, zc0, p, Y, p, yc0, p, k0, k1, acc);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(BT * BT);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = wi * WT + i * 16 + Mma<T>::row(lk, q);
+                const int jj = wj * WT + j * 16 + lr;
+                out[ii * BT + jj] = (double)acc[i][j][q];
+            }
+}
+
+// Split-bf16 Gram pass (MIXED): Z^T Y ~ Zh^T Yh + Zh^T Yl + Zl^T Yh, three
+// bf16 MFMA products with float32 accumulation over 256-row segments that are
+// then added into float64 registers; partials as in k_gram.
+template <int WM>
+__global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
+                                                  const float* __restrict__ G, int64_t n, int p,
+                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int64_t chunk, double* __restrict__ part,
+                                                  const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int WT = 16 * WM, BT = 2 * WT;
+    const int nwg = gridDim.x;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int tile = lid % n_tiles, c = lid / n_tiles;
+    int bi, bj;
+    bool isS;
+    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    const float* Y = isS ? X : G;
+    const int wave = threadIdx.x >> 6, wi = wave >> 1, wj = wave & 1;
+    const int zc0 = bi * BT + wi * WT, yc0 = bj * BT + wj * WT;
+    const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
+    const int lane = threadIdx.x & 63, lr = lane & 15, g = lane >> 4;
+    double dacc[WM][WM][4];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dacc[i][j][q] = 0.0;
+    if (zc0 < p && yc0 < p) {
+        bool zok[WM], yok[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            zok[i] = (zc0 + i * 16 + lr) < p;
+            yok[i] = (yc0 + i * 16 + lr) < p;
+        }
+        for (int64_t ks = k0; ks < k1; ks += 256) {
+            const int64_t ke = min(k1, ks + 256);
+            f4 acc[WM][WM];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WM; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
+            for (int64_t k = ks; k < ke; k += 32) {
+                bf8 ah[WM], al[WM], bh[WM], bl[WM];
+#pragma unroll
+                for (int i = 0; i < WM; ++i) {
+                    float a[8], b[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int64_t row = k + 8 * g + e;
+                        const bool rok = row < ke;
+                        a[e] = (rok && zok[i]) ? X[row * p + zc0 + i * 16 + lr] : 0.f;
+                        b[e] = (rok && yok[i]) ? Y[row * p + yc0 + i * 16 + lr] : 0.f;
+                    }
+                    split2(a, ah[i], al[i]);
+                    split2(b, bh[i], bl[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WM; ++j) {
+                        acc[i][j] = mma_bf(ah[i], bh[j], acc[i][j]);
+                        acc[i][j] = mma_bf(ah[i], bl[j], acc[i][j]);
+                        acc[i][j] = mma_bf(al[i], bh[j], acc[i][j]);
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WM; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dacc[i][j][q] += (double)acc[i][j][q];
+        }
+    }
+    double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(BT * BT);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = wi * WT + i * 16 + Mma<float>::row(g, q);
+                const int jj = wj * WT + j * 16 + lr;
+                out[ii * BT + jj] = dacc[i][j][q];
+            }
+}
+
+// out[s][c][k] (s = 0, 1, 2: the exact bf16 split h, m, l of float(M[k][c])),
+// rows c < prow, columns k < pk, zero outside p x p: the transposed, padded
+// operand layout the split-bf16 row-block product reads with 16-byte loads.
+__global__ __launch_bounds__(256) void k_split3_t(const double* __restrict__ M,
+                                                  __bf16* __restrict__ out, int p, int prow,
+                                                  int pk, const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)prow * pk;
+    if (e >= tot) return;
+    const int c = (int)(e / pk), k = (int)(e % pk);
+    const float x = (c < p && k < p) ? (float)M[(size_t)k * p + c] : 0.f;
+    const __bf16 hb = (__bf16)x;
+    const float r = x - (float)hb;
+    const __bf16 mb = (__bf16)r;
+    out[e] = hb;
+    out[tot + e] = mb;
+    out[2 * tot + e] = (__bf16)(r - (float)mb);
+}
+
+// MIXED form of k_residual: the same epilogue, with X M computed as six
+// split-bf16 MFMA products sum_{a+b<=2} X_a M_b (X split on the fly, M from
+// k_split3_t), i.e. float32-level accuracy (relative error ~2^-23).
+template <bool APPLY>
+__global__ __launch_bounds__(256) void k_residual_bf6(
+    const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
+    const __bf16* __restrict__ MS, const __bf16* __restrict__ PS, int prow, int pk,
+    const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
+    double* __restrict__ part_col, double* __restrict__ part_scal,
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    if (st && st->done) return;
+    __shared__ float Xs[64][36];
+    __shared__ double sh[4];
+    __shared__ double scol[2][2][64];
+    const int nwg = gridDim.x;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int rb = lid / ncb, cb = lid % ncb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, g = lane >> 4;
+    const int c0 = cb * 64 + wc * 32;
+    const size_t tot = (size_t)prow * pk;
+
+    bool kkt_due = false, have_prev = false, iterate = false;
+    double eta_prev = 1.0;
+    if (!APPLY) {
+        const int k = st->iter;
+        iterate = (mode == RES_ITERATE);
+        kkt_due = (mode == RES_KKT_ONLY) || (k % prm->kkt_every == 0) || (k >= prm->max_iter);
+        have_prev = iterate && (k >= 1);
+        eta_prev = st->eta;
+    }
+    double cxg[2] = {0.0, 0.0}, cgg[2] = {0.0, 0.0};
+    double skk = 0.0, sss = 0.0, ssy = 0.0, syy = 0.0;
+
+    for (int64_t rt = rb; rt < nrt; rt += nrb) {
+        const int64_t r0 = rt * 64;
+        f4 a1[2][2], a2[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a1[i][j][q] = 0.f;
+                    a2[i][j][q] = 0.f;
+                }
+        for (int kc = 0; kc < p; kc += 32) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+                const int rr = e >> 5, kk = e & 31;
+                const int64_t r = r0 + rr;
+                const int k = kc + kk;
+                Xs[rr][kk] = (r < n && k < p) ? X[(size_t)r * p + k] : 0.f;
+            }
+            __syncthreads();
+            bf8 xh[2], xm[2], xl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                float xa[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xa[e] = Xs[wr * 32 + i * 16 + lr][8 * g + e];
+                split3(xa, xh[i], xm[i], xl[i]);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = c0 + j * 16 + lr;
+                if (APPLY || iterate) {
+                    const bf8* mp = (const bf8*)(MS + (size_t)c * pk + kc + 8 * g);
+                    const bf8 mh = mp[0];
+                    const bf8 mm = *(const bf8*)((const __bf16*)mp + tot);
+                    const bf8 ml = *(const bf8*)((const __bf16*)mp + 2 * tot);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        f4 acc = a1[i][j];
+                        acc = mma_bf(xh[i], mh, acc);
+                        acc = mma_bf(xh[i], mm, acc);
+                        acc = mma_bf(xm[i], mh, acc);
+                        acc = mma_bf(xh[i], ml, acc);
+                        acc = mma_bf(xl[i], mh, acc);
+                        acc = mma_bf(xm[i], mm, acc);
+                        a1[i][j] = acc;
+                    }
+                }
+                if (kkt_due) {
+                    const bf8* pp = (const bf8*)(PS + (size_t)c * pk + kc + 8 * g);
+                    const bf8 ph = pp[0];
+                    const bf8 pm = *(const bf8*)((const __bf16*)pp + tot);
+                    const bf8 pl = *(const bf8*)((const __bf16*)pp + 2 * tot);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        f4 acc = a2[i][j];
+                        acc = mma_bf(xh[i], ph, acc);
+                        acc = mma_bf(xh[i], pm, acc);
+                        acc = mma_bf(xm[i], ph, acc);
+                        acc = mma_bf(xh[i], pl, acc);
+                        acc = mma_bf(xl[i], ph, acc);
+                        acc = mma_bf(xm[i], pm, acc);
+                        a2[i][j] = acc;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = r0 + wr * 32 + i * 16 + Mma<float>::row(g, q);
+                    const int c = c0 + j * 16 + lr;
+                    if (r >= n || c >= p) continue;
+                    const size_t idx = (size_t)r * p + c;
+                    if (APPLY) {
+                        G[idx] = a1[i][j][q];
+                        continue;
+                    }
+                    const double gv = (double)G[idx];
+                    if (kkt_due) {
+                        const double rk = gv - (double)a2[i][j][q];
+                        skk += rk * rk;
+                    }
+                    if (!iterate) continue;
+                    const float glt = (float)(gv - (double)a1[i][j][q]);
+                    G[idx] = glt;
+                    const double gl = (double)glt;
+                    const double x = (double)X[idx];
+                    cxg[j] += x * gl;
+                    cgg[j] += gl * gl;
+                    if (have_prev) {
+                        const double glp = (double)Gprev[idx];
+                        const double sd = (1.0 - nu[c]) * x - glp / eta_prev;
+                        const double yd = gl - glp;
+                        sss += sd * sd;
+                        ssy += sd * yd;
+                        syy += yd * yd;
+                    }
+                }
+    }
+    if (APPLY) return;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        cxg[j] += __shfl_xor(cxg[j], 16, 64);
+        cxg[j] += __shfl_xor(cxg[j], 32, 64);
+        cgg[j] += __shfl_xor(cgg[j], 16, 64);
+        cgg[j] += __shfl_xor(cgg[j], 32, 64);
+    }
+    if (iterate) {
+        if (g == 0) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                scol[wr][0][wc * 32 + j * 16 + lr] = cxg[j];
+                scol[wr][1][wc * 32 + j * 16 + lr] = cgg[j];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int c = cb * 64 + threadIdx.x;
+            if (c < p) {
+                double* pc = part_col + ((size_t)rb * p + c) * 2;
+                pc[0] = scol[0][0][threadIdx.x] + scol[1][0][threadIdx.x];
+                pc[1] = scol[0][1][threadIdx.x] + scol[1][1][threadIdx.x];
+            }
+        }
+    }
+    const double t0 = block_sum256(skk, sh);
+    const double t1 = block_sum256(sss, sh);
+    const double t2 = block_sum256(ssy, sh);
+    const double t3 = block_sum256(syy, sh);
+    if (threadIdx.x == 0) {
+        double* ps = part_scal + (size_t)lid * 4;
+        ps[0] = t0;
+        ps[1] = t1;
+        ps[2] = t2;
+        ps[3] = t3;
+    }
+}
+
+// Sum the chunk partials in a fixed order; S is written from its upper blocks
+// (entries with row <= col) and mirrored, so it is exactly symmetric.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+                                                     int nchunks, int n_tiles, int bt, int nb,
+                                                     int n_s_tiles, int p,
+                                                     double* __restrict__ S,
+                                                     double* __restrict__ W,
+                                                     const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)bt * bt;
+    if (e >= per * n_tiles) return;
+    const int tile = (int)(e / per);
+    const int ii = (int)((e % per) / bt), jj = (int)(e % bt);
+    int bi, bj;
+    bool isS;
+    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    const int r = bi * bt + ii, c = bj * bt + jj;
+    if (r >= p || c >= p) return;
+    if (isS && r > c) return;
+    if (!isS && !W) return;
+    double s = 0.0;
+    const size_t stride = (size_t)n_tiles * per;
+    for (int q = 0; q < nchunks; ++q) s += part[(size_t)q * stride + e];
+    if (isS) {
+        S[(size_t)r * p + c] = s;
+        S[(size_t)c * p + r] = s;
+    } else {
+        W[(size_t)r * p + c] = s;
+    }
+}
+
+// Dense gradient G = A X = A^T X (A symmetric), written straight to G.
+template <typename T, int WM>
+__global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
+                                                    const T* __restrict__ X, T* __restrict__ G,
+                                                    int64_t n, int p, int nbp,
+                                                    const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int WT = 16 * WM, BT = 2 * WT;
+    const int nwg = gridDim.x;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int bi = lid / nbp, bj = lid % nbp;
+    const int wave = threadIdx.x >> 6, wi = wave >> 1, wj = wave & 1;
+    const int zc0 = bi * BT + wi * WT, yc0 = bj * BT + wj * WT;
+    typename Mma<T>::acc acc[WM][WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
+    if (zc0 < n && yc0 < p) tn_mac<T, WM>(A, n, zc0, (int)n, X, p, yc0, p, 0, n, acc);
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WM; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = zc0 + i * 16 + Mma<T>::row(lk, q);
+                const int c = yc0 + j * 16 + lr;
+                if (r < n && c < p) G[(size_t)r * p + c] = acc[i][j][q];
+            }
+}
+
+// -------------------------------------------------------- p x p stage 1 ----
+// Psi = (W + W^T)/2 (eq. (Lambda1)); C = S - I; for PCAL with the Phi rule
+// d_i = [X^T grad_X L_beta(X, Psi)]_ii = [W - S Psi + beta S C]_ii (eq. (lambda2));
+// M_L = Psi - beta C + Diag(d), so that grad_X L_beta(X, Lam) = G - X M_L.
+__global__ __launch_bounds__(1024) void k_stage1(const DevParams* __restrict__ prm,
+                                                 const double* __restrict__ S,
+                                                 const double* __restrict__ W,
+                                                 double* __restrict__ Psi,
+                                                 double* __restrict__ ML, int p,
+                                                 DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double sd[1024];
+    __shared__ double sred[1024];
+    const int t = threadIdx.x;
+    const double beta = prm->beta;
+    const bool phi_rule = (prm->variant == STF_PCAL) && (prm->mult_rule == STF_MULT_PSI_PHI);
+    for (int i = t; i < p; i += blockDim.x) {
+        double d = 0.0;
+        if (phi_rule) {
+            double sp = 0.0, sc = 0.0;
+            for (int j = 0; j < p; ++j) {
+                const double sij = S[(size_t)i * p + j];
+                const double psi_ji = 0.5 * (W[(size_t)j * p + i] + W[(size_t)i * p + j]);
+                const double c_ji = S[(size_t)j * p + i] - (i == j ? 1.0 : 0.0);
+                sp += sij * psi_ji;
+                sc += sij * c_ji;
+            }
+            d = W[(size_t)i * p + i] - sp + beta * sc;
+        }
+        sd[i] = d;
+    }
+    __syncthreads();
+    double f2 = 0.0;
+    const size_t p2 = (size_t)p * p;
+    for (size_t e = t; e < p2; e += blockDim.x) {
+        const int i = (int)(e / p), j = (int)(e % p);
+        const double psi = 0.5 * (W[e] + W[(size_t)j * p + i]);
+        const double c = S[e] - (i == j ? 1.0 : 0.0);
+        f2 += c * c;
+        Psi[e] = psi;
+        ML[e] = psi - beta * c + (i == j ? sd[i] : 0.0);
+    }
+    sred[t] = f2;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (t < off) sred[t] += sred[t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double feas = sqrt(sred[0]);
+        st->feas = feas;
+        if (!isfinite(feas) || feas > prm->feas_blowup) {
+            st->done = 1;
+            st->status = STF_E_DIVERGED;
+            st->final_iter = st->iter;
+        }
+    }
+}
+
+// ------------------------------------------------------ residual pass ------
+// For a 64 x 64 tile of rows x columns:  gradL = G - X M_L  (written over G),
+// and when the stop test is due also R = G - X Psi with ||R||_F^2 accumulated.
+// The Barzilai-Borwein pair uses the stored gradL^{k-1} (in Gprev) and the
+// identity X^{k-1} = nu^{k-1} X^k + gradL^{k-1} / eta^{k-1} (the PCAL scaling
+// undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
+// APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
+template <typename T, bool APPLY>
+__global__ __launch_bounds__(256) void k_residual(
+    const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
+    const double* __restrict__ ML, const double* __restrict__ Psi,
+    const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
+    double* __restrict__ part_col, double* __restrict__ part_scal,
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    if (st && st->done) return;
+    __shared__ T Xs[64][33];
+    __shared__ double sh[4];
+    __shared__ double scol[2][2][64];
+    const int nwg = gridDim.x;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int rb = lid / ncb, cb = lid % ncb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int c0 = cb * 64 + wc * 32;
+
+    bool kkt_due = false, have_prev = false, iterate = false;
+    double eta_prev = 1.0;
+    if (!APPLY) {
+        const int k = st->iter;
+        iterate = (mode == RES_ITERATE);
+        kkt_due = (mode == RES_KKT_ONLY) ||
+                  (k % prm->kkt_every == 0) || (k >= prm->max_iter);
+        have_prev = iterate && (k >= 1);
+        eta_prev = st->eta;
+    }
+    double cxg[2] = {0.0, 0.0}, cgg[2] = {0.0, 0.0};
+    double skk = 0.0, sss = 0.0, ssy = 0.0, syy = 0.0;
+
+    for (int64_t rt = rb; rt < nrt; rt += nrb) {
+        const int64_t r0 = rt * 64;
+        typename Mma<T>::acc a1[2][2], a2[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a1[i][j][q] = 0;
+                    a2[i][j][q] = 0;
+                }
+        for (int kc = 0; kc < p; kc += 32) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+                const int rr = e >> 5, kk = e & 31;
+                const int64_t r = r0 + rr;
+                const int k = kc + kk;
+                Xs[rr][kk] = (r < n && k < p) ? X[(size_t)r * p + k] : (T)0;
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int kk = 0; kk < 32; kk += 4) {
+                const int k = kc + kk + lk;
+                T a[2], b1[2], b2[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = Xs[wr * 32 + i * 16 + lr][kk + lk];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int c = c0 + j * 16 + lr;
+                    const bool ok = (k < p) && (c < p);
+                    const size_t idx = (size_t)k * p + c;
+                    b1[j] = (ok && (APPLY || iterate)) ? (T)ML[idx] : (T)0;
+                    b2[j] = (ok && kkt_due) ? (T)Psi[idx] : (T)0;
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        if (APPLY || iterate) a1[i][j] = Mma<T>::run(a[i], b1[j], a1[i][j]);
+                        if (kkt_due) a2[i][j] = Mma<T>::run(a[i], b2[j], a2[i][j]);
+                    }
+            }
+        }
+        // epilogue
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = r0 + wr * 32 + i * 16 + Mma<T>::row(lk, q);
+                    const int c = c0 + j * 16 + lr;
+                    if (r >= n || c >= p) continue;
+                    const size_t idx = (size_t)r * p + c;
+                    if (APPLY) {
+                        G[idx] = (T)a1[i][j][q];
+                        continue;
+                    }
+                    const double g = (double)G[idx];
+                    if (kkt_due) {
+                        const double rk = g - (double)a2[i][j][q];
+                        skk += rk * rk;
+                    }
+                    if (!iterate) continue;
+                    const T glt = (T)(g - (double)a1[i][j][q]);
+                    G[idx] = glt;
+                    const double gl = (double)glt;
+                    const double x = (double)X[idx];
+                    cxg[j] += x * gl;
+                    cgg[j] += gl * gl;
+                    if (have_prev) {
+                        const double glp = (double)Gprev[idx];
+                        const double sd = (1.0 - nu[c]) * x - glp / eta_prev;
+                        const double yd = gl - glp;
+                        sss += sd * sd;
+                        ssy += sd * yd;
+                        syy += yd * yd;
+                    }
+                }
+    }
+    if (APPLY) return;
+    // column partials: reduce over the 4 row groups of a wave, then the 2 wave rows
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        cxg[j] += __shfl_xor(cxg[j], 16, 64);
+        cxg[j] += __shfl_xor(cxg[j], 32, 64);
+        cgg[j] += __shfl_xor(cgg[j], 16, 64);
+        cgg[j] += __shfl_xor(cgg[j], 32, 64);
+    }
+    if (iterate) {
+        if (lk == 0) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                scol[wr][0][wc * 32 + j * 16 + lr] = cxg[j];
+                scol[wr][1][wc * 32 + j * 16 + lr] = cgg[j];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int c = cb * 64 + threadIdx.x;
+            if (c < p) {
+                double* pc = part_col + ((size_t)rb * p + c) * 2;
+                pc[0] = scol[0][0][threadIdx.x] + scol[1][0][threadIdx.x];
+                pc[1] = scol[0][1][threadIdx.x] + scol[1][1][threadIdx.x];
+            }
+        }
+    }
+    const double t0 = block_sum256(skk, sh);
+    const double t1 = block_sum256(sss, sh);
+    const double t2 = block_sum256(ssy, sh);
+    const double t3 = block_sum256(syy, sh);
+    if (threadIdx.x == 0) {
+        double* ps = part_scal + (size_t)lid * 4;
+        ps[0] = t0;
+        ps[1] = t1;
+        ps[2] = t2;
+        ps[3] = t3;
+    }
+}
+
+// Column partial sums over the row blocks, in a fixed order.
+__global__ __launch_bounds__(64) void k_colreduce(const double* __restrict__ part_col, int nrb,
+                                                  int p, double* __restrict__ colxg,
+                                                  double* __restrict__ colgg,
+                                                  const DevState* __restrict__ st) {
+    if (st->done) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * p) return;
+    double s = 0.0;
+    for (int b = 0; b < nrb; ++b) s += part_col[(size_t)b * 2 * p + e];
+    const int c = e >> 1;
+    if (e & 1)
+        colgg[c] = s;
+    else
+        colxg[c] = s;
+}
+
+// -------------------------------------------------------- p x p stage 2 ----
+// Stop test (Section 5.1), eta^k (Section 5.1 rules), PCAL column norms.
+__global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
+                                                 const double* __restrict__ part_scal,
+                                                 int nparts, const double* __restrict__ S,
+                                                 const double* __restrict__ colxg,
+                                                 const double* __restrict__ colgg,
+                                                 double* __restrict__ nu, int p,
+                                                 DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double sr[4][1024];
+    __shared__ double s_eta;
+    __shared__ int s_stop;
+    const int t = threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < nparts; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += part_scal[(size_t)b * 4 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sr[q][t] = v[q];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sr[q][t] += sr[q][t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int k = st->iter;
+        const bool kkt_due = (k % prm->kkt_every == 0) || (k >= prm->max_iter);
+        int stop = 0;
+        if (kkt_due) {
+            const double kkt = sqrt(sr[0][0]);
+            if (k == 0) st->kkt0 = kkt;
+            st->kkt = kkt;
+            if (!isfinite(kkt)) {
+                st->status = STF_E_DIVERGED;
+                stop = 1;
+            } else if (st->kkt0 == 0.0 || kkt <= prm->tol * st->kkt0) {
+                st->status = STF_OK;
+                stop = 1;
+            }
+        }
+        if (!stop && k >= prm->max_iter) {
+            st->status = STF_MAX_ITER;
+            stop = 1;
+        }
+        double eta = st->eta;
+        if (!stop) {
+            const double ss = sr[1][0], sy = sr[2][0], yy = sr[3][0];
+            const int rule = prm->eta_rule;
+            if (rule == STF_ETA_CONST) {
+                eta = prm->eta_const;
+            } else if (k == 0) {
+                eta = prm->eta0;
+            } else {
+                double pss = ss, psy = sy, pyy = yy;
+                bool have = true;
+                if (prm->bb_index == STF_BB_LAGGED) {
+                    pss = st->ss_l;
+                    psy = st->sy_l;
+                    pyy = st->yy_l;
+                    have = (k >= 2);
+                }
+                if (!have) {
+                    eta = prm->eta0;
+                } else {
+                    double q = NAN;
+                    if (rule == STF_ETA_DIFF) {
+                        q = (pss > 0.0) ? sqrt(pyy) / sqrt(pss) : NAN;
+                    } else if (rule == STF_ETA_BB1 || (rule == STF_ETA_ABB && (k & 1))) {
+                        q = (pss > 0.0) ? fabs(psy) / pss : NAN;
+                    } else {
+                        q = (psy != 0.0) ? pyy / fabs(psy) : NAN;
+                    }
+                    if (isfinite(q) && q > 0.0) eta = q;
+                }
+            }
+            st->ss_l = ss;
+            st->sy_l = sy;
+            st->yy_l = yy;
+            st->eta = eta;
+        }
+        if (stop) {
+            st->done = 1;
+            st->final_iter = k;
+        }
+        s_eta = eta;
+        s_stop = stop;
+    }
+    __syncthreads();
+    if (s_stop) return;
+    const double eta = s_eta;
+    const bool pcal = prm->variant == STF_PCAL;
+    for (int c = t; c < p; c += blockDim.x) {
+        double nv = 1.0;
+        if (pcal) {
+            // ||X_c - gradL_c / eta||_2^2 expanded with float64 column dots
+            const double y2 = S[(size_t)c * p + c] - 2.0 * colxg[c] / eta + colgg[c] / (eta * eta);
+            nv = sqrt(y2);
+        }
+        nu[c] = nv;
+    }
+    __syncthreads();
+    if (t == 0) st->iter = st->iter + 1;
+}
+
+// ------------------------------------------------------------- update ------
+// X <- (X - gradL / eta) / nu (nu = 1 for PLAM), rho <- diag(X X^T).
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(T* __restrict__ X, const T* __restrict__ GL,
+                                                int64_t n, int p, const double* __restrict__ nu,
+                                                double* __restrict__ rho,
+                                                const DevState* __restrict__ st) {
+    if (st->done) return;
+    const double eta = st->eta;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)gridDim.x * 4) {
+        T* xr = X + (size_t)r * p;
+        const T* gr = GL + (size_t)r * p;
+        double s = 0.0;
+        for (int c = lane; c < p; c += 64) {
+            const double y = ((double)xr[c] - (double)gr[c] / eta) / nu[c];
+            const T yt = (T)y;
+            xr[c] = yt;
+            s += (double)yt * (double)yt;
+        }
+        if (rho) {
+            s = wave_sum(s);
+            if (lane == 0) rho[r] = s;
+        }
+    }
+}
+
+// --------------------------------------------------------- CholeskyQR ------
+// R upper with R^T R = S (right-looking, one workgroup), then Rinv = R^{-1}.
+__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ S,
+                                                   double* __restrict__ R,
+                                                   double* __restrict__ Rinv, int p,
+                                                   DevState* __restrict__ st) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    const size_t p2 = (size_t)p * p;
+    __shared__ int bad;
+    if (t == 0) bad = 0;
+    for (size_t e = t; e < p2; e += nt) {
+        const int i = (int)(e / p), j = (int)(e % p);
+        R[e] = (j >= i) ? S[e] : 0.0;
+        Rinv[e] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < p; ++j) {
+        __shared__ double piv;
+        if (t == 0) {
+            const double d = R[(size_t)j * p + j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = j + 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(d);
+            }
+            R[(size_t)j * p + j] = piv;
+        }
+        __syncthreads();
+        for (int i = j + 1 + t; i < p; i += nt) R[(size_t)j * p + i] /= piv;
+        __syncthreads();
+        // trailing update of the upper triangle: R[i][l] -= R[j][i] R[j][l], j < i <= l
+        const int m = p - j - 1;
+        const size_t cnt = (size_t)m * m;
+        for (size_t e = t; e < cnt; e += nt) {
+            const int i = j + 1 + (int)(e / m), l = j + 1 + (int)(e % m);
+            if (l >= i) R[(size_t)i * p + l] -= R[(size_t)j * p + i] * R[(size_t)j * p + l];
+        }
+        __syncthreads();
+    }
+    // Rinv column by column: R x = e_c by back substitution (upper triangular)
+    for (int c = t; c < p; c += nt) {
+        Rinv[(size_t)c * p + c] = 1.0 / R[(size_t)c * p + c];
+        for (int i = c - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int l = i + 1; l <= c; ++l) s += R[(size_t)i * p + l] * Rinv[(size_t)l * p + c];
+            Rinv[(size_t)i * p + c] = -s / R[(size_t)i * p + i];
+        }
+    }
+    __syncthreads();
+    if (t == 0 && st) st->info = bad;
+}
+
+// ---------------------------------------------------------- conversions ----
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, size_t count) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (size_t)gridDim.x * blockDim.x)
+        out[e] = (B)in[e];
+}
+
+// --------------------------------------------------------- evaluation ------
+// Partial dot products <x, g> over n*p and <rho, phi> over n.
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ X,
+                                              const double* __restrict__ G, size_t np,
+                                              const double* __restrict__ rho,
+                                              const double* __restrict__ phi, int64_t n,
+                                              double* __restrict__ out) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < np;
+         e += (size_t)gridDim.x * blockDim.x)
+        a += X[e] * G[e];
+    if (rho && phi)
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+             e += (int64_t)gridDim.x * blockDim.x)
+            b += rho[e] * phi[e];
+    const double ta = block_sum256(a, sh);
+    const double tb = block_sum256(b, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x * 2] = ta;
+        out[blockIdx.x * 2 + 1] = tb;
+    }
+}
+
+// f = 1/2 <X, G> - alpha/4 rho^T phi  (since G = H0 X + alpha Diag(phi) X),
+// kkt = sqrt(sum of the residual partials), feas = ||S - I||_F.
+__global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ dots, int nd,
+                                                     const double* __restrict__ part_scal,
+                                                     int nps, const double* __restrict__ S,
+                                                     int p, double alpha,
+                                                     DevState* __restrict__ st) {
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0, k2 = 0.0, f2 = 0.0;
+    for (int i = threadIdx.x; i < nd; i += 256) {
+        a += dots[2 * i];
+        b += dots[2 * i + 1];
+    }
+    for (int i = threadIdx.x; i < nps; i += 256) k2 += part_scal[(size_t)i * 4];
+    const size_t p2 = (size_t)p * p;
+    for (size_t e = threadIdx.x; e < p2; e += 256) {
+        const int i = (int)(e / p), j = (int)(e % p);
+        const double c = S[e] - (i == j ? 1.0 : 0.0);
+        f2 += c * c;
+    }
+    a = block_sum256(a, sh);
+    b = block_sum256(b, sh);
+    k2 = block_sum256(k2, sh);
+    f2 = block_sum256(f2, sh);
+    if (threadIdx.x == 0) {
+        st->red[0] = 0.5 * a - 0.25 * alpha * b;
+        st->red[1] = sqrt(k2);
+        st->red[2] = sqrt(f2);
+    }
+}
+
+// =================================================================== host ===
+
+static inline unsigned grid_rows(int64_t n) {
+    int64_t g = (n + 3) / 4;
+    if (g > 65536) g = 65536;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+void launch_init_state(DevState* st, hipStream_t s) { k_init_state<<<1, 1, 0, s>>>(st); }
+
+void launch_rowsq(int dtype, const void* X, int64_t n, int p, double* rho, const DevState* st,
+                  hipStream_t s) {
+    if (dtype == STF_F64)
+        k_rowsq<double><<<grid_rows(n), 256, 0, s>>>((const double*)X, n, p, rho, st);
+    else
+        k_rowsq<float><<<grid_rows(n), 256, 0, s>>>((const float*)X, n, p, rho, st);
+}
+
+void launch_dst_init(const stf_problem* prob, double* dst, hipStream_t s) {
+    const int nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
+    double* Sx = dst;
+    double* Sy = Sx + (size_t)nx * nx;
+    double* Sz = Sy + (size_t)ny * ny;
+    double* lx = Sz + (size_t)nz * nz;
+    double* ly = lx + nx;
+    double* lz = ly + ny;
+    k_dst_init<<<(nx * nx + 255) / 256, 256, 0, s>>>(Sx, lx, nx);
+    k_dst_init<<<(ny * ny + 255) / 256, 256, 0, s>>>(Sy, ly, ny);
+    k_dst_init<<<(nz * nz + 255) / 256, 256, 0, s>>>(Sz, lz, nz);
+}
+
+void launch_hartree(const stf_problem* prob, const double* rho, double* phi, double* scr,
+                    double* dst, const DevState* st, hipStream_t s) {
+    const int64_t n = prob->n;
+    if (prob->kind == STF_KIND_STENCIL1D) {
+        k_hartree1d<<<1, 1024, 0, s>>>(rho, phi, n, st);
+        return;
+    }
+    const int nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
+    const double* Sx = dst;
+    const double* Sy = Sx + (size_t)nx * nx;
+    const double* Sz = Sy + (size_t)ny * ny;
+    const double* lx = Sz + (size_t)nz * nz;
+    const double* ly = lx + nx;
+    const double* lz = ly + ny;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    // forward transform along x, y, z; divide by the eigenvalues; transform back
+    k_dst_axis<<<g, 256, 0, s>>>(rho, scr, Sx, nx, sx, n, nullptr, nullptr, nullptr, nx, ny, st);
+    k_dst_axis<<<g, 256, 0, s>>>(scr, phi, Sy, ny, sy, n, nullptr, nullptr, nullptr, nx, ny, st);
+    k_dst_axis<<<g, 256, 0, s>>>(phi, scr, Sz, nz, sz, n, lx, ly, lz, nx, ny, st);
+    k_dst_axis<<<g, 256, 0, s>>>(scr, phi, Sx, nx, sx, n, nullptr, nullptr, nullptr, nx, ny, st);
+    k_dst_axis<<<g, 256, 0, s>>>(phi, scr, Sy, ny, sy, n, nullptr, nullptr, nullptr, nx, ny, st);
+    k_dst_axis<<<g, 256, 0, s>>>(scr, phi, Sz, nz, sz, n, nullptr, nullptr, nullptr, nx, ny, st);
+}
+
+void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, const double* phi,
+                 const DevState* st, hipStream_t s) {
+    const int64_t n = prob->n;
+    const int p = prob->p;
+    if (prob->kind == STF_KIND_DENSE) {
+        // WG tile 128 x 128 for wide p, 32 x 32 otherwise
+        if (p > 64) {
+            const int nbp = (p + 127) / 128;
+            const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
+            if (dtype == STF_F64)
+                k_dense_grad<double, 4><<<nwg, 256, 0, s>>>((const double*)prob->A,
+                                                            (const double*)X, (double*)G, n, p,
+                                                            nbp, st);
+            else
+                k_dense_grad<float, 4><<<nwg, 256, 0, s>>>((const float*)prob->A,
+                                                           (const float*)X, (float*)G, n, p,
+                                                           nbp, st);
+        } else {
+            const int nbp = (p + 31) / 32;
+            const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
+            if (dtype == STF_F64)
+                k_dense_grad<double, 1><<<nwg, 256, 0, s>>>((const double*)prob->A,
+                                                            (const double*)X, (double*)G, n, p,
+                                                            nbp, st);
+            else
+                k_dense_grad<float, 1><<<nwg, 256, 0, s>>>((const float*)prob->A,
+                                                           (const float*)X, (float*)G, n, p,
+                                                           nbp, st);
+        }
+        return;
+    }
+    const int dim3d = prob->kind == STF_KIND_STENCIL3D;
+    const double* ph = (prob->alpha != 0.0) ? phi : nullptr;
+    if (dtype == STF_F64)
+        k_grad_stencil<double><<<grid_rows(n), 256, 0, s>>>(
+            (const double*)X, (double*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
+            dim3d, prob->v, ph, prob->alpha, st);
+    else
+        k_grad_stencil<float><<<grid_rows(n), 256, 0, s>>>(
+            (const float*)X, (float*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
+            dim3d, prob->v, ph, prob->alpha, st);
+}
+
+template <typename T>
+static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n, int p,
+                          double* part, const DevState* st, hipStream_t s, int n_tiles) {
+    const unsigned nwg = (unsigned)(n_tiles * gp.nchunks);
+    switch (gp.wm) {
+        case 1:
+            k_gram<T, 1><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                              part, st);
+            break;
+        case 2:
+            k_gram<T, 2><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                              part, st);
+            break;
+        default:
+            k_gram<T, 4><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                              part, st);
+            break;
+    }
+}
+
+void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, const void* G,
+                 int64_t n, int p, double* part, double* S, double* W, const DevState* st,
+                 hipStream_t s) {
+    const int n_tiles = W ? gp.n_tiles : gp.n_s_tiles;
+    if (dtype == STF_F32 && precision == STF_PREC_MIXED) {
+        const unsigned nwg = (unsigned)(n_tiles * gp.nchunks);
+        const float* x = (const float*)X;
+        const float* gg = (const float*)G;
+        if (gp.wm == 1)
+            k_gram_bf3<1><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                               part, st);
+        else if (gp.wm == 2)
+            k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                               part, st);
+        else
+            k_gram_bf3<4><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+                                               part, st);
+    } else if (dtype == STF_F64)
+        gram_dispatch<double>(gp, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles);
+    else
+        gram_dispatch<float>(gp, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles);
+    const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
+    k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+        part, gp.nchunks, n_tiles, gp.bt, gp.nb, gp.n_s_tiles, p, S, W, st);
+}
+
+void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
+                   double* ML, int p, DevState* st, hipStream_t s) {
+    k_stage1<<<1, 1024, 0, s>>>(prm, S, W, Psi, ML, p, st);
+}
+
+void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X, void* G,
+                     const void* Gprev, const double* ML, const double* Psi, const double* nu,
+                     int64_t n, int p, double* part_col, double* part_scal,
+                     const DevParams* prm, DevState* st, int mode, void* mix, hipStream_t s) {
+    const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
+    if (dtype == STF_F32 && precision == STF_PREC_MIXED) {
+        const int prow = rp.ncb * 64, pk = (p + 31) / 32 * 32;
+        __bf16* MS = (__bf16*)mix;
+        __bf16* PS = MS + (size_t)3 * prow * pk;
+        const unsigned gs = (unsigned)(((size_t)prow * pk + 255) / 256);
+        if (mode == RES_ITERATE) k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
+        k_split3_t<<<gs, 256, 0, s>>>(Psi, PS, p, prow, pk, st);
+        k_residual_bf6<false><<<nwg, 256, 0, s>>>(
+            (const float*)X, (float*)G, (const float*)Gprev, MS, PS, prow, pk, nu, n, p, rp.nrb,
+            rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
+        return;
+    }
+    if (dtype == STF_F64)
+        k_residual<double, false><<<nwg, 256, 0, s>>>(
+            (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
+            rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
+    else
+        k_residual<float, false><<<nwg, 256, 0, s>>>(
+            (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
+            rp.nrt, part_col, part_scal, prm, st, mode);
+}
+
+void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
+                   const double* part_scal, const double* S, double* colxg, double* colgg,
+                   double* nu, int p, DevState* st, hipStream_t s) {
+    k_colreduce<<<(2 * p + 63) / 64, 64, 0, s>>>(part_col, rp.nrb, p, colxg, colgg, st);
+    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, colxg, colgg, nu, p, st);
+}
+
+void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
+                   double* rho, const DevState* st, hipStream_t s) {
+    if (dtype == STF_F64)
+        k_update<double><<<grid_rows(n), 256, 0, s>>>((double*)X, (const double*)GL, n, p, nu,
+                                                      rho, st);
+    else
+        k_update<float><<<grid_rows(n), 256, 0, s>>>((float*)X, (const float*)GL, n, p, nu, rho,
+                                                     st);
+}
+
+void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const double* M,
+                  int64_t n, int p, hipStream_t s) {
+    const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
+    if (dtype == STF_F64)
+        k_residual<double, true><<<nwg, 256, 0, s>>>((const double*)X, (double*)Out, nullptr, M,
+                                                     nullptr, nullptr, n, p, rp.nrb, rp.ncb,
+                                                     rp.nrt, nullptr, nullptr, nullptr, nullptr,
+                                                     0);
+    else
+        k_residual<float, true><<<nwg, 256, 0, s>>>((const float*)X, (float*)Out, nullptr, M,
+                                                    nullptr, nullptr, n, p, rp.nrb, rp.ncb,
+                                                    rp.nrt, nullptr, nullptr, nullptr, nullptr,
+                                                    0);
+}
+
+void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,
+                     hipStream_t s) {
+    k_chol_inv<<<1, 1024, 0, s>>>(S, R, Rinv, p, st);
+}
+
+void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,
+                    hipStream_t s) {
+    unsigned g = (unsigned)((count + 255) / 256);
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    if (in_dtype == STF_F32 && to_dtype == STF_F64)
+        k_convert<float, double><<<g, 256, 0, s>>>((const float*)in, (double*)out, count);
+    else if (in_dtype == STF_F64 && to_dtype == STF_F32)
+        k_convert<double, float><<<g, 256, 0, s>>>((const double*)in, (float*)out, count);
+    else if (in_dtype == STF_F64)
+        k_convert<double, double><<<g, 256, 0, s>>>((const double*)in, (double*)out, count);
+    else
+        k_convert<float, float><<<g, 256, 0, s>>>((const float*)in, (float*)out, count);
+}
+
+void launch_eval_finish(const stf_problem* prob, const double* X, const double* G,
+                        const double* rho, const double* phi, const double* S, int64_t n, int p,
+                        double* dots, const double* part_scal, int nps, DevState* st,
+                        hipStream_t s) {
+    const int nd = 512;
+    const bool hart = prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
+    k_dots<<<nd, 256, 0, s>>>(X, G, (size_t)n * p, hart ? rho : nullptr, hart ? phi : nullptr,
+                              n, dots);
+    k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, S, p, hart ? prob->alpha : 0.0, st);
+}
+
+}  // namespace stf

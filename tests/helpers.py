@@ -23,3 +23,17 @@ def projector_distance(X, Y):
     """||X X^T - Y Y^T||_F via the p x p identity (no n x n matrices)."""
     a = np.linalg.norm(X.T @ X) ** 2 + np.linalg.norm(Y.T @ Y) ** 2 - 2 * np.linalg.norm(X.T @ Y) ** 2
     return float(np.sqrt(max(a, 0.0)))
+
+
+def green_1d_extended(rho):
+    """phi = T^{-1} rho for T = tridiag(-1,2,-1) by the textbook Green's function
+    min(i,j)(n+1-max(i,j))/(n+1), evaluated with prefix / suffix sums in x87
+    extended precision (64-bit mantissa) and returned as float64."""
+    r = np.asarray(rho, dtype=np.longdouble)
+    n = r.shape[0]
+    j = np.arange(1, n + 1, dtype=np.longdouble)
+    A = np.cumsum(j * r)                          # sum_{j <= i} j rho_j
+    t = (n + 1 - j) * r
+    B = np.cumsum(t[::-1])[::-1] - t              # sum_{j > i} (n+1-j) rho_j
+    phi = ((n + 1 - j) * A + j * B) / (n + 1)
+    return phi.astype(np.float64)

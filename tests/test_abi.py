@@ -1,0 +1,114 @@
+"""The C-ABI library loads and exports every entry point include/stiefel.h declares.
+
+Host-only: no call here touches a GPU (stf_workspace_size, stf_strerror and
+stf_version are pure host functions; argument validation of the compute entry
+points returns before any device work).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1810_03930_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M):
+            name = m.group(1)
+            if name not in ("if", "for", "while", "return", "sizeof"):
+                names.append(name)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert "stf_solve" in names and "pcal_solve" in names and "plam_solve" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) <= set(L.SIGNATURES), \
+        set(declared_functions()) - set(L.SIGNATURES)
+
+
+def test_struct_layouts_match_header():
+    # offsets and sizes that the C compiler gives the structs on x86-64
+    assert ctypes.sizeof(L.StfProblem) == 56
+    assert L.StfProblem.alpha.offset == 32 and L.StfProblem.A.offset == 48
+    assert ctypes.sizeof(L.StfOptions) == 48 + 40
+    assert L.StfOptions.beta.offset == 48
+    assert ctypes.sizeof(L.StfResult) == 8 + 8 * 8 + 8 * 8 + 8
+
+
+def _problem(kind=L.KIND_STENCIL1D, n=1000, p=10, grid=None):
+    cp = L.StfProblem()
+    cp.kind, cp.n, cp.p = kind, n, p
+    g = grid or (n, 1, 1)
+    cp.grid[0], cp.grid[1], cp.grid[2] = g
+    cp.A_dtype = L.F64
+    cp.alpha = 1.0
+    return cp
+
+
+def test_workspace_size_host_only():
+    lib = L.load()
+    ok = _problem()
+    assert lib.stf_workspace_size(ctypes.byref(ok), None) > 1000 * 10 * 8
+    bad = _problem(n=15, p=10)                 # n < 2p (Section 1 requires 2p <= n)
+    assert lib.stf_workspace_size(ctypes.byref(bad), None) == 0
+    bad3 = _problem(kind=L.KIND_STENCIL3D, n=1000, grid=(10, 10, 9))
+    assert lib.stf_workspace_size(ctypes.byref(bad3), None) == 0
+    dense_no_a = _problem(kind=L.KIND_DENSE)
+    assert lib.stf_workspace_size(ctypes.byref(dense_no_a), None) == 0
+    opt = L.StfOptions()
+    opt.precision = L.PREC_FP64
+    s64 = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    opt.precision = L.PREC_FP32
+    s32 = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    assert s64 > 0 and s32 > 0
+    assert lib.stf_workspace_size(ctypes.byref(ok), None) == max(s64, s32)
+
+
+def test_invalid_arguments_rejected_before_device_work():
+    lib = L.load()
+    bad = _problem(n=15, p=10)
+    res = L.StfResult()
+    opt = L.StfOptions()
+    rc = lib.stf_solve(ctypes.byref(bad), None, ctypes.byref(opt), None, 0, None, None,
+                       ctypes.byref(res), None)
+    assert rc == L.E_INVALID
+    ok = _problem()
+    opt.variant = 7
+    rc = lib.stf_solve(ctypes.byref(ok), ctypes.c_void_p(1), ctypes.byref(opt),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_INVALID
+    # the Phi-corrected multiplier is a PCAL rule (eq. (lambda2))
+    opt.variant, opt.mult_rule, opt.eta_rule, opt.kkt_every, opt.check_every = \
+        L.PLAM, L.MULT_PSI_PHI, L.ETA_ABB, 1, 1
+    opt.eta0, opt.tol = 1.0, 1e-8
+    rc = lib.stf_solve(ctypes.byref(ok), ctypes.c_void_p(1), ctypes.byref(opt),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_UNSUPPORTED
+    # too small a workspace is refused before anything is enqueued
+    opt.mult_rule = L.MULT_PSI
+    rc = lib.stf_solve(ctypes.byref(ok), ctypes.c_void_p(1), ctypes.byref(opt),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_WORKSPACE
+
+
+def test_strerror_and_version():
+    for code in [0, 1, -1, -2, -3, -4, -5, -6]:
+        assert len(L.strerror(code)) > 5
+    assert L.strerror(12345) == "unknown status"
+    assert L.load().stf_version().decode().startswith("stiefel")

@@ -52,6 +52,18 @@ def test_hartree_1d_green_function():
     assert np.allclose(op.hartree(rho), green @ rho, rtol=1e-13, atol=0)
 
 
+def test_hartree_1d_large_n_extended_precision():
+    """At n = 20000 (condition number ~ 1.6e8) the refined solve stays at the
+    unit-roundoff level of an extended-precision Green's-function evaluation."""
+    from tests.helpers import green_1d_extended
+    n = 20000
+    prob, _ = W.ks1d(n=n, p=2)
+    rho = W.random_uniform(2, n)
+    phi = OracleProblem(prob).hartree(rho)
+    ex = green_1d_extended(rho)
+    assert np.linalg.norm(phi - ex) <= 1e-15 * np.linalg.norm(ex)
+
+
 def test_hartree_3d_residual_and_sine_mode():
     grid = (9, 7, 6)
     prob, _, _ = W.ks3d(grid=grid, p=2)
