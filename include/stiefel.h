@@ -130,7 +130,11 @@ typedef struct stf_problem {
  * profile     : 1 = bracket every kernel group of every iteration with HIP
  *               events (no graph) and report per-group times in
  *               stf_result.kernel_ms / prof_iters
- * feas_blowup : divergence threshold on ||X^T X - I||_F (e.g. 1e3)          */
+ * feas_blowup : divergence threshold on ||X^T X - I||_F (e.g. 1e3)
+ * history     : device, (max_iter + 1) x 4 float64, or NULL: row k receives
+ *               { ||G - X Psi||_F (NaN when the stop test was not due),
+ *                 ||X^T X - I||_F, eta^k (NaN on the last row), k } as
+ *               iteration k finishes (the per-iteration record of Figs. 1-5) */
 typedef struct stf_options {
     int32_t variant;
     int32_t mult_rule;
@@ -149,6 +153,7 @@ typedef struct stf_options {
     double eta_const;
     double tol;
     double feas_blowup;
+    double* history;
 } stf_options;
 
 /* ---- result (host struct) -------------------------------------------------

@@ -55,6 +55,7 @@ class StfOptions(ctypes.Structure):
         ("eta_const", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("feas_blowup", ctypes.c_double),
+        ("history", ctypes.c_void_p),
     ]
 
 

@@ -36,11 +36,13 @@ GramPlan make_gram_plan(int64_t n, int p) {
     return g;
 }
 
-ResPlan make_res_plan(int64_t n, int p) {
+ResPlan make_res_plan(int64_t n, int p, int tile) {
     ResPlan r;
-    r.ncb = (p + 63) / 64;
-    r.nrt = (n + 63) / 64;
-    int64_t nrb = (2048 + r.ncb - 1) / r.ncb;
+    r.tile = tile;
+    r.ncb = (p + tile - 1) / tile;
+    r.nrt = (n + tile - 1) / tile;
+    const int64_t target = (tile == 128) ? 1024 : 2048;
+    int64_t nrb = (target + r.ncb - 1) / r.ncb;
     nrb = std::min<int64_t>(nrb, r.nrt);
     r.nrb = (int)std::max<int64_t>(nrb, 1);
     return r;
@@ -85,15 +87,22 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.Rm = take(pp);
     L.Rinv = take(pp);
     L.Lam = take(pp);
+    L.Bm = take(pp);
+    L.T1 = take(pp);
+    L.T2 = take(pp);
+    L.fpart = take((size_t)p * 8);
     L.nu = take((size_t)p * 8);
     L.colxg = take((size_t)p * 8);
     L.colgg = take((size_t)p * 8);
     L.gram = make_gram_plan(n, p);
     L.gram64 = L.gram;
     L.gram_part = take((size_t)L.gram.nchunks * L.gram.n_tiles * L.gram.bt * L.gram.bt * 8);
-    L.res = make_res_plan(n, p);
-    L.res_col = take((size_t)L.res.nrb * p * 2 * 8);
-    L.res_scal = take((size_t)L.res.nrb * L.res.ncb * 4 * 8);
+    L.res = make_res_plan(n, p, 128);
+    L.res64 = make_res_plan(n, p, 64);
+    const size_t nrb_max = (size_t)std::max(L.res.nrb, L.res64.nrb);
+    const size_t nwg_max = std::max((size_t)L.res.nrb * L.res.ncb, (size_t)L.res64.nrb * L.res64.ncb);
+    L.res_col = take(nrb_max * p * 2 * 8);
+    L.res_scal = take(nwg_max * 4 * 8);
     L.dots = take(512 * 2 * 8);
     if (prob->kind == STF_KIND_STENCIL3D) {
         const size_t nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
@@ -102,7 +111,7 @@ Layout make_layout(const stf_problem* prob, int precision) {
         L.dst = take(8);
     }
     {
-        const size_t prow = (size_t)L.res.ncb * 64, pk = (size_t)(p + 31) / 32 * 32;
+        const size_t prow = (size_t)L.res64.ncb * 64, pk = (size_t)(p + 31) / 32 * 32;
         L.mix = take(2 * 3 * prow * pk * 2);
     }
     L.total = off;
@@ -201,7 +210,7 @@ static int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, d
     launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, X, G64, n, p, w.at<double>(w.L.gram_part),
                 w.at<double>(w.L.S), w.at<double>(w.L.W), nullptr, s);
     launch_stage1(prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
-                  w.at<double>(w.L.ML), p, st, s);
+                  w.at<double>(w.L.ML), nullptr, w.at<double>(w.L.fpart), p, st, s);
     // the dot products read G before the KKT pass (which does not write in this mode)
     launch_residual(STF_F64, STF_PREC_FP64, w.L.res, X, G64, nullptr, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), nullptr, n, p, w.at<double>(w.L.res_col),
@@ -245,16 +254,22 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
                 w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s);
     mark(3);
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
-                  w.at<double>(w.L.ML), p, c.st, s);
+                  w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
+    if (c.precision == STF_PREC_FP64)
+        launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
+                            w.at<double>(w.L.T1), w.at<double>(w.L.T2), p, c.st, s);
     mark(4);
-    launch_residual(c.dtype, c.precision, w.L.res, c.X, Gc, Gp, w.at<double>(w.L.ML),
+    const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.res64 : w.L.res;
+    launch_residual(c.dtype, c.precision, rp, c.X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
                     w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
                     RES_ITERATE, w.base + w.L.mix, s);
     mark(5);
-    launch_stage2(c.prm, w.L.res, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
-                  w.at<double>(w.L.S), w.at<double>(w.L.colxg), w.at<double>(w.L.colgg),
-                  w.at<double>(w.L.nu), p, c.st, s);
+    launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
+                  w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Bm),
+                  w.at<double>(w.L.T1), w.at<double>(w.L.T2), w.at<double>(w.L.fpart),
+                  w.at<double>(w.L.colxg), w.at<double>(w.L.colgg), w.at<double>(w.L.nu), p, c.st,
+                  s);
     mark(6);
     launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s);
     mark(7);
@@ -309,8 +324,8 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     hp.bb_index = opt->bb_index;
     hp.max_iter = opt->max_iter;
     hp.kkt_every = opt->kkt_every;
-    hp.n_scal_parts = w.L.res.nrb * w.L.res.ncb;
-    hp.n_col_parts = w.L.res.nrb;
+    hp.kkt_identity = (opt->precision == STF_PREC_FP64) ? 1 : 0;
+    hp.history = opt->history;
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);

@@ -35,6 +35,9 @@ struct DevParams {
     int32_t variant, mult_rule, eta_rule, bb_index, max_iter, kkt_every;
     int32_t n_scal_parts;   // number of scalar partial slots written by the residual pass
     int32_t n_col_parts;    // number of row-block column partials
+    int32_t kkt_identity;   // 1: stop test from the float64 p x p identity (no second product)
+    int32_t pad;
+    double* history;        // optional per-iteration record, (max_iter + 1) x 4
 };
 
 // Tiling of the split-K Gram pass.
@@ -48,11 +51,12 @@ struct GramPlan {
     int64_t chunk;   // rows per chunk (multiple of 4)
 };
 
-// Tiling of the row-block x (p x p) product pass.
+// Tiling of the row-block x (p x p) product pass (square tiles of `tile`).
 struct ResPlan {
-    int nrb;         // row-block workgroups (each strides over 64-row tiles)
-    int ncb;         // ceil(p / 64) column blocks
-    int64_t nrt;     // ceil(n / 64) row tiles
+    int tile;        // 128 (float64 / float32 kernels) or 64 (split-bf16 kernel)
+    int nrb;         // row-block workgroups (each strides over row tiles)
+    int ncb;         // ceil(p / tile) column blocks
+    int64_t nrt;     // ceil(n / tile) row tiles
 };
 
 // Byte offsets of every buffer inside the caller's workspace.
@@ -61,7 +65,7 @@ struct Layout {
     size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
     size_t x64, g64;      // float64 n*p buffers for CholeskyQR2 and the final evaluation
     size_t rho, phi, hscr;
-    size_t S, W, Psi, ML, Rm, Rinv, Lam;
+    size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, T2, fpart;
     size_t nu, colxg, colgg;
     size_t gram_part;
     size_t res_col, res_scal, dots;
@@ -70,12 +74,13 @@ struct Layout {
     size_t total;
     GramPlan gram;        // plan for the iteration dtype
     GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)
-    ResPlan res;
+    ResPlan res;          // float64 / float32 residual pass
+    ResPlan res64;        // split-bf16 residual pass (MIXED)
 };
 
 int elem_size(int dtype);
 GramPlan make_gram_plan(int64_t n, int p);
-ResPlan make_res_plan(int64_t n, int p);
+ResPlan make_res_plan(int64_t n, int p, int tile);
 Layout make_layout(const stf_problem* prob, int precision);
 
 // ---- launchers (stf_kernels.hip); all enqueue on `s` -----------------------
@@ -91,15 +96,20 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
                  double* W, const DevState* st, hipStream_t s);
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
-                   double* Psi, double* ML, int p, DevState* st, hipStream_t s);
+                   double* Psi, double* ML, double* Bm, double* feas_part, int p,
+                   DevState* st, hipStream_t s);
+void launch_kkt_products(const double* S, const double* ML, const double* Bm, double* T1,
+                         double* T2, int p, DevState* st, hipStream_t s);
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      void* G, const void* Gprev, const double* ML, const double* Psi,
                      const double* nu, int64_t n, int p, double* part_col,
                      double* part_scal, const DevParams* prm, DevState* st,
                      int mode, void* mix, hipStream_t s);
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
-                   const double* part_scal, const double* S, double* colxg,
-                   double* colgg, double* nu, int p, DevState* st, hipStream_t s);
+                   const double* part_scal, const double* S, const double* W,
+                   const double* Bm, const double* T1, const double* T2,
+                   const double* feas_part, double* colxg, double* colgg, double* nu,
+                   int p, DevState* st, hipStream_t s);
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
                    const double* nu, double* rho, const DevState* st, hipStream_t s);
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out,

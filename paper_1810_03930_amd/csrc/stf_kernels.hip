@@ -742,72 +742,63 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
 }
 
 // -------------------------------------------------------- p x p stage 1 ----
-// Psi = (W + W^T)/2 (eq. (Lambda1)); C = S - I; for PCAL with the Phi rule
-// d_i = [X^T grad_X L_beta(X, Psi)]_ii = [W - S Psi + beta S C]_ii (eq. (lambda2));
-// M_L = Psi - beta C + Diag(d), so that grad_X L_beta(X, Lam) = G - X M_L.
-__global__ __launch_bounds__(1024) void k_stage1(const DevParams* __restrict__ prm,
-                                                 const double* __restrict__ S,
-                                                 const double* __restrict__ W,
-                                                 double* __restrict__ Psi,
-                                                 double* __restrict__ ML, int p,
-                                                 DevState* __restrict__ st) {
+// One workgroup per row i:  Psi = (W + W^T)/2 (eq. (Lambda1)); C = S - I; for
+// PCAL with the Phi rule d_i = [X^T grad_X L_beta(X, Psi)]_ii
+// = [W - S Psi + beta S C]_ii (eq. (lambda2)); M_L = Psi - beta C + Diag(d), so
+// that grad_X L_beta(X, Lam) = G - X M_L; Bm = beta C - Diag(d) (so that
+// G - X Psi = gradL - X Bm); feas_part[i] = sum_j C_ij^2.
+__global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ prm,
+                                                const double* __restrict__ S,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ Psi,
+                                                double* __restrict__ ML,
+                                                double* __restrict__ Bm,
+                                                double* __restrict__ feas_part, int p,
+                                                const DevState* __restrict__ st) {
     if (st->done) return;
-    __shared__ double sd[1024];
-    __shared__ double sred[1024];
-    const int t = threadIdx.x;
+    __shared__ double sh[4];
+    __shared__ double s_d;
+    const int i = blockIdx.x, tid = threadIdx.x;
     const double beta = prm->beta;
     const bool phi_rule = (prm->variant == STF_PCAL) && (prm->mult_rule == STF_MULT_PSI_PHI);
-    for (int i = t; i < p; i += blockDim.x) {
-        double d = 0.0;
-        if (phi_rule) {
-            double sp = 0.0, sc = 0.0;
-            for (int j = 0; j < p; ++j) {
-                const double sij = S[(size_t)i * p + j];
-                const double psi_ji = 0.5 * (W[(size_t)j * p + i] + W[(size_t)i * p + j]);
-                const double c_ji = S[(size_t)j * p + i] - (i == j ? 1.0 : 0.0);
-                sp += sij * psi_ji;
-                sc += sij * c_ji;
-            }
-            d = W[(size_t)i * p + i] - sp + beta * sc;
-        }
-        sd[i] = d;
-    }
-    __syncthreads();
-    double f2 = 0.0;
-    const size_t p2 = (size_t)p * p;
-    for (size_t e = t; e < p2; e += blockDim.x) {
-        const int i = (int)(e / p), j = (int)(e % p);
-        const double psi = 0.5 * (W[e] + W[(size_t)j * p + i]);
-        const double c = S[e] - (i == j ? 1.0 : 0.0);
+    const double* Si = S + (size_t)i * p;
+    const double* Wi = W + (size_t)i * p;
+    double sp = 0.0, sc = 0.0, f2 = 0.0;
+    for (int j = tid; j < p; j += 256) {
+        const double psi = 0.5 * (Wi[j] + W[(size_t)j * p + i]);
+        const double c = Si[j] - (i == j ? 1.0 : 0.0);
+        sp += Si[j] * psi;   // S symmetric: S_ij Psi_ji = S_ij Psi_ij
+        sc += Si[j] * c;
         f2 += c * c;
-        Psi[e] = psi;
-        ML[e] = psi - beta * c + (i == j ? sd[i] : 0.0);
     }
-    sred[t] = f2;
+    sp = block_sum256(sp, sh);
+    sc = block_sum256(sc, sh);
+    f2 = block_sum256(f2, sh);
+    if (tid == 0) {
+        s_d = phi_rule ? (Wi[i] - sp + beta * sc) : 0.0;
+        feas_part[i] = f2;
+    }
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (t < off) sred[t] += sred[t + off];
-        __syncthreads();
-    }
-    if (t == 0) {
-        const double feas = sqrt(sred[0]);
-        st->feas = feas;
-        if (!isfinite(feas) || feas > prm->feas_blowup) {
-            st->done = 1;
-            st->status = STF_E_DIVERGED;
-            st->final_iter = st->iter;
-        }
+    const double d = s_d;
+    for (int j = tid; j < p; j += 256) {
+        const double psi = 0.5 * (Wi[j] + W[(size_t)j * p + i]);
+        const double c = Si[j] - (i == j ? 1.0 : 0.0);
+        const double dd = (i == j) ? d : 0.0;
+        Psi[(size_t)i * p + j] = psi;
+        ML[(size_t)i * p + j] = psi - beta * c + dd;
+        if (Bm) Bm[(size_t)i * p + j] = beta * c - dd;
     }
 }
 
 // ------------------------------------------------------ residual pass ------
-// For a 64 x 64 tile of rows x columns:  gradL = G - X M_L  (written over G),
-// and when the stop test is due also R = G - X Psi with ||R||_F^2 accumulated.
+// For a 128 x 128 tile of rows x columns (four waves of 64 x 64; X and M_L
+// staged through LDS in K-chunks):  gradL = G - X M_L  (written over G), and,
+// when KKT and the stop test is due, R = G - X Psi with ||R||_F^2 accumulated.
 // The Barzilai-Borwein pair uses the stored gradL^{k-1} (in Gprev) and the
 // identity X^{k-1} = nu^{k-1} X^k + gradL^{k-1} / eta^{k-1} (the PCAL scaling
 // undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
-template <typename T, bool APPLY>
+template <typename T, bool APPLY, bool KKT>
 __global__ __launch_bounds__(256) void k_residual(
     const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
@@ -815,81 +806,99 @@ __global__ __launch_bounds__(256) void k_residual(
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
     if (st && st->done) return;
-    __shared__ T Xs[64][33];
+    constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
+    constexpr int XS = KC + 1;
+    constexpr int MST = 128 + 4;
+    __shared__ T Xs[128 * XS];
+    __shared__ T Ms[KC * MST];
+    __shared__ T Ps[KKT ? KC * MST : 1];
     __shared__ double sh[4];
-    __shared__ double scol[2][2][64];
+    __shared__ double scol[2][2][128];
     const int nwg = gridDim.x;
     const int lid = xcd_remap(blockIdx.x, nwg);
     const int rb = lid / ncb, cb = lid % ncb;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
-    const int c0 = cb * 64 + wc * 32;
+    const int cblk = cb * 128;
+    const int c0 = cblk + wc * 64;
 
-    bool kkt_due = false, have_prev = false, iterate = false;
+    bool kkt_due = false, have_prev = false, iterate = APPLY;
     double eta_prev = 1.0;
     if (!APPLY) {
         const int k = st->iter;
         iterate = (mode == RES_ITERATE);
-        kkt_due = (mode == RES_KKT_ONLY) ||
-                  (k % prm->kkt_every == 0) || (k >= prm->max_iter);
+        kkt_due = KKT && ((mode == RES_KKT_ONLY) || (k % prm->kkt_every == 0) ||
+                          (k >= prm->max_iter));
         have_prev = iterate && (k >= 1);
         eta_prev = st->eta;
     }
-    double cxg[2] = {0.0, 0.0}, cgg[2] = {0.0, 0.0};
+    double cxg[4] = {0.0, 0.0, 0.0, 0.0}, cgg[4] = {0.0, 0.0, 0.0, 0.0};
     double skk = 0.0, sss = 0.0, ssy = 0.0, syy = 0.0;
 
     for (int64_t rt = rb; rt < nrt; rt += nrb) {
-        const int64_t r0 = rt * 64;
-        typename Mma<T>::acc a1[2][2], a2[2][2];
+        const int64_t r0 = rt * 128;
+        typename Mma<T>::acc a1[4][4], a2[KKT ? 4 : 1][4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a1[i][j][q] = 0;
-                    a2[i][j][q] = 0;
-                }
-        for (int kc = 0; kc < p; kc += 32) {
+                for (int q = 0; q < 4; ++q) a1[i][j][q] = 0;
+#pragma unroll
+        for (int i = 0; i < (KKT ? 4 : 1); ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a2[i][j][q] = 0;
+        for (int kc = 0; kc < p; kc += KC) {
             __syncthreads();
-            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-                const int rr = e >> 5, kk = e & 31;
+            for (int e = tid; e < 128 * KC; e += 256) {
+                const int rr = e / KC, kk = e % KC;
                 const int64_t r = r0 + rr;
                 const int k = kc + kk;
-                Xs[rr][kk] = (r < n && k < p) ? X[(size_t)r * p + k] : (T)0;
+                Xs[rr * XS + kk] = (r < n && k < p) ? X[(size_t)r * p + k] : (T)0;
+            }
+            for (int e = tid; e < KC * 128; e += 256) {
+                const int kk = e >> 7, cc = e & 127;
+                const int k = kc + kk, c = cblk + cc;
+                const bool ok = (k < p) && (c < p);
+                const size_t idx = (size_t)k * p + c;
+                if (iterate) Ms[kk * MST + cc] = ok ? (T)ML[idx] : (T)0;
+                if (KKT && kkt_due) Ps[kk * MST + cc] = ok ? (T)Psi[idx] : (T)0;
             }
             __syncthreads();
 #pragma unroll 2
-            for (int kk = 0; kk < 32; kk += 4) {
-                const int k = kc + kk + lk;
-                T a[2], b1[2], b2[2];
+            for (int kk = 0; kk < KC; kk += 4) {
+                T a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) a[i] = Xs[wr * 32 + i * 16 + lr][kk + lk];
+                for (int i = 0; i < 4; ++i) a[i] = Xs[(wr * 64 + i * 16 + lr) * XS + kk + lk];
+                if (iterate) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int c = c0 + j * 16 + lr;
-                    const bool ok = (k < p) && (c < p);
-                    const size_t idx = (size_t)k * p + c;
-                    b1[j] = (ok && (APPLY || iterate)) ? (T)ML[idx] : (T)0;
-                    b2[j] = (ok && kkt_due) ? (T)Psi[idx] : (T)0;
+                    for (int j = 0; j < 4; ++j) b[j] = Ms[(kk + lk) * MST + wc * 64 + j * 16 + lr];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) a1[i][j] = Mma<T>::run(a[i], b[j], a1[i][j]);
                 }
+                if (KKT && kkt_due) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 4; ++j) b[j] = Ps[(kk + lk) * MST + wc * 64 + j * 16 + lr];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        if (APPLY || iterate) a1[i][j] = Mma<T>::run(a[i], b1[j], a1[i][j]);
-                        if (kkt_due) a2[i][j] = Mma<T>::run(a[i], b2[j], a2[i][j]);
-                    }
+                    for (int i = 0; i < (KKT ? 4 : 1); ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) a2[i][j] = Mma<T>::run(a[i], b[j], a2[i][j]);
+                }
             }
         }
         // epilogue
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int64_t r = r0 + wr * 32 + i * 16 + Mma<T>::row(lk, q);
+                    const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
                     const int c = c0 + j * 16 + lr;
                     if (r >= n || c >= p) continue;
                     const size_t idx = (size_t)r * p + c;
@@ -897,13 +906,13 @@ __global__ __launch_bounds__(256) void k_residual(
                         G[idx] = (T)a1[i][j][q];
                         continue;
                     }
-                    const double g = (double)G[idx];
-                    if (kkt_due) {
-                        const double rk = g - (double)a2[i][j][q];
+                    const double gv = (double)G[idx];
+                    if (KKT && kkt_due) {
+                        const double rk = gv - (double)a2[KKT ? i : 0][j][q];
                         skk += rk * rk;
                     }
                     if (!iterate) continue;
-                    const T glt = (T)(g - (double)a1[i][j][q]);
+                    const T glt = (T)(gv - (double)a1[i][j][q]);
                     G[idx] = glt;
                     const double gl = (double)glt;
                     const double x = (double)X[idx];
@@ -922,7 +931,7 @@ __global__ __launch_bounds__(256) void k_residual(
     if (APPLY) return;
     // column partials: reduce over the 4 row groups of a wave, then the 2 wave rows
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 4; ++j) {
         cxg[j] += __shfl_xor(cxg[j], 16, 64);
         cxg[j] += __shfl_xor(cxg[j], 32, 64);
         cgg[j] += __shfl_xor(cgg[j], 16, 64);
@@ -931,18 +940,18 @@ __global__ __launch_bounds__(256) void k_residual(
     if (iterate) {
         if (lk == 0) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                scol[wr][0][wc * 32 + j * 16 + lr] = cxg[j];
-                scol[wr][1][wc * 32 + j * 16 + lr] = cgg[j];
+            for (int j = 0; j < 4; ++j) {
+                scol[wr][0][wc * 64 + j * 16 + lr] = cxg[j];
+                scol[wr][1][wc * 64 + j * 16 + lr] = cgg[j];
             }
         }
         __syncthreads();
-        if (threadIdx.x < 64) {
-            const int c = cb * 64 + threadIdx.x;
+        if (tid < 128) {
+            const int c = cblk + tid;
             if (c < p) {
                 double* pc = part_col + ((size_t)rb * p + c) * 2;
-                pc[0] = scol[0][0][threadIdx.x] + scol[1][0][threadIdx.x];
-                pc[1] = scol[0][1][threadIdx.x] + scol[1][1][threadIdx.x];
+                pc[0] = scol[0][0][tid] + scol[1][0][tid];
+                pc[1] = scol[0][1][tid] + scol[1][1][tid];
             }
         }
     }
@@ -950,7 +959,7 @@ __global__ __launch_bounds__(256) void k_residual(
     const double t1 = block_sum256(sss, sh);
     const double t2 = block_sum256(ssy, sh);
     const double t3 = block_sum256(syy, sh);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double* ps = part_scal + (size_t)lid * 4;
         ps[0] = t0;
         ps[1] = t1;
@@ -959,56 +968,116 @@ __global__ __launch_bounds__(256) void k_residual(
     }
 }
 
-// Column partial sums over the row blocks, in a fixed order.
-__global__ __launch_bounds__(64) void k_colreduce(const double* __restrict__ part_col, int nrb,
-                                                  int p, double* __restrict__ colxg,
-                                                  double* __restrict__ colgg,
+// Column partial sums over the row blocks in a fixed order: 32 (column, dot)
+// pairs per workgroup, each summed by 8 threads over interleaved row blocks.
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part_col, int nrb,
+                                                   int p, double* __restrict__ colxg,
+                                                   double* __restrict__ colgg,
+                                                   const DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double sred[8][32];
+    const int e = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int part = threadIdx.x >> 5;
+    double s = 0.0;
+    if (e < 2 * p)
+        for (int b = part; b < nrb; b += 8) s += part_col[(size_t)b * 2 * p + e];
+    sred[part][threadIdx.x & 31] = s;
+    __syncthreads();
+    if (threadIdx.x < 32 && e < 2 * p) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += sred[q][threadIdx.x];
+        const int c = e >> 1;
+        if (e & 1)
+            colgg[c] = t;
+        else
+            colxg[c] = t;
+    }
+}
+
+// T1 = S M_L and T2 = S B for p x p float64 matrices (blockIdx.z selects),
+// the two products of the float64 KKT identity evaluated in stage 2.
+__global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
+                                                  const double* __restrict__ M1,
+                                                  const double* __restrict__ M2,
+                                                  double* __restrict__ T1,
+                                                  double* __restrict__ T2, int p,
                                                   const DevState* __restrict__ st) {
     if (st->done) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 2 * p) return;
-    double s = 0.0;
-    for (int b = 0; b < nrb; ++b) s += part_col[(size_t)b * 2 * p + e];
-    const int c = e >> 1;
-    if (e & 1)
-        colgg[c] = s;
-    else
-        colxg[c] = s;
+    __shared__ double As[16][17], Bs[16][17];
+    const double* B = blockIdx.z ? M2 : M1;
+    double* C = blockIdx.z ? T2 : T1;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < p; k0 += 16) {
+        As[ty][tx] = (row < p && k0 + tx < p) ? S[(size_t)row * p + k0 + tx] : 0.0;
+        Bs[ty][tx] = (k0 + ty < p && col < p) ? B[(size_t)(k0 + ty) * p + col] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += As[ty][k] * Bs[k][tx];
+        __syncthreads();
+    }
+    if (row < p && col < p) C[(size_t)row * p + col] = acc;
 }
 
 // -------------------------------------------------------- p x p stage 2 ----
-// Stop test (Section 5.1), eta^k (Section 5.1 rules), PCAL column norms.
+// Divergence check, stop test (Section 5.1), eta^k (Section 5.1 rules), PCAL
+// column norms.  With prm->kkt_identity (float64 form) the stop test uses
+//   ||G - X Psi||^2 = ||gradL||^2 - 2 <W - S M_L, Bm> + <Bm, S Bm>
+// (G - X Psi = gradL - X Bm and X^T gradL = W - S M_L), whose terms are the
+// float64 column dots of the residual pass and p x p products.
 __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
+                                                 const double* __restrict__ W,
+                                                 const double* __restrict__ Bm,
+                                                 const double* __restrict__ T1,
+                                                 const double* __restrict__ T2,
+                                                 const double* __restrict__ feas_part,
                                                  const double* __restrict__ colxg,
                                                  const double* __restrict__ colgg,
                                                  double* __restrict__ nu, int p,
                                                  DevState* __restrict__ st) {
     if (st->done) return;
-    __shared__ double sr[4][1024];
+    __shared__ double sr[7][1024];
     __shared__ double s_eta;
     __shared__ int s_stop;
     const int t = threadIdx.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool ident = prm->kkt_identity != 0;
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = t; b < nparts; b += blockDim.x)
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] += part_scal[(size_t)b * 4 + q];
+    for (int i = t; i < p; i += blockDim.x) v[4] += feas_part[i];
+    if (ident) {
+        for (int i = t; i < p; i += blockDim.x) v[5] += colgg[i];
+        const size_t p2 = (size_t)p * p;
+        for (size_t e = t; e < p2; e += blockDim.x)
+            v[6] += Bm[e] * (T2[e] - 2.0 * (W[e] - T1[e]));
+    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sr[q][t] = v[q];
+    for (int q = 0; q < 7; ++q) sr[q][t] = v[q];
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
         if (t < off)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sr[q][t] += sr[q][t + off];
+            for (int q = 0; q < 7; ++q) sr[q][t] += sr[q][t + off];
         __syncthreads();
     }
     if (t == 0) {
         const int k = st->iter;
-        const bool kkt_due = (k % prm->kkt_every == 0) || (k >= prm->max_iter);
         int stop = 0;
+        const double feas = sqrt(sr[4][0]);
+        st->feas = feas;
+        if (!isfinite(feas) || feas > prm->feas_blowup) {
+            st->status = STF_E_DIVERGED;
+            stop = 1;
+        }
+        const bool kkt_due = !stop && ((k % prm->kkt_every == 0) || (k >= prm->max_iter));
         if (kkt_due) {
-            const double kkt = sqrt(sr[0][0]);
+            const double k2 = ident ? fmax(0.0, sr[5][0] + sr[6][0]) : sr[0][0];
+            const double kkt = sqrt(k2);
             if (k == 0) st->kkt0 = kkt;
             st->kkt = kkt;
             if (!isfinite(kkt)) {
@@ -1062,6 +1131,13 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
         if (stop) {
             st->done = 1;
             st->final_iter = k;
+        }
+        if (prm->history && k <= prm->max_iter) {
+            double* h = prm->history + (size_t)k * 4;
+            h[0] = kkt_due ? st->kkt : NAN;
+            h[1] = feas;
+            h[2] = stop ? NAN : eta;
+            h[3] = (double)k;
         }
         s_eta = eta;
         s_stop = stop;
@@ -1373,8 +1449,15 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
 }
 
 void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
-                   double* ML, int p, DevState* st, hipStream_t s) {
-    k_stage1<<<1, 1024, 0, s>>>(prm, S, W, Psi, ML, p, st);
+                   double* ML, double* Bm, double* feas_part, int p, DevState* st,
+                   hipStream_t s) {
+    k_stage1<<<p, 256, 0, s>>>(prm, S, W, Psi, ML, Bm, feas_part, p, st);
+}
+
+void launch_kkt_products(const double* S, const double* ML, const double* Bm, double* T1,
+                         double* T2, int p, DevState* st, hipStream_t s) {
+    dim3 grid((p + 15) / 16, (p + 15) / 16, 2);
+    k_pp_gemm2<<<grid, 256, 0, s>>>(S, ML, Bm, T1, T2, p, st);
 }
 
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X, void* G,
@@ -1382,33 +1465,43 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      int64_t n, int p, double* part_col, double* part_scal,
                      const DevParams* prm, DevState* st, int mode, void* mix, hipStream_t s) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
-    if (dtype == STF_F32 && precision == STF_PREC_MIXED) {
+    if (dtype == STF_F32 && precision == STF_PREC_MIXED && mode == RES_ITERATE) {
         const int prow = rp.ncb * 64, pk = (p + 31) / 32 * 32;
         __bf16* MS = (__bf16*)mix;
         __bf16* PS = MS + (size_t)3 * prow * pk;
         const unsigned gs = (unsigned)(((size_t)prow * pk + 255) / 256);
-        if (mode == RES_ITERATE) k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
+        k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
         k_split3_t<<<gs, 256, 0, s>>>(Psi, PS, p, prow, pk, st);
         k_residual_bf6<false><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, MS, PS, prow, pk, nu, n, p, rp.nrb,
             rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
         return;
     }
-    if (dtype == STF_F64)
-        k_residual<double, false><<<nwg, 256, 0, s>>>(
-            (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
-            rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
-    else
-        k_residual<float, false><<<nwg, 256, 0, s>>>(
+    // float64 iterations evaluate the stop test by the p x p identity (no second product)
+    const bool kkt_prod = (mode == RES_KKT_ONLY) || (dtype == STF_F32);
+    if (dtype == STF_F64) {
+        if (kkt_prod)
+            k_residual<double, false, true><<<nwg, 256, 0, s>>>(
+                (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
+                rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
+        else
+            k_residual<double, false, false><<<nwg, 256, 0, s>>>(
+                (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
+                rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
+    } else {
+        k_residual<float, false, true><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
+    }
 }
 
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
-                   const double* part_scal, const double* S, double* colxg, double* colgg,
-                   double* nu, int p, DevState* st, hipStream_t s) {
-    k_colreduce<<<(2 * p + 63) / 64, 64, 0, s>>>(part_col, rp.nrb, p, colxg, colgg, st);
-    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, colxg, colgg, nu, p, st);
+                   const double* part_scal, const double* S, const double* W, const double* Bm,
+                   const double* T1, const double* T2, const double* feas_part, double* colxg,
+                   double* colgg, double* nu, int p, DevState* st, hipStream_t s) {
+    k_colreduce<<<(2 * p + 31) / 32, 256, 0, s>>>(part_col, rp.nrb, p, colxg, colgg, st);
+    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, W, Bm, T1, T2, feas_part,
+                                colxg, colgg, nu, p, st);
 }
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
@@ -1425,12 +1518,12 @@ void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const 
                   int64_t n, int p, hipStream_t s) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     if (dtype == STF_F64)
-        k_residual<double, true><<<nwg, 256, 0, s>>>((const double*)X, (double*)Out, nullptr, M,
+        k_residual<double, true, false><<<nwg, 256, 0, s>>>((const double*)X, (double*)Out, nullptr, M,
                                                      nullptr, nullptr, n, p, rp.nrb, rp.ncb,
                                                      rp.nrt, nullptr, nullptr, nullptr, nullptr,
                                                      0);
     else
-        k_residual<float, true><<<nwg, 256, 0, s>>>((const float*)X, (float*)Out, nullptr, M,
+        k_residual<float, true, false><<<nwg, 256, 0, s>>>((const float*)X, (float*)Out, nullptr, M,
                                                     nullptr, nullptr, n, p, rp.nrb, rp.ncb,
                                                     rp.nrt, nullptr, nullptr, nullptr, nullptr,
                                                     0);

@@ -137,9 +137,12 @@ def alloc_workspace(dp: DeviceProblem, opts: Optional[SolveOptions] = None) -> t
 
 def solve(dp: DeviceProblem, X: torch.Tensor, opts: SolveOptions,
           workspace: Optional[torch.Tensor] = None, want_x64: bool = False,
-          want_lambda: bool = False, stream=None, raise_on_error: bool = True):
+          want_lambda: bool = False, stream=None, raise_on_error: bool = True,
+          history: Optional[torch.Tensor] = None):
     """Run PLAM / PCAL in place on X (device, row-major n x p).
 
+    history: optional device float64 tensor of shape (max_iter + 1, 4) that
+    receives (KKT, feasibility, eta, k) per iteration.
     Returns (result dict, X64 or None, Lambda or None)."""
     lib = L.load()
     if X.dtype != storage_dtype(opts.precision) or not X.is_contiguous() or not X.is_cuda:
@@ -147,6 +150,12 @@ def solve(dp: DeviceProblem, X: torch.Tensor, opts: SolveOptions,
     if tuple(X.shape) != (dp.n, dp.p):
         raise ValueError("X has the wrong shape")
     cp, co = dp.c(), opts.c()
+    if history is not None:
+        if (history.dtype != torch.float64 or not history.is_cuda or not history.is_contiguous()
+                or tuple(history.shape) != (opts.max_iter + 1, 4)):
+            raise ValueError("history must be a contiguous device float64 (max_iter+1, 4) tensor")
+        history.fill_(float("nan"))
+        co.history = history.data_ptr()
     ws = workspace if workspace is not None else alloc_workspace(dp, opts)
     x64 = torch.empty((dp.n, dp.p), dtype=torch.float64, device=X.device) if want_x64 else None
     lam = torch.empty((dp.p, dp.p), dtype=torch.float64, device=X.device) if want_lambda else None

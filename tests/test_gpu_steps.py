@@ -120,9 +120,10 @@ def test_gram_fp32(n, p):
 
 @pytest.mark.parametrize("n,p", [(1000, 37), (5003, 100), (4096, 256), (700, 20)])
 def test_gram_mixed_split_bf16(n, p):
-    """Split-bf16 Gram (three bf16 products, float32 tiles, float64 across tiles):
-    the dropped lo*lo term and the float32 tile sums bound the error by a few
-    1e-7 of |X|_F |Y|_F / sqrt(n)-sized entries; checked at 2e-6 relative."""
+    """Split-bf16 Gram (three bf16 products, float32 tiles, float64 across tiles).
+    Each product carries a relative error of order 2^-16 (x = hi + lo leaves
+    2^-16 |x|; the lo*lo term is dropped), so for these N(0,1) matrices the
+    Frobenius error is ~2^-16 sqrt(p/n) relative: checked at 1e-5."""
     prob, _ = W.ks1d(n=n, p=p)
     X = W.random_matrix(11, (n, p)).astype(np.float32)
     G = W.random_matrix(12, (n, p)).astype(np.float32)
@@ -131,7 +132,7 @@ def test_gram_mixed_split_bf16(n, p):
     Xd, Gd = X.astype(np.float64), G.astype(np.float64)
     errS, errW = rel(to_np(Sg), Xd.T @ Xd), rel(to_np(Wg), Xd.T @ Gd)
     print(f"mixed gram n={n} p={p}: rel err S {errS:.2e} W {errW:.2e}")
-    assert errS <= 2e-6 and errW <= 2e-6
+    assert errS <= 1e-5 and errW <= 1e-5
     assert np.array_equal(to_np(Sg), to_np(Sg).T)
 
 
