@@ -249,6 +249,29 @@ int stf_cholqr2(const stf_problem* prob, double* X, void* ws, size_t ws_bytes,
 int stf_eval(const stf_problem* prob, const double* X, double* out3,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- adjoint (implicit differentiation of the stationary point) ---------
+ * d l(X*) / dV for the diagonal potential V of the objective, given the
+ * Euclidean gradient gradX = dl/dX* of a loss that is invariant under
+ * X* -> X* Q (Q orthogonal).  Differentiating the stationarity condition
+ * grad f(X) = X Lam (eq. (kkt)) on the horizontal space {xi : X^T xi = 0}
+ * gives Hess[zeta] = P(gradX) with Hess[xi] = P(grad^2 f(X)[xi] - xi Lam),
+ * P = I - X X^T (the form of (son)); then dl/dV = -rowdot(zeta, X*).
+ * The system is solved by float64 conjugate gradients on the device.
+ *   Xstar  : device n x p float64, orthonormal stationary point (e.g. X64_out of stf_solve)
+ *   Lam    : device p x p float64, Psi(grad f(X*)^T X*) (Lam_out of stf_solve)
+ *   gradX  : device n x p float64;  gradV: device n float64 (output)
+ *   cg_tol : relative residual target of CG;  cg_maxit: iteration cap
+ *   ws     : device workspace of ws_bytes >= stf_adjoint_workspace_size(prob)
+ *   cg_iters, cg_relres : host outputs (may be NULL)
+ * Returns STF_OK, STF_MAX_ITER (cap reached, gradV still written),
+ * STF_E_DIVERGED (the Hessian is not positive definite on the horizontal
+ * space: X* is not a strict local minimizer), or another STF_E_* code. */
+size_t stf_adjoint_workspace_size(const stf_problem* prob);
+int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* Lam,
+                   const double* gradX, double* gradV, double cg_tol, int32_t cg_maxit,
+                   void* ws, size_t ws_bytes, int32_t* cg_iters, double* cg_relres,
+                   hipStream_t stream);
+
 /* Human-readable name of a return code (static string). */
 const char* stf_strerror(int code);
 

@@ -98,6 +98,10 @@ SIGNATURES = {
                                 _VP, _VP, _SZ, _VP]),
     "stf_cholqr2": (ctypes.c_int, [_P(StfProblem), _VP, _VP, _SZ, _VP]),
     "stf_eval": (ctypes.c_int, [_P(StfProblem), _VP, _P(ctypes.c_double), _VP, _SZ, _VP]),
+    "stf_adjoint_workspace_size": (_SZ, [_P(StfProblem)]),
+    "pcal_adjoint_v": (ctypes.c_int, [_P(StfProblem), _VP, _VP, _VP, _VP, ctypes.c_double,
+                                      ctypes.c_int32, _VP, _SZ, _P(ctypes.c_int32),
+                                      _P(ctypes.c_double), _VP]),
     "stf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stf_version": (ctypes.c_char_p, []),
 }

@@ -364,16 +364,21 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     memset(&hs, 0, sizeof(hs));
     const int64_t limit = (int64_t)opt->max_iter + 1;
     int64_t enq = 0;
+    int64_t last_todo = 0;
     int hip_err = 0;
     while (true) {
         if (gexec) {
             if (hipGraphLaunch(gexec, s) != hipSuccess) { hip_err = 1; break; }
             enq += chunk;
+            last_todo = chunk;
         } else {
-            for (int i = 0; i < chunk; ++i)
+            // no iterations past max_iter: the last uncaptured chunk is clamped
+            const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
+            for (int i = 0; i < todo; ++i)
                 enqueue_iteration(c, (int)((enq + i) & 1), s,
                                   prof ? &pev[(size_t)i * (STF_NPROF + 1)] : nullptr);
-            enq += chunk;
+            enq += todo;
+            last_todo = todo;
             if (last_launch()) { hip_err = 1; break; }
         }
         if (hipMemcpyAsync(&hs, c.st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -383,9 +388,9 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         }
         if (prof) {
             // iterations after "done" are no-ops; count only the ones that ran
-            const int64_t first = enq - chunk;
+            const int64_t first = enq - last_todo;
             const int64_t last = hs.done ? (int64_t)hs.final_iter : enq - 1;
-            for (int i = 0; i < chunk && first + i <= last; ++i) {
+            for (int i = 0; i < last_todo && first + i <= last; ++i) {
                 hipEvent_t* e = &pev[(size_t)i * (STF_NPROF + 1)];
                 for (int g = 0; g < STF_NPROF; ++g) {
                     float ms = 0.f;

@@ -92,6 +92,7 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi,
 void launch_dst_init(const stf_problem* prob, double* dst_tables, hipStream_t s);
 void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
                  const double* phi, const DevState* st, hipStream_t s);
+// S = X^T X (if S) and W = X^T G (if W), float64 p x p, full
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
                  double* W, const DevState* st, hipStream_t s);
@@ -112,8 +113,9 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
                    int p, DevState* st, hipStream_t s);
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
                    const double* nu, double* rho, const DevState* st, hipStream_t s);
+// Out = X M (subtract = 0) or Out -= X M (subtract = 1); M float64 p x p
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out,
-                  const double* M, int64_t n, int p, hipStream_t s);
+                  const double* M, int64_t n, int p, hipStream_t s, int subtract = 0);
 void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,
                      hipStream_t s);
 void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,

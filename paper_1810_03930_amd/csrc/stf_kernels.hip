@@ -117,13 +117,13 @@ __global__ void k_init_state(DevState* st) {
 // -------------------------------------------------------------- density ----
 // rho_r = sum_c X_rc^2 (float64 accumulation); one wave per row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rowsq(const T* __restrict__ X, int64_t n, int p,
+__device__ __forceinline__ void body_rowsq(const T* __restrict__ X, int64_t n, int p,
                                                double* __restrict__ rho,
-                                               const DevState* __restrict__ st) {
+                                               const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     const int lane = threadIdx.x & 63;
-    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
-         r += (int64_t)gridDim.x * 4) {
+    for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)nblk_ * 4) {
         const T* xr = X + (size_t)r * p;
         double s = 0.0;
         for (int c = lane; c < p; c += 64) {
@@ -134,6 +134,13 @@ __global__ __launch_bounds__(256) void k_rowsq(const T* __restrict__ X, int64_t 
         if (lane == 0) rho[r] = s;
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowsq(const T* __restrict__ X, int64_t n, int p,
+                                               double* __restrict__ rho,
+                                               const DevState* __restrict__ st) {
+    body_rowsq<T>(X, n, p, rho, st, blockIdx.x, gridDim.x);
+}
+
 
 // ------------------------------------------------------------- Hartree ----
 // 1D: phi = T^{-1} rho with T = tridiag(-1,2,-1) of order n, through the
@@ -141,9 +148,9 @@ __global__ __launch_bounds__(256) void k_rowsq(const T* __restrict__ X, int64_t 
 // (1-based), i.e. phi_i = ((n+1-i) A_i + i B_i) / (n+1) with the prefix sum
 // A_i = sum_{j<=i} j rho_j and the suffix sum B_i = sum_{j>i} (n+1-j) rho_j.
 // One workgroup of 1024 threads; each thread owns a contiguous chunk.
-__global__ __launch_bounds__(1024) void k_hartree1d(const double* __restrict__ rho,
+__device__ __forceinline__ void body_hartree1d(const double* __restrict__ rho,
                                                     double* __restrict__ phi, int64_t n,
-                                                    const DevState* __restrict__ st) {
+                                                    const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     __shared__ double sa[1024], sb[1024];
     const int t = threadIdx.x, nt = blockDim.x;
@@ -183,6 +190,12 @@ __global__ __launch_bounds__(1024) void k_hartree1d(const double* __restrict__ r
         B += (np1 - j) * rho[i];
     }
 }
+__global__ __launch_bounds__(1024) void k_hartree1d(const double* __restrict__ rho,
+                                                    double* __restrict__ phi, int64_t n,
+                                                    const DevState* __restrict__ st) {
+    body_hartree1d(rho, phi, n, st, blockIdx.x, gridDim.x);
+}
+
 
 // 3D: the orthonormal DST-I matrix S_m[k][j] = sqrt(2/(m+1)) sin(pi (k+1)(j+1)/(m+1))
 // diagonalizes tridiag(-1,2,-1) of order m with eigenvalues 4 sin^2(pi (k+1) / (2(m+1))).
@@ -229,17 +242,17 @@ __global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
 // G = (L + Diag v + alpha Diag phi) X for the 1D / 3D Dirichlet stencils.
 // One wave per grid point (row), lanes stride over the p columns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
+__device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                                                       T* __restrict__ G, int64_t n, int p,
                                                       int nx, int ny, int nz, int dim3d,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
                                                       double alpha,
-                                                      const DevState* __restrict__ st) {
+                                                      const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     const int lane = threadIdx.x & 63;
-    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
-         r += (int64_t)gridDim.x * 4) {
+    for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)nblk_ * 4) {
         double dg = dim3d ? 6.0 : 2.0;
         if (v) dg += v[r];
         if (phi) dg += alpha * phi[r];
@@ -268,6 +281,17 @@ __global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
+                                                      T* __restrict__ G, int64_t n, int p,
+                                                      int nx, int ny, int nz, int dim3d,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ phi,
+                                                      double alpha,
+                                                      const DevState* __restrict__ st) {
+    body_grad_stencil<T>(X, G, n, p, nx, ny, nz, dim3d, v, phi, alpha, st, blockIdx.x, gridDim.x);
+}
+
 
 // ------------------------------------------------- transposed products ----
 // acc[i][j] += sum_{k0 <= k < k1} Z[k][zc0 + 16 i + (row in tile)] * Y[k][yc0 + 16 j + ...]
@@ -348,15 +372,15 @@ __device__ __forceinline__ void gram_tile(int t, int nb, int n_s_tiles, int& bi,
 // Split-K Gram pass: part[chunk][tile][bt][bt] (float64) holds the chunk's
 // contribution to the tile of S (upper blocks, Y = X) or W (Y = G).
 template <typename T, int WM>
-__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* __restrict__ G,
+__device__ __forceinline__ void body_gram(const T* __restrict__ X, const T* __restrict__ G,
                                               int64_t n, int p, int nb, int n_s_tiles,
                                               int n_tiles, int64_t chunk,
                                               double* __restrict__ part,
-                                              const DevState* __restrict__ st) {
+                                              const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     constexpr int WT = 16 * WM, BT = 2 * WT;
-    const int nwg = gridDim.x;
-    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int nwg = nblk_;
+    const int lid = xcd_remap(bid_, nwg);
     // consecutive logical ids share a chunk (same rows: L2 reuse inside one XCD)
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
@@ -387,20 +411,173 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* 
                 out[ii * BT + jj] = (double)acc[i][j][q];
             }
 }
+template <typename T, int WM>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* __restrict__ G,
+                                              int64_t n, int p, int nb, int n_s_tiles,
+                                              int n_tiles, int64_t chunk,
+                                              double* __restrict__ part,
+                                              const DevState* __restrict__ st) {
+    body_gram<T, WM>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+}
+
+
+// LDS-staged split-K Gram pass for 128 x 128 tiles (p > 64): the workgroup
+// walks its chunk of rows KC at a time, staging the tile's 128 columns of Z
+// (= X) and of Y (= X or G) for those rows in LDS, prefetched one step ahead
+// into registers; four waves of 64 x 64.  float32 tiles are added into float64
+// every 256 rows.  Partials as in k_gram.
+template <typename T>
+__device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
+                                                  const T* __restrict__ G, int64_t n, int p,
+                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int64_t chunk, double* __restrict__ part,
+                                                  const DevState* __restrict__ st, int bid_, int nblk_) {
+    if (st && st->done) return;
+    constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
+    constexpr int LS = 128 + 4;
+    constexpr int VX = 16 / (int)sizeof(T);
+    constexpr int NV = KC * 128 / VX / 256;
+    constexpr int FLUSH = 256 / KC;
+    __shared__ T Zs[KC * LS];
+    __shared__ T Ys[KC * LS];
+    const int nwg = nblk_;
+    const int lid = xcd_remap(bid_, nwg);
+    const int tile = lid % n_tiles, c = lid / n_tiles;
+    int bi, bj;
+    bool isS;
+    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    const T* Y = isS ? X : G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int zc = bi * 128, yc = bj * 128;
+    const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
+    const bool vec = (p % VX) == 0;
+    T zr[NV][VX], yr[NV][VX];
+    auto load = [&](int64_t kb) {
+#pragma unroll
+        for (int s2 = 0; s2 < NV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int kk = e / (128 / VX), col = (e % (128 / VX)) * VX;
+            const int64_t row = kb + kk;
+            const int zcol = zc + col, ycol = yc + col;
+            typedef T tv __attribute__((ext_vector_type(VX)));
+            if (vec && row < k1 && zcol + VX <= p) {
+                const tv w = *(const tv*)(X + (size_t)row * p + zcol);
+#pragma unroll
+                for (int v = 0; v < VX; ++v) zr[s2][v] = w[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    zr[s2][v] = (row < k1 && zcol + v < p) ? X[(size_t)row * p + zcol + v] : (T)0;
+            }
+            if (vec && row < k1 && ycol + VX <= p) {
+                const tv w = *(const tv*)(Y + (size_t)row * p + ycol);
+#pragma unroll
+                for (int v = 0; v < VX; ++v) yr[s2][v] = w[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    yr[s2][v] = (row < k1 && ycol + v < p) ? Y[(size_t)row * p + ycol + v] : (T)0;
+            }
+        }
+    };
+    typename Mma<T>::acc acc[4][4];
+    double dacc[sizeof(T) == 4 ? 4 : 1][4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dacc[i][j][q] = 0.0;
+    }
+    const bool active = (zc < p) && (yc < p) && (k0 < k1);
+    if (active) load(k0);
+    int step = 0;
+    for (int64_t kb = k0; active && kb < k1; kb += KC, ++step) {
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < NV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int kk = e / (128 / VX), col = (e % (128 / VX)) * VX;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                Zs[kk * LS + col + v] = zr[s2][v];
+                Ys[kk * LS + col + v] = yr[s2][v];
+            }
+        }
+        __syncthreads();
+        if (kb + KC < k1) load(kb + KC);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Zs[(kk + lk) * LS + wi * 64 + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Ys[(kk + lk) * LS + wj * 64 + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = Mma<T>::run(a[i], b[j], acc[i][j]);
+        }
+        if constexpr (sizeof(T) == 4) {
+            if ((step % FLUSH) == FLUSH - 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            dacc[i][j][q] += (double)acc[i][j][q];
+                            acc[i][j][q] = 0;
+                        }
+            }
+        }
+    }
+    double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = wi * 64 + i * 16 + Mma<T>::row(lk, q);
+                const int jj = wj * 64 + j * 16 + lr;
+                if constexpr (sizeof(T) == 4)
+                    out[ii * 128 + jj] = dacc[i][j][q] + (double)acc[i][j][q];
+                else
+                    out[ii * 128 + jj] = (double)acc[i][j][q];
+            }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_lds(const T* __restrict__ X,
+                                                  const T* __restrict__ G, int64_t n, int p,
+                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int64_t chunk, double* __restrict__ part,
+                                                  const DevState* __restrict__ st) {
+    body_gram_lds<T>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+}
+
 
 // Split-bf16 Gram pass (MIXED): Z^T Y ~ Zh^T Yh + Zh^T Yl + Zl^T Yh, three
 // bf16 MFMA products with float32 accumulation over 256-row segments that are
 // then added into float64 registers; partials as in k_gram.
 template <int WM>
-__global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
+__device__ __forceinline__ void body_gram_bf3(const float* __restrict__ X,
                                                   const float* __restrict__ G, int64_t n, int p,
                                                   int nb, int n_s_tiles, int n_tiles,
                                                   int64_t chunk, double* __restrict__ part,
-                                                  const DevState* __restrict__ st) {
+                                                  const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     constexpr int WT = 16 * WM, BT = 2 * WT;
-    const int nwg = gridDim.x;
-    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int nwg = nblk_;
+    const int lid = xcd_remap(bid_, nwg);
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
     bool isS;
@@ -477,15 +654,24 @@ __global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
                 out[ii * BT + jj] = dacc[i][j][q];
             }
 }
+template <int WM>
+__global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
+                                                  const float* __restrict__ G, int64_t n, int p,
+                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int64_t chunk, double* __restrict__ part,
+                                                  const DevState* __restrict__ st) {
+    body_gram_bf3<WM>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+}
+
 
 // out[s][c][k] (s = 0, 1, 2: the exact bf16 split h, m, l of float(M[k][c])),
 // rows c < prow, columns k < pk, zero outside p x p: the transposed, padded
 // operand layout the split-bf16 row-block product reads with 16-byte loads.
-__global__ __launch_bounds__(256) void k_split3_t(const double* __restrict__ M,
+__device__ __forceinline__ void body_split3_t(const double* __restrict__ M,
                                                   __bf16* __restrict__ out, int p, int prow,
-                                                  int pk, const DevState* __restrict__ st) {
+                                                  int pk, const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)bid_ * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)prow * pk;
     if (e >= tot) return;
     const int c = (int)(e / pk), k = (int)(e % pk);
@@ -497,23 +683,29 @@ __global__ __launch_bounds__(256) void k_split3_t(const double* __restrict__ M,
     out[tot + e] = mb;
     out[2 * tot + e] = (__bf16)(r - (float)mb);
 }
+__global__ __launch_bounds__(256) void k_split3_t(const double* __restrict__ M,
+                                                  __bf16* __restrict__ out, int p, int prow,
+                                                  int pk, const DevState* __restrict__ st) {
+    body_split3_t(M, out, p, prow, pk, st, blockIdx.x, gridDim.x);
+}
+
 
 // MIXED form of k_residual: the same epilogue, with X M computed as six
 // split-bf16 MFMA products sum_{a+b<=2} X_a M_b (X split on the fly, M from
 // k_split3_t), i.e. float32-level accuracy (relative error ~2^-23).
 template <bool APPLY>
-__global__ __launch_bounds__(256) void k_residual_bf6(
+__device__ __forceinline__ void body_residual_bf6(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
     const __bf16* __restrict__ MS, const __bf16* __restrict__ PS, int prow, int pk,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
-    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_) {
     if (st && st->done) return;
     __shared__ float Xs[64][36];
     __shared__ double sh[4];
     __shared__ double scol[2][2][64];
-    const int nwg = gridDim.x;
-    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int nwg = nblk_;
+    const int lid = xcd_remap(bid_, nwg);
     const int rb = lid / ncb, cb = lid % ncb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, g = lane >> 4;
@@ -674,17 +866,27 @@ __global__ __launch_bounds__(256) void k_residual_bf6(
         ps[3] = t3;
     }
 }
+template <bool APPLY>
+__global__ __launch_bounds__(256) void k_residual_bf6(
+    const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
+    const __bf16* __restrict__ MS, const __bf16* __restrict__ PS, int prow, int pk,
+    const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
+    double* __restrict__ part_col, double* __restrict__ part_scal,
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    body_residual_bf6<APPLY>(X, G, Gprev, MS, PS, prow, pk, nu, n, p, nrb, ncb, nrt, part_col, part_scal, prm, st, mode, blockIdx.x, gridDim.x);
+}
+
 
 // Sum the chunk partials in a fixed order; S is written from its upper blocks
 // (entries with row <= col) and mirrored, so it is exactly symmetric.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+__device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
                                                      int n_s_tiles, int p,
                                                      double* __restrict__ S,
                                                      double* __restrict__ W,
-                                                     const DevState* __restrict__ st) {
+                                                     const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)bid_ * blockDim.x + threadIdx.x;
     const int64_t per = (int64_t)bt * bt;
     if (e >= per * n_tiles) return;
     const int tile = (int)(e / per);
@@ -706,6 +908,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
         W[(size_t)r * p + c] = s;
     }
 }
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+                                                     int nchunks, int n_tiles, int bt, int nb,
+                                                     int n_s_tiles, int p,
+                                                     double* __restrict__ S,
+                                                     double* __restrict__ W,
+                                                     const DevState* __restrict__ st) {
+    body_gram_reduce(part, nchunks, n_tiles, bt, nb, n_s_tiles, p, S, W, st, blockIdx.x, gridDim.x);
+}
+
 
 // Dense gradient G = A X = A^T X (A symmetric), written straight to G.
 template <typename T, int WM>
@@ -747,18 +958,18 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
 // = [W - S Psi + beta S C]_ii (eq. (lambda2)); M_L = Psi - beta C + Diag(d), so
 // that grad_X L_beta(X, Lam) = G - X M_L; Bm = beta C - Diag(d) (so that
 // G - X Psi = gradL - X Bm); feas_part[i] = sum_j C_ij^2.
-__global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ prm,
+__device__ __forceinline__ void body_stage1(const DevParams* __restrict__ prm,
                                                 const double* __restrict__ S,
                                                 const double* __restrict__ W,
                                                 double* __restrict__ Psi,
                                                 double* __restrict__ ML,
                                                 double* __restrict__ Bm,
                                                 double* __restrict__ feas_part, int p,
-                                                const DevState* __restrict__ st) {
+                                                const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
     __shared__ double sh[4];
     __shared__ double s_d;
-    const int i = blockIdx.x, tid = threadIdx.x;
+    const int i = bid_, tid = threadIdx.x;
     const double beta = prm->beta;
     const bool phi_rule = (prm->variant == STF_PCAL) && (prm->mult_rule == STF_MULT_PSI_PHI);
     const double* Si = S + (size_t)i * p;
@@ -789,6 +1000,17 @@ __global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ pr
         if (Bm) Bm[(size_t)i * p + j] = beta * c - dd;
     }
 }
+__global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ prm,
+                                                const double* __restrict__ S,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ Psi,
+                                                double* __restrict__ ML,
+                                                double* __restrict__ Bm,
+                                                double* __restrict__ feas_part, int p,
+                                                const DevState* __restrict__ st) {
+    body_stage1(prm, S, W, Psi, ML, Bm, feas_part, p, st, blockIdx.x, gridDim.x);
+}
+
 
 // ------------------------------------------------------ residual pass ------
 // For a 128 x 128 tile of rows x columns (four waves of 64 x 64; X and M_L
@@ -799,12 +1021,12 @@ __global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ pr
 // undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
 template <typename T, bool APPLY, bool KKT>
-__global__ __launch_bounds__(256) void k_residual(
+__device__ __forceinline__ void body_residual(
     const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
-    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_) {
     if (st && st->done) return;
     constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
     constexpr int XS = KC + 1;
@@ -814,8 +1036,8 @@ __global__ __launch_bounds__(256) void k_residual(
     __shared__ T Ps[KKT ? KC * MST : 1];
     __shared__ double sh[4];
     __shared__ double scol[2][2][128];
-    const int nwg = gridDim.x;
-    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int nwg = nblk_;
+    const int lid = xcd_remap(bid_, nwg);
     const int rb = lid / ncb, cb = lid % ncb;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
@@ -835,8 +1057,94 @@ __global__ __launch_bounds__(256) void k_residual(
     }
     double cxg[4] = {0.0, 0.0, 0.0, 0.0}, cgg[4] = {0.0, 0.0, 0.0, 0.0};
     double skk = 0.0, sss = 0.0, ssy = 0.0, syy = 0.0;
+    const double rinv_eta = 1.0 / eta_prev;
+    // per-column constants of this lane's four output columns
+    bool cok[4];
+    double onu[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = c0 + j * 16 + lr;
+        cok[j] = c < p;
+        onu[j] = (!APPLY && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
+    }
+    // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x 128),
+    // 16-byte vectors when the row pitch allows it, prefetched one chunk ahead
+    constexpr int VX = 16 / (int)sizeof(T);          // elements of X per 16-byte load
+    constexpr int NXV = 128 * KC / VX / 256;         // X vectors per thread
+    constexpr int NMV = KC * 128 / 2 / 256;          // float64 pairs of M per thread
+    const bool vec = ((p % VX) == 0);
+    T xr[NXV][VX];
+    T mr[NMV][2], pr[KKT ? NMV : 1][2];
+    auto load_chunk = [&](int64_t r0, int kc) {
+#pragma unroll
+        for (int s2 = 0; s2 < NXV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int rr = e / (KC / VX), kv = e % (KC / VX);
+            const int64_t r = r0 + rr;
+            const int k = kc + kv * VX;
+            if (vec && r < n && k + VX <= p) {
+                // 16-byte aligned: p is a multiple of VX and k of VX
+                typedef T tv __attribute__((ext_vector_type(VX)));
+                const tv w = *(const tv*)(X + (size_t)r * p + k);
+#pragma unroll
+                for (int v = 0; v < VX; ++v) xr[s2][v] = w[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    xr[s2][v] = (r < n && k + v < p) ? X[(size_t)r * p + k + v] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < NMV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int kk = e >> 6, cc = (e & 63) * 2;
+            const int k = kc + kk, c = cblk + cc;
+            if ((p & 1) == 0 && k < p && c + 2 <= p) {
+                typedef double dv2 __attribute__((ext_vector_type(2)));
+                const size_t idx = (size_t)k * p + c;
+                const dv2 z = {0.0, 0.0};
+                const dv2 m = iterate ? *(const dv2*)(ML + idx) : z;
+                mr[s2][0] = (T)m[0];
+                mr[s2][1] = (T)m[1];
+                if (KKT) {
+                    const dv2 q = kkt_due ? *(const dv2*)(Psi + idx) : z;
+                    pr[KKT ? s2 : 0][0] = (T)q[0];
+                    pr[KKT ? s2 : 0][1] = (T)q[1];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const bool ok = (k < p) && (c + v < p);
+                    const size_t idx = (size_t)k * p + c + v;
+                    mr[s2][v] = (iterate && ok) ? (T)ML[idx] : (T)0;
+                    if (KKT) pr[KKT ? s2 : 0][v] = (kkt_due && ok) ? (T)Psi[idx] : (T)0;
+                }
+            }
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int s2 = 0; s2 < NXV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int rr = e / (KC / VX), kv = e % (KC / VX);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) Xs[rr * XS + kv * VX + v] = xr[s2][v];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < NMV; ++s2) {
+            const int e = tid + 256 * s2;
+            const int kk = e >> 6, cc = (e & 63) * 2;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                Ms[kk * MST + cc + v] = mr[s2][v];
+                if (KKT) Ps[kk * MST + cc + v] = pr[KKT ? s2 : 0][v];
+            }
+        }
+    };
 
-    for (int64_t rt = rb; rt < nrt; rt += nrb) {
+    int64_t rt = rb;
+    if (rt < nrt) load_chunk(rt * 128, 0);
+    for (; rt < nrt; rt += nrb) {
         const int64_t r0 = rt * 128;
         typename Mma<T>::acc a1[4][4], a2[KKT ? 4 : 1][4];
 #pragma unroll
@@ -853,22 +1161,14 @@ __global__ __launch_bounds__(256) void k_residual(
                 for (int q = 0; q < 4; ++q) a2[i][j][q] = 0;
         for (int kc = 0; kc < p; kc += KC) {
             __syncthreads();
-            for (int e = tid; e < 128 * KC; e += 256) {
-                const int rr = e / KC, kk = e % KC;
-                const int64_t r = r0 + rr;
-                const int k = kc + kk;
-                Xs[rr * XS + kk] = (r < n && k < p) ? X[(size_t)r * p + k] : (T)0;
-            }
-            for (int e = tid; e < KC * 128; e += 256) {
-                const int kk = e >> 7, cc = e & 127;
-                const int k = kc + kk, c = cblk + cc;
-                const bool ok = (k < p) && (c < p);
-                const size_t idx = (size_t)k * p + c;
-                if (iterate) Ms[kk * MST + cc] = ok ? (T)ML[idx] : (T)0;
-                if (KKT && kkt_due) Ps[kk * MST + cc] = ok ? (T)Psi[idx] : (T)0;
-            }
+            store_chunk();
             __syncthreads();
-#pragma unroll 2
+            // prefetch the next chunk (or the first chunk of the next row tile)
+            if (kc + KC < p)
+                load_chunk(r0, kc + KC);
+            else if (rt + nrb < nrt)
+                load_chunk((rt + nrb) * 128, 0);
+#pragma unroll
             for (int kk = 0; kk < KC; kk += 4) {
                 T a[4], b[4];
 #pragma unroll
@@ -891,42 +1191,66 @@ __global__ __launch_bounds__(256) void k_residual(
                 }
             }
         }
-        // epilogue
+        // epilogue, one 16-row sub-tile at a time with all its loads issued first
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+            if (APPLY) {
+                // mode 0: Out = X M; mode 1: Out -= X M
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
+                        if (r < n && cok[j]) {
+                            const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
+                            if (mode == 1)
+                                G[idx] = (T)((double)G[idx] - (double)a1[i][j][q]);
+                            else
+                                G[idx] = (T)a1[i][j][q];
+                        }
+                    }
+                continue;
+            }
+            T gv[4][4], xv[4][4], gpv[4][4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
-                    const int c = c0 + j * 16 + lr;
-                    if (r >= n || c >= p) continue;
-                    const size_t idx = (size_t)r * p + c;
-                    if (APPLY) {
-                        G[idx] = (T)a1[i][j][q];
-                        continue;
-                    }
-                    const double gv = (double)G[idx];
+                    const bool ok = (r < n) && cok[j];
+                    const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
+                    gv[j][q] = ok ? G[idx] : (T)0;
+                    xv[j][q] = (ok && iterate) ? X[idx] : (T)0;
+                    gpv[j][q] = (ok && have_prev) ? Gprev[idx] : (T)0;
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
+                    if (r >= n || !cok[j]) continue;
+                    const double g = (double)gv[j][q];
                     if (KKT && kkt_due) {
-                        const double rk = gv - (double)a2[KKT ? i : 0][j][q];
+                        const double rk = g - (double)a2[KKT ? i : 0][j][q];
                         skk += rk * rk;
                     }
                     if (!iterate) continue;
-                    const T glt = (T)(gv - (double)a1[i][j][q]);
-                    G[idx] = glt;
+                    const T glt = (T)(g - (double)a1[i][j][q]);
+                    G[(size_t)r * p + c0 + j * 16 + lr] = glt;
                     const double gl = (double)glt;
-                    const double x = (double)X[idx];
+                    const double x = (double)xv[j][q];
                     cxg[j] += x * gl;
                     cgg[j] += gl * gl;
                     if (have_prev) {
-                        const double glp = (double)Gprev[idx];
-                        const double sd = (1.0 - nu[c]) * x - glp / eta_prev;
+                        const double glp = (double)gpv[j][q];
+                        const double sd = onu[j] * x - glp * rinv_eta;
                         const double yd = gl - glp;
                         sss += sd * sd;
                         ssy += sd * yd;
                         syy += yd * yd;
                     }
                 }
+        }
     }
     if (APPLY) return;
     // column partials: reduce over the 4 row groups of a wave, then the 2 wave rows
@@ -967,16 +1291,26 @@ __global__ __launch_bounds__(256) void k_residual(
         ps[3] = t3;
     }
 }
+template <typename T, bool APPLY, bool KKT>
+__global__ __launch_bounds__(256) void k_residual(
+    const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
+    const double* __restrict__ ML, const double* __restrict__ Psi,
+    const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
+    double* __restrict__ part_col, double* __restrict__ part_scal,
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
+    body_residual<T, APPLY, KKT>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col, part_scal, prm, st, mode, blockIdx.x, gridDim.x);
+}
+
 
 // Column partial sums over the row blocks in a fixed order: 32 (column, dot)
 // pairs per workgroup, each summed by 8 threads over interleaved row blocks.
-__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part_col, int nrb,
+__device__ __forceinline__ void body_colreduce(const double* __restrict__ part_col, int nrb,
                                                    int p, double* __restrict__ colxg,
                                                    double* __restrict__ colgg,
-                                                   const DevState* __restrict__ st) {
+                                                   const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
     __shared__ double sred[8][32];
-    const int e = blockIdx.x * 32 + (threadIdx.x & 31);
+    const int e = bid_ * 32 + (threadIdx.x & 31);
     const int part = threadIdx.x >> 5;
     double s = 0.0;
     if (e < 2 * p)
@@ -994,6 +1328,13 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
             colxg[c] = t;
     }
 }
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part_col, int nrb,
+                                                   int p, double* __restrict__ colxg,
+                                                   double* __restrict__ colgg,
+                                                   const DevState* __restrict__ st) {
+    body_colreduce(part_col, nrb, p, colxg, colgg, st, blockIdx.x, gridDim.x);
+}
+
 
 // T1 = S M_L and T2 = S B for p x p float64 matrices (blockIdx.z selects),
 // the two products of the float64 KKT identity evaluated in stage 2.
@@ -1027,7 +1368,7 @@ __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
 //   ||G - X Psi||^2 = ||gradL||^2 - 2 <W - S M_L, Bm> + <Bm, S Bm>
 // (G - X Psi = gradL - X Bm and X^T gradL = W - S M_L), whose terms are the
 // float64 column dots of the residual pass and p x p products.
-__global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
+__device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
                                                  const double* __restrict__ W,
@@ -1038,7 +1379,7 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
                                                  const double* __restrict__ colxg,
                                                  const double* __restrict__ colgg,
                                                  double* __restrict__ nu, int p,
-                                                 DevState* __restrict__ st) {
+                                                 DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
     __shared__ double sr[7][1024];
     __shared__ double s_eta;
@@ -1158,19 +1499,34 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
     __syncthreads();
     if (t == 0) st->iter = st->iter + 1;
 }
+__global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
+                                                 const double* __restrict__ part_scal,
+                                                 int nparts, const double* __restrict__ S,
+                                                 const double* __restrict__ W,
+                                                 const double* __restrict__ Bm,
+                                                 const double* __restrict__ T1,
+                                                 const double* __restrict__ T2,
+                                                 const double* __restrict__ feas_part,
+                                                 const double* __restrict__ colxg,
+                                                 const double* __restrict__ colgg,
+                                                 double* __restrict__ nu, int p,
+                                                 DevState* __restrict__ st) {
+    body_stage2(prm, part_scal, nparts, S, W, Bm, T1, T2, feas_part, colxg, colgg, nu, p, st, blockIdx.x, gridDim.x);
+}
+
 
 // ------------------------------------------------------------- update ------
 // X <- (X - gradL / eta) / nu (nu = 1 for PLAM), rho <- diag(X X^T).
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(T* __restrict__ X, const T* __restrict__ GL,
+__device__ __forceinline__ void body_update(T* __restrict__ X, const T* __restrict__ GL,
                                                 int64_t n, int p, const double* __restrict__ nu,
                                                 double* __restrict__ rho,
-                                                const DevState* __restrict__ st) {
+                                                const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
     const double eta = st->eta;
     const int lane = threadIdx.x & 63;
-    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n;
-         r += (int64_t)gridDim.x * 4) {
+    for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
+         r += (int64_t)nblk_ * 4) {
         T* xr = X + (size_t)r * p;
         const T* gr = GL + (size_t)r * p;
         double s = 0.0;
@@ -1186,6 +1542,14 @@ __global__ __launch_bounds__(256) void k_update(T* __restrict__ X, const T* __re
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(T* __restrict__ X, const T* __restrict__ GL,
+                                                int64_t n, int p, const double* __restrict__ nu,
+                                                double* __restrict__ rho,
+                                                const DevState* __restrict__ st) {
+    body_update<T>(X, GL, n, p, nu, rho, st, blockIdx.x, gridDim.x);
+}
+
 
 // --------------------------------------------------------- CholeskyQR ------
 // R upper with R^T R = S (right-looking, one workgroup), then Rinv = R^{-1}.
@@ -1416,8 +1780,13 @@ static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n,
                                               part, st);
             break;
         default:
-            k_gram<T, 4><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
-                                              part, st);
+            // float64: LDS-staged with prefetch; float32: direct fragment loads measured faster
+            if (sizeof(T) == 8)
+                k_gram_lds<T><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles,
+                                                   gp.chunk, part, st);
+            else
+                k_gram<T, 4><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles,
+                                                  gp.chunk, part, st);
             break;
     }
 }
@@ -1425,27 +1794,30 @@ static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n,
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, const void* G,
                  int64_t n, int p, double* part, double* S, double* W, const DevState* st,
                  hipStream_t s) {
-    const int n_tiles = W ? gp.n_tiles : gp.n_s_tiles;
+    // tiles: the upper blocks of S (when S is wanted) followed by all blocks of W
+    const int nst = S ? gp.n_s_tiles : 0;
+    const int n_tiles = nst + (W ? gp.nb * gp.nb : 0);
+    if (n_tiles == 0) return;
+    GramPlan g2 = gp;
+    g2.n_s_tiles = nst;
     if (dtype == STF_F32 && precision == STF_PREC_MIXED) {
         const unsigned nwg = (unsigned)(n_tiles * gp.nchunks);
         const float* x = (const float*)X;
         const float* gg = (const float*)G;
         if (gp.wm == 1)
-            k_gram_bf3<1><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
-                                               part, st);
+            k_gram_bf3<1><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
         else if (gp.wm == 2)
-            k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
-                                               part, st);
+            k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
         else
-            k_gram_bf3<4><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
-                                               part, st);
-    } else if (dtype == STF_F64)
-        gram_dispatch<double>(gp, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles);
-    else
-        gram_dispatch<float>(gp, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles);
+            k_gram_bf3<4><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
+    } else if (dtype == STF_F64) {
+        gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles);
+    } else {
+        gram_dispatch<float>(g2, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles);
+    }
     const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
-    k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
-        part, gp.nchunks, n_tiles, gp.bt, gp.nb, gp.n_s_tiles, p, S, W, st);
+    k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
+                                                                 gp.nb, nst, p, S, W, st);
 }
 
 void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
@@ -1515,18 +1887,16 @@ void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const d
 }
 
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const double* M,
-                  int64_t n, int p, hipStream_t s) {
+                  int64_t n, int p, hipStream_t s, int subtract) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     if (dtype == STF_F64)
-        k_residual<double, true, false><<<nwg, 256, 0, s>>>((const double*)X, (double*)Out, nullptr, M,
-                                                     nullptr, nullptr, n, p, rp.nrb, rp.ncb,
-                                                     rp.nrt, nullptr, nullptr, nullptr, nullptr,
-                                                     0);
+        k_residual<double, true, false><<<nwg, 256, 0, s>>>(
+            (const double*)X, (double*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
+            rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
     else
-        k_residual<float, true, false><<<nwg, 256, 0, s>>>((const float*)X, (float*)Out, nullptr, M,
-                                                    nullptr, nullptr, n, p, rp.nrb, rp.ncb,
-                                                    rp.nrt, nullptr, nullptr, nullptr, nullptr,
-                                                    0);
+        k_residual<float, true, false><<<nwg, 256, 0, s>>>(
+            (const float*)X, (float*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
+            rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
 }
 
 void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,

@@ -240,3 +240,31 @@ def evaluate(dp: DeviceProblem, X: torch.Tensor, workspace=None, stream=None):
     if rc:
         raise StiefelError(rc, "stf_eval")
     return float(out[0]), float(out[1]), float(out[2])
+
+
+def adjoint_v(dp: DeviceProblem, Xstar: torch.Tensor, Lam: torch.Tensor, gradX: torch.Tensor,
+              cg_tol: float = 1e-10, cg_maxit: int = 2000, workspace=None, stream=None):
+    """dl/dV by implicit differentiation (pcal_adjoint_v); all tensors float64 on the device.
+
+    Returns (gradV, cg_iters, cg_relres)."""
+    lib = L.load()
+    for t in (Xstar, Lam, gradX):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("adjoint inputs must be contiguous float64 device tensors")
+    cp = dp.c()
+    size = lib.stf_adjoint_workspace_size(ctypes.byref(cp))
+    if size == 0:
+        raise StiefelError(L.E_INVALID, "stf_adjoint_workspace_size")
+    ws = workspace if workspace is not None else torch.empty(size, dtype=torch.uint8,
+                                                             device=Xstar.device)
+    gV = torch.empty(dp.n, dtype=torch.float64, device=Xstar.device)
+    its = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    rc = lib.pcal_adjoint_v(ctypes.byref(cp), ctypes.c_void_p(Xstar.data_ptr()),
+                            ctypes.c_void_p(Lam.data_ptr()), ctypes.c_void_p(gradX.data_ptr()),
+                            ctypes.c_void_p(gV.data_ptr()), float(cg_tol), int(cg_maxit),
+                            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                            ctypes.byref(its), ctypes.byref(rr), _stream_handle(stream))
+    if rc < 0:
+        raise StiefelError(rc, "pcal_adjoint_v")
+    return gV, int(its.value), float(rr.value)
