@@ -226,6 +226,7 @@ struct IterCtx {
     Ws w;
     int dtype, precision;
     void* X;
+    double* Xm;  // float64 master iterate of the float32 forms (null in float64)
     DevState* st;
     DevParams* prm;
 };
@@ -248,7 +249,8 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
         launch_hartree(prob, rho, w.at<double>(w.L.phi), w.at<double>(w.L.hscr),
                        w.at<double>(w.L.dst), c.st, s);
     mark(1);
-    launch_grad(prob, c.dtype, c.X, Gc, w.at<double>(w.L.phi), c.st, s);
+    launch_grad(prob, c.dtype, c.X, Gc, w.at<double>(w.L.phi), c.st, s,
+                prob->kind == STF_KIND_DENSE ? nullptr : c.Xm);
     mark(2);
     launch_gram(c.dtype, c.precision, w.L.gram, c.X, Gc, n, p, w.at<double>(w.L.gram_part),
                 w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s);
@@ -271,7 +273,7 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
                   w.at<double>(w.L.colxg), w.at<double>(w.L.colgg), w.at<double>(w.L.nu), p, c.st,
                   s);
     mark(6);
-    launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s);
+    launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s, c.Xm);
     mark(7);
 }
 
@@ -308,6 +310,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     c.dtype = dtype;
     c.precision = opt->precision;
     c.X = X;
+    c.Xm = (dtype == STF_F32) ? w.at<double>(w.L.x64) : nullptr;
     c.st = w.at<DevState>(w.L.state);
     c.prm = w.at<DevParams>(w.L.params);
 
@@ -329,7 +332,11 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);
-    if (has_hartree(prob)) launch_rowsq(dtype, X, n, p, w.at<double>(w.L.rho), c.st, s);
+    // the float32 forms iterate on a float64 master copy; X holds its rounding
+    if (c.Xm) launch_convert(STF_F64, X, STF_F32, c.Xm, (size_t)n * p, s);
+    if (has_hartree(prob))
+        launch_rowsq(c.Xm ? STF_F64 : dtype, c.Xm ? (const void*)c.Xm : X, n, p,
+                     w.at<double>(w.L.rho), c.st, s);
     if ((rc = last_launch())) return rc;
 
     hipEvent_t e0, e1, e2;
@@ -434,9 +441,8 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         Xd = (double*)X;
         tmp = w.at<double>(w.L.g[1]);
     } else {
-        Xd = w.at<double>(w.L.x64);
+        Xd = c.Xm;
         tmp = w.at<double>(w.L.g64);
-        launch_convert(STF_F64, X, STF_F32, Xd, (size_t)n * p, s);
     }
     DevState* st_eval = w.at<DevState>(w.L.state_eval);
     launch_init_state(st_eval, s);

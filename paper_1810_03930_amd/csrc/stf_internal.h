@@ -90,8 +90,10 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi,
                     double* scratch, double* dst_tables, const DevState* st,
                     hipStream_t s);
 void launch_dst_init(const stf_problem* prob, double* dst_tables, hipStream_t s);
+// Xm (float32 G only): the stencil reads this float64 copy of X instead of X
 void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
-                 const double* phi, const DevState* st, hipStream_t s);
+                 const double* phi, const DevState* st, hipStream_t s,
+                 const double* Xm = nullptr);
 // S = X^T X (if S) and W = X^T G (if W), float64 p x p, full
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
@@ -111,8 +113,10 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
                    const double* Bm, const double* T1, const double* T2,
                    const double* feas_part, double* colxg, double* colgg, double* nu,
                    int p, DevState* st, hipStream_t s);
+// Xm (float32 X only): float64 master iterate, read and written; X gets its rounding
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
-                   const double* nu, double* rho, const DevState* st, hipStream_t s);
+                   const double* nu, double* rho, const DevState* st, hipStream_t s,
+                   double* Xm = nullptr);
 // Out = X M (subtract = 0) or Out -= X M (subtract = 1); M float64 p x p
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out,
                   const double* M, int64_t n, int p, hipStream_t s, int subtract = 0);

@@ -239,11 +239,12 @@ __global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
 }
 
 // ------------------------------------------------------------ gradient ----
-// G = (L + Diag v + alpha Diag phi) X for the 1D / 3D Dirichlet stencils.
-// One wave per grid point (row), lanes stride over the p columns.
-template <typename T>
+// G = (L + Diag v + alpha Diag phi) X for the 1D / 3D Dirichlet stencils,
+// computed in the arithmetic of the input X and stored as TO.  One wave per
+// grid point (row), lanes stride over the p columns.
+template <typename T, typename TO>
 __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
-                                                      T* __restrict__ G, int64_t n, int p,
+                                                      TO* __restrict__ G, int64_t n, int p,
                                                       int nx, int ny, int nz, int dim3d,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
@@ -273,23 +274,23 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
         }
         const T tdg = (T)dg;
         const T* xr = X + (size_t)r * p;
-        T* gr = G + (size_t)r * p;
+        TO* gr = G + (size_t)r * p;
         for (int c = lane; c < p; c += 64) {
             T s = tdg * xr[c];
             for (int q = 0; q < nn; ++q) s -= X[(size_t)nb[q] * p + c];
-            gr[c] = s;
+            gr[c] = (TO)s;
         }
     }
 }
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
-                                                      T* __restrict__ G, int64_t n, int p,
+                                                      TO* __restrict__ G, int64_t n, int p,
                                                       int nx, int ny, int nz, int dim3d,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
                                                       double alpha,
                                                       const DevState* __restrict__ st) {
-    body_grad_stencil<T>(X, G, n, p, nx, ny, nz, dim3d, v, phi, alpha, st, blockIdx.x, gridDim.x);
+    body_grad_stencil<T, TO>(X, G, n, p, nx, ny, nz, dim3d, v, phi, alpha, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -869,9 +870,8 @@ __device__ __forceinline__ void body_residual_bf6(
 template <bool APPLY>
 __global__ __launch_bounds__(256) void k_residual_bf6(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
-    const __bf16* __restrict__ MS, const __bf16* __restrict__ PS, int prow, int pk,
-    const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
-    double* __restrict__ part_col, double* __restrict__ part_scal,
+    const __bf16* __restrict__ MS, const __bf16* __restrict__ PS, int prow, int pk, const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb,
+    int64_t nrt, double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
     body_residual_bf6<APPLY>(X, G, Gprev, MS, PS, prow, pk, nu, n, p, nrb, ncb, nrt, part_col, part_scal, prm, st, mode, blockIdx.x, gridDim.x);
 }
@@ -1518,7 +1518,8 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
 // ------------------------------------------------------------- update ------
 // X <- (X - gradL / eta) / nu (nu = 1 for PLAM), rho <- diag(X X^T).
 template <typename T>
-__device__ __forceinline__ void body_update(T* __restrict__ X, const T* __restrict__ GL,
+__device__ __forceinline__ void body_update(T* __restrict__ X, double* __restrict__ Xm,
+                                                const T* __restrict__ GL,
                                                 int64_t n, int p, const double* __restrict__ nu,
                                                 double* __restrict__ rho,
                                                 const DevState* __restrict__ st, int bid_, int nblk_) {
@@ -1528,13 +1529,16 @@ __device__ __forceinline__ void body_update(T* __restrict__ X, const T* __restri
     for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
          r += (int64_t)nblk_ * 4) {
         T* xr = X + (size_t)r * p;
+        double* xm = Xm ? Xm + (size_t)r * p : nullptr;
         const T* gr = GL + (size_t)r * p;
         double s = 0.0;
         for (int c = lane; c < p; c += 64) {
-            const double y = ((double)xr[c] - (double)gr[c] / eta) / nu[c];
+            const double x = xm ? xm[c] : (double)xr[c];
+            const double y = (x - (double)gr[c] / eta) / nu[c];
             const T yt = (T)y;
             xr[c] = yt;
-            s += (double)yt * (double)yt;
+            if (xm) xm[c] = y;
+            s += xm ? y * y : (double)yt * (double)yt;
         }
         if (rho) {
             s = wave_sum(s);
@@ -1543,11 +1547,12 @@ __device__ __forceinline__ void body_update(T* __restrict__ X, const T* __restri
     }
 }
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(T* __restrict__ X, const T* __restrict__ GL,
+__global__ __launch_bounds__(256) void k_update(T* __restrict__ X, double* __restrict__ Xm,
+                                                const T* __restrict__ GL,
                                                 int64_t n, int p, const double* __restrict__ nu,
                                                 double* __restrict__ rho,
                                                 const DevState* __restrict__ st) {
-    body_update<T>(X, GL, n, p, nu, rho, st, blockIdx.x, gridDim.x);
+    body_update<T>(X, Xm, GL, n, p, nu, rho, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -1724,7 +1729,7 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi, dou
 }
 
 void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, const double* phi,
-                 const DevState* st, hipStream_t s) {
+                 const DevState* st, hipStream_t s, const double* Xm) {
     const int64_t n = prob->n;
     const int p = prob->p;
     if (prob->kind == STF_KIND_DENSE) {
@@ -1757,11 +1762,16 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
     const int dim3d = prob->kind == STF_KIND_STENCIL3D;
     const double* ph = (prob->alpha != 0.0) ? phi : nullptr;
     if (dtype == STF_F64)
-        k_grad_stencil<double><<<grid_rows(n), 256, 0, s>>>(
+        k_grad_stencil<double, double><<<grid_rows(n), 256, 0, s>>>(
             (const double*)X, (double*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
             dim3d, prob->v, ph, prob->alpha, st);
+    else if (Xm)
+        // float32 G of the float64 master iterate, stencil evaluated in float64
+        k_grad_stencil<double, float><<<grid_rows(n), 256, 0, s>>>(
+            Xm, (float*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2], dim3d, prob->v,
+            ph, prob->alpha, st);
     else
-        k_grad_stencil<float><<<grid_rows(n), 256, 0, s>>>(
+        k_grad_stencil<float, float><<<grid_rows(n), 256, 0, s>>>(
             (const float*)X, (float*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
             dim3d, prob->v, ph, prob->alpha, st);
 }
@@ -1877,13 +1887,13 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
 }
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
-                   double* rho, const DevState* st, hipStream_t s) {
+                   double* rho, const DevState* st, hipStream_t s, double* Xm) {
     if (dtype == STF_F64)
-        k_update<double><<<grid_rows(n), 256, 0, s>>>((double*)X, (const double*)GL, n, p, nu,
-                                                      rho, st);
+        k_update<double><<<grid_rows(n), 256, 0, s>>>((double*)X, nullptr, (const double*)GL, n,
+                                                      p, nu, rho, st);
     else
-        k_update<float><<<grid_rows(n), 256, 0, s>>>((float*)X, (const float*)GL, n, p, nu, rho,
-                                                     st);
+        k_update<float><<<grid_rows(n), 256, 0, s>>>((float*)X, Xm, (const float*)GL, n, p, nu,
+                                                     rho, st);
 }
 
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const double* M,
