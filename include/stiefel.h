@@ -131,6 +131,14 @@ typedef struct stf_problem {
  *               events (no graph) and report per-group times in
  *               stf_result.kernel_ms / prof_iters
  * feas_blowup : divergence threshold on ||X^T X - I||_F (e.g. 1e3)
+ * switch_tol  : STF_PREC_FP32 / STF_PREC_MIXED only; 0 = never.  Once the
+ *               stop test of iteration k finds ||G - X Psi||_F <= switch_tol
+ *               times the same at X^0 (and above tol), iteration k is redone
+ *               in float64 from the float64 master iterate, with the eta,
+ *               column norms and previous gradL carried over, and the solve
+ *               continues in float64 (stf_result.switch_iter = k).  The float32
+ *               forms stall where rounding noise in G and X M dominates the
+ *               Barzilai-Borwein quotients; this finishes the descent exactly.
  * history     : device, (max_iter + 1) x 4 float64, or NULL: row k receives
  *               { ||G - X Psi||_F (NaN when the stop test was not due),
  *                 ||X^T X - I||_F, eta^k (NaN on the last row), k } as
@@ -153,6 +161,7 @@ typedef struct stf_options {
     double eta_const;
     double tol;
     double feas_blowup;
+    double switch_tol;
     double* history;
 } stf_options;
 
@@ -168,7 +177,9 @@ typedef struct stf_options {
  * ms_loop : wall time of the iteration loop (device events)
  * ms_orth : wall time of CholeskyQR2 + the float64 final evaluation
  * kernel_ms[STF_NPROF] : with opt->profile, summed device time of each
- *           kernel group (STF_PROF_*) over prof_iters iterations          */
+ *           kernel group (STF_PROF_*) over prof_iters iterations
+ * switch_iter : iteration at which a float32 / mixed solve continued in
+ *           float64 (see switch_tol), or -1                                 */
 #define STF_PROF_HARTREE  0
 #define STF_PROF_GRAD     1
 #define STF_PROF_GRAM     2
@@ -190,7 +201,7 @@ typedef struct stf_result {
     double ms_orth;
     double kernel_ms[8];
     int32_t prof_iters;
-    int32_t reserved;
+    int32_t switch_iter;
 } stf_result;
 
 /* Bytes of device workspace needed by stf_solve / plam_solve / pcal_solve and

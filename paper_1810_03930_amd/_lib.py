@@ -55,6 +55,7 @@ class StfOptions(ctypes.Structure):
         ("eta_const", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("feas_blowup", ctypes.c_double),
+        ("switch_tol", ctypes.c_double),
         ("history", ctypes.c_void_p),
     ]
 
@@ -73,7 +74,7 @@ class StfResult(ctypes.Structure):
         ("ms_orth", ctypes.c_double),
         ("kernel_ms", ctypes.c_double * 8),
         ("prof_iters", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("switch_iter", ctypes.c_int32),
     ]
 
 PROF_NAMES = ["hartree", "grad", "gram", "stage1", "residual", "stage2", "update"]

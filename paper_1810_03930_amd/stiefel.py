@@ -99,6 +99,7 @@ class SolveOptions:
     eta_const: float = 1.0
     tol: float = 1e-8
     feas_blowup: float = 1e3
+    switch_tol: float = 0.0
 
     def c(self) -> L.StfOptions:
         o = L.StfOptions()
@@ -118,6 +119,7 @@ class SolveOptions:
         o.eta_const = float(self.eta_const)
         o.tol = float(self.tol)
         o.feas_blowup = float(self.feas_blowup)
+        o.switch_tol = float(self.switch_tol)
         return o
 
 

@@ -46,8 +46,8 @@ def test_struct_layouts_match_header():
     # offsets and sizes that the C compiler gives the structs on x86-64
     assert ctypes.sizeof(L.StfProblem) == 56
     assert L.StfProblem.alpha.offset == 32 and L.StfProblem.A.offset == 48
-    assert ctypes.sizeof(L.StfOptions) == 48 + 48
-    assert L.StfOptions.beta.offset == 48
+    assert ctypes.sizeof(L.StfOptions) == 48 + 56
+    assert L.StfOptions.beta.offset == 48 and L.StfOptions.history.offset == 96
     assert ctypes.sizeof(L.StfResult) == 8 + 8 * 8 + 8 * 8 + 8
 
 
