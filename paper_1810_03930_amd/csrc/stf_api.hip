@@ -39,6 +39,20 @@ GramPlan make_gram_plan(int64_t n, int p) {
 ResPlan make_res_plan(int64_t n, int p, int tile) {
     ResPlan r;
     r.tile = tile;
+    if (tile == 256) {
+        // one workgroup per CU (the M_L slice fills most of the LDS), 64-column blocks
+        r.ncb = (p + 63) / 64;
+        r.nrt = (n + 255) / 256;
+        const int64_t pk = (p + 31) / 32 * 32;
+        if (pk > 384) {
+            r.nrb = 0;
+            return r;
+        }
+        int64_t nrb = (256 + r.ncb - 1) / r.ncb;
+        nrb = std::min<int64_t>(nrb, r.nrt);
+        r.nrb = (int)std::max<int64_t>(nrb, 1);
+        return r;
+    }
     r.ncb = (p + tile - 1) / tile;
     r.nrt = (n + tile - 1) / tile;
     const int64_t target = (tile == 128) ? 1024 : 2048;
@@ -75,6 +89,7 @@ Layout make_layout(const stf_problem* prob, int precision) {
     } else {
         L.x64 = take(np * 8);
         L.g64 = take(np * 8);
+        L.g64b = take(np * 8);
     }
     L.rho = take((size_t)n * 8);
     L.phi = take((size_t)n * 8);
@@ -99,8 +114,11 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.gram_part = take((size_t)L.gram.nchunks * L.gram.n_tiles * L.gram.bt * L.gram.bt * 8);
     L.res = make_res_plan(n, p, 128);
     L.res64 = make_res_plan(n, p, 64);
-    const size_t nrb_max = (size_t)std::max(L.res.nrb, L.res64.nrb);
-    const size_t nwg_max = std::max((size_t)L.res.nrb * L.res.ncb, (size_t)L.res64.nrb * L.res64.ncb);
+    L.resmx = make_res_plan(n, p, 256);
+    const size_t nrb_max = (size_t)std::max({L.res.nrb, L.res64.nrb, L.resmx.nrb});
+    const size_t nwg_max = std::max({(size_t)L.res.nrb * L.res.ncb,
+                                     (size_t)L.res64.nrb * L.res64.ncb,
+                                     (size_t)L.resmx.nrb * L.resmx.ncb});
     L.res_col = take(nrb_max * p * 2 * 8);
     L.res_scal = take(nwg_max * 4 * 8);
     L.dots = take(512 * 2 * 8);
@@ -227,6 +245,7 @@ struct IterCtx {
     int dtype, precision;
     void* X;
     double* Xm;  // float64 master iterate of the float32 forms (null in float64)
+    size_t g[2]; // G / gradL double buffer (workspace offsets)
     DevState* st;
     DevParams* prm;
 };
@@ -241,8 +260,8 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     const Ws& w = c.w;
     const int64_t n = prob->n;
     const int p = prob->p;
-    void* Gc = w.base + w.L.g[parity];
-    void* Gp = w.base + w.L.g[parity ^ 1];
+    void* Gc = w.base + c.g[parity];
+    void* Gp = w.base + c.g[parity ^ 1];
     double* rho = has_hartree(prob) ? w.at<double>(w.L.rho) : nullptr;
     mark(0);
     if (has_hartree(prob))
@@ -257,11 +276,10 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     mark(3);
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
                   w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
-    if (c.precision == STF_PREC_FP64)
-        launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
-                            w.at<double>(w.L.T1), w.at<double>(w.L.T2), p, c.st, s);
+    launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
+                        w.at<double>(w.L.T1), w.at<double>(w.L.T2), p, c.st, s);
     mark(4);
-    const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.res64 : w.L.res;
+    const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.mixed_plan() : w.L.res;
     launch_residual(c.dtype, c.precision, rp, c.X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
                     w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
@@ -311,6 +329,8 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     c.precision = opt->precision;
     c.X = X;
     c.Xm = (dtype == STF_F32) ? w.at<double>(w.L.x64) : nullptr;
+    c.g[0] = w.L.g[0];
+    c.g[1] = w.L.g[1];
     c.st = w.at<DevState>(w.L.state);
     c.prm = w.at<DevParams>(w.L.params);
 
@@ -327,7 +347,8 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     hp.bb_index = opt->bb_index;
     hp.max_iter = opt->max_iter;
     hp.kkt_every = opt->kkt_every;
-    hp.kkt_identity = (opt->precision == STF_PREC_FP64) ? 1 : 0;
+    hp.kkt_identity = 1;
+    hp.switch_tol = (opt->precision == STF_PREC_FP64) ? 0.0 : std::max(0.0, opt->switch_tol);
     hp.history = opt->history;
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);
@@ -347,8 +368,6 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
 
     int chunk = std::max(1, opt->check_every);
     if (opt->use_graph && (chunk & 1)) chunk += 1;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
     const bool prof = opt->profile != 0;
     std::vector<hipEvent_t> pev;
     if (prof) {
@@ -357,61 +376,93 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     }
     double kms[STF_NPROF] = {0};
     int prof_iters = 0;
-    // the legacy default stream cannot be captured: run uncaptured there
-    if (opt->use_graph && !prof && s != nullptr) {
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < chunk; ++i) enqueue_iteration(c, i & 1, s);
-        if (hipStreamEndCapture(s, &graph) != hipSuccess) return STF_E_HIP;
-        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(graph);
-            return STF_E_HIP;
-        }
-    }
     DevState hs;
     memset(&hs, 0, sizeof(hs));
     const int64_t limit = (int64_t)opt->max_iter + 1;
-    int64_t enq = 0;
-    int64_t last_todo = 0;
-    int hip_err = 0;
-    while (true) {
-        if (gexec) {
-            if (hipGraphLaunch(gexec, s) != hipSuccess) { hip_err = 1; break; }
-            enq += chunk;
-            last_todo = chunk;
-        } else {
-            // no iterations past max_iter: the last uncaptured chunk is clamped
-            const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
-            for (int i = 0; i < todo; ++i)
-                enqueue_iteration(c, (int)((enq + i) & 1), s,
-                                  prof ? &pev[(size_t)i * (STF_NPROF + 1)] : nullptr);
-            enq += todo;
-            last_todo = todo;
-            if (last_launch()) { hip_err = 1; break; }
-        }
-        if (hipMemcpyAsync(&hs, c.st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            hip_err = 1;
-            break;
-        }
-        if (prof) {
-            // iterations after "done" are no-ops; count only the ones that ran
-            const int64_t first = enq - last_todo;
-            const int64_t last = hs.done ? (int64_t)hs.final_iter : enq - 1;
-            for (int i = 0; i < last_todo && first + i <= last; ++i) {
-                hipEvent_t* e = &pev[(size_t)i * (STF_NPROF + 1)];
-                for (int g = 0; g < STF_NPROF; ++g) {
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e[g], e[g + 1]);
-                    kms[g] += ms;
-                }
-                ++prof_iters;
+
+    // Enqueue iterations k0, k0+1, ... of context cc in chunks until the
+    // device state says "done"; returns nonzero on a HIP error.
+    auto run_phase = [&](const IterCtx& cc, int64_t k0) -> int {
+        hipGraphExec_t gexec = nullptr;
+        hipGraph_t graph = nullptr;
+        // the legacy default stream cannot be captured: run uncaptured there
+        if (opt->use_graph && !prof && s != nullptr) {
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
+            for (int i = 0; i < chunk; ++i) enqueue_iteration(cc, (int)((k0 + i) & 1), s);
+            if (hipStreamEndCapture(s, &graph) != hipSuccess) return 1;
+            if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphDestroy(graph);
+                return 1;
             }
         }
-        if (hs.done) break;
-        if (enq > limit + 2 * chunk) { hip_err = 1; break; }  // stage 2 ends every run by max_iter
+        int64_t enq = k0;
+        int64_t last_todo = 0;
+        int err = 0;
+        while (true) {
+            if (gexec) {
+                if (hipGraphLaunch(gexec, s) != hipSuccess) { err = 1; break; }
+                enq += chunk;
+                last_todo = chunk;
+            } else {
+                // no iterations past max_iter: the last uncaptured chunk is clamped
+                const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
+                for (int i = 0; i < todo; ++i)
+                    enqueue_iteration(cc, (int)((enq + i) & 1), s,
+                                      prof ? &pev[(size_t)i * (STF_NPROF + 1)] : nullptr);
+                enq += todo;
+                last_todo = todo;
+                if (last_launch()) { err = 1; break; }
+            }
+            if (hipMemcpyAsync(&hs, cc.st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                err = 1;
+                break;
+            }
+            if (prof) {
+                // iterations after "done" are no-ops; count only the ones that ran
+                const int64_t first = enq - last_todo;
+                const int64_t last = hs.done ? (int64_t)hs.final_iter : enq - 1;
+                for (int i = 0; i < last_todo && first + i <= last; ++i) {
+                    hipEvent_t* e = &pev[(size_t)i * (STF_NPROF + 1)];
+                    for (int g = 0; g < STF_NPROF; ++g) {
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, e[g], e[g + 1]);
+                        kms[g] += ms;
+                    }
+                    ++prof_iters;
+                }
+            }
+            if (hs.done) break;
+            if (enq > limit + 2 * chunk) { err = 1; break; }  // stage 2 ends every run by max_iter
+        }
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (graph) hipGraphDestroy(graph);
+        return err;
+    };
+
+    int hip_err = run_phase(c, 0);
+    res->switch_iter = -1;
+    if (!hip_err && hs.done && hs.status == STF_SWITCH) {
+        // Redo iteration k in float64 from the master iterate: the previous
+        // gradL (float32, exact in float64) seeds the Barzilai-Borwein pair.
+        const int64_t k = hs.final_iter;
+        res->switch_iter = (int)k;
+        IterCtx c64 = c;
+        c64.dtype = STF_F64;
+        c64.precision = STF_PREC_FP64;
+        c64.X = c.Xm;
+        c64.Xm = nullptr;
+        c64.g[k & 1] = w.L.g64;
+        c64.g[(k & 1) ^ 1] = w.L.g64b;
+        if (k >= 1)
+            launch_convert(STF_F64, w.base + c.g[(k & 1) ^ 1], STF_F32,
+                           w.base + c64.g[(k & 1) ^ 1], (size_t)n * p, s);
+        hp.switch_tol = 0.0;
+        if (hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess)
+            hip_err = 1;
+        launch_resume_state(c.st, s);
+        if (!hip_err) hip_err = run_phase(c64, k);
     }
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
     for (auto& e : pev) (void)hipEventDestroy(e);
     for (int g = 0; g < STF_NPROF; ++g) res->kernel_ms[g] = kms[g];
     res->prof_iters = prof_iters;

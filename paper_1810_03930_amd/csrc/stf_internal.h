@@ -37,8 +37,12 @@ struct DevParams {
     int32_t n_col_parts;    // number of row-block column partials
     int32_t kkt_identity;   // 1: stop test from the float64 p x p identity (no second product)
     int32_t pad;
+    double switch_tol;      // relative KKT at which a reduced-precision solve hands over
     double* history;        // optional per-iteration record, (max_iter + 1) x 4
 };
+
+// Internal status of a reduced-precision phase that reached switch_tol.
+#define STF_SWITCH 2
 
 // Tiling of the split-K Gram pass.
 struct GramPlan {
@@ -51,9 +55,10 @@ struct GramPlan {
     int64_t chunk;   // rows per chunk (multiple of 4)
 };
 
-// Tiling of the row-block x (p x p) product pass (square tiles of `tile`).
+// Tiling of the row-block x (p x p) product pass (square tiles of `tile`;
+// tile 256 is the LDS-resident split-bf16 kernel: 256-row tiles, 64-column blocks).
 struct ResPlan {
-    int tile;        // 128 (float64 / float32 kernels) or 64 (split-bf16 kernel)
+    int tile;        // 128 (float64 / float32), 64 or 256 (split-bf16 kernels)
     int nrb;         // row-block workgroups (each strides over row tiles)
     int ncb;         // ceil(p / tile) column blocks
     int64_t nrt;     // ceil(n / tile) row tiles
@@ -63,7 +68,8 @@ struct ResPlan {
 struct Layout {
     size_t state, state_eval, params, params_eval;
     size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
-    size_t x64, g64;      // float64 n*p buffers for CholeskyQR2 and the final evaluation
+    size_t x64, g64;      // float64 n*p buffers: master iterate (float32 forms) and scratch
+    size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
     size_t rho, phi, hscr;
     size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, T2, fpart;
     size_t nu, colxg, colgg;
@@ -75,7 +81,9 @@ struct Layout {
     GramPlan gram;        // plan for the iteration dtype
     GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)
     ResPlan res;          // float64 / float32 residual pass
-    ResPlan res64;        // split-bf16 residual pass (MIXED)
+    ResPlan res64;        // split-bf16 residual pass (MIXED), M_L from global memory
+    ResPlan resmx;        // split-bf16 residual pass (MIXED), M_L resident in LDS (pk <= 384)
+    const ResPlan& mixed_plan() const { return resmx.nrb > 0 ? resmx : res64; }
 };
 
 int elem_size(int dtype);
@@ -129,6 +137,7 @@ void launch_eval_finish(const stf_problem* prob, const double* X, const double* 
                         int64_t n, int p, double* dots, const double* part_scal, int nps,
                         DevState* st, hipStream_t s);
 void launch_init_state(DevState* st, hipStream_t s);
+void launch_resume_state(DevState* st, hipStream_t s);
 
 // residual modes
 enum { RES_ITERATE = 0, RES_KKT_ONLY = 1 };

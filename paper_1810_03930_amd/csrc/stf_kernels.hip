@@ -106,6 +106,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg) {
 }
 
 // ---------------------------------------------------------------- state ----
+// Clear the stop flag after a precision hand-over (iteration k is redone).
+__global__ void k_resume_state(DevState* st) {
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->status = 0;
+    }
+}
+
 __global__ void k_init_state(DevState* st) {
     if (threadIdx.x == 0) {
         DevState z;
@@ -665,6 +673,145 @@ __global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
 }
 
 
+// LDS-staged split-K Gram pass of the MIXED form for 128 x 128 tiles (p > 64).
+// The workgroup walks its chunk of rows KS at a time.  Each thread loads KS/2
+// rows of one column of Z (= X) and of Y (= X or G) -- 256-byte coalesced
+// loads per wave, prefetched one step ahead -- splits them into bf16 pairs
+// h + l and stores them transposed (K contiguous, 144-byte pitch, so that the
+// 16-byte operand reads of 16 lanes hit distinct banks).  Four waves of 64 x 64
+// accumulate hh + hl + lh in float32, added into float64 every 256 rows.
+// Partials as in k_gram.
+__device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
+                                                  const float* __restrict__ G, int64_t n, int p,
+                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int64_t chunk, double* __restrict__ part,
+                                                  const DevState* __restrict__ st, int bid_,
+                                                  int nblk_) {
+    if (st && st->done) return;
+    constexpr int KS = 64;            // rows per step
+    constexpr int KP = KS + 8;        // LDS pitch in bf16
+    constexpr int RH = KS / 2;        // rows per loader thread
+    constexpr int FLUSH = 256 / KS;   // steps between float64 flushes
+    __shared__ __attribute__((aligned(16))) __bf16 Ls[4][128 * KP];  // Zh, Zl, Yh, Yl
+    const int lid = xcd_remap(bid_, nblk_);
+    const int tile = lid % n_tiles, c = lid / n_tiles;
+    int bi, bj;
+    bool isS;
+    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    const float* Y = isS ? X : G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
+    const int lr = lane & 15, g = lane >> 4;
+    const int zc = bi * 128, yc = bj * 128;
+    const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
+    // loader role: column lc of the tile, rows RH * lh .. RH * lh + RH - 1 of a step
+    const int lc = tid & 127, lh = tid >> 7;
+    const bool zok = zc + lc < p, yok = yc + lc < p;
+    const float* zp = X + zc + lc;
+    const float* yp = Y + yc + lc;
+    float zr[RH], yr[RH];
+    auto load = [&](int64_t kb) {
+#pragma unroll
+        for (int e = 0; e < RH; ++e) {
+            const int64_t row = kb + RH * lh + e;
+            const bool rok = row < k1;
+            zr[e] = (rok && zok) ? zp[(size_t)row * p] : 0.f;
+            yr[e] = (rok && yok) ? yp[(size_t)row * p] : 0.f;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < RH / 8; ++q) {
+            float a[8], b[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                a[e] = zr[8 * q + e];
+                b[e] = yr[8 * q + e];
+            }
+            bf8 ah, al, bh, bl;
+            split2(a, ah, al);
+            split2(b, bh, bl);
+            const int o = lc * KP + RH * lh + 8 * q;
+            *(bf8*)&Ls[0][o] = ah;
+            *(bf8*)&Ls[1][o] = al;
+            *(bf8*)&Ls[2][o] = bh;
+            *(bf8*)&Ls[3][o] = bl;
+        }
+    };
+    f4 acc[4][4];
+    double dacc[4][4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[i][j][q] = 0.f;
+                dacc[i][j][q] = 0.0;
+            }
+    const bool active = (zc < p) && (yc < p) && (k0 < k1);
+    if (active) load(k0);
+    int step = 0;
+    for (int64_t kb = k0; active && kb < k1; kb += KS, ++step) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (kb + KS < k1) load(kb + KS);
+#pragma unroll
+        for (int ks = 0; ks < KS; ks += 32) {
+            bf8 ah[4], al[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = (wi * 64 + i * 16 + lr) * KP + ks + 8 * g;
+                ah[i] = *(const bf8*)&Ls[0][o];
+                al[i] = *(const bf8*)&Ls[1][o];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = (wj * 64 + j * 16 + lr) * KP + ks + 8 * g;
+                const bf8 bh = *(const bf8*)&Ls[2][o];
+                const bf8 bl = *(const bf8*)&Ls[3][o];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
+            }
+        }
+        if (step % FLUSH == FLUSH - 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        dacc[i][j][q] += (double)acc[i][j][q];
+                        acc[i][j][q] = 0.f;
+                    }
+        }
+    }
+    double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = wi * 64 + i * 16 + Mma<float>::row(g, q);
+                const int jj = wj * 64 + j * 16 + lr;
+                out[ii * 128 + jj] = dacc[i][j][q] + (double)acc[i][j][q];
+            }
+}
+__global__ __launch_bounds__(256) void k_gram_bf3_lds(const float* __restrict__ X,
+                                                      const float* __restrict__ G, int64_t n,
+                                                      int p, int nb, int n_s_tiles, int n_tiles,
+                                                      int64_t chunk, double* __restrict__ part,
+                                                      const DevState* __restrict__ st) {
+    body_gram_bf3_lds(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x,
+                      gridDim.x);
+}
+
+
 // out[s][c][k] (s = 0, 1, 2: the exact bf16 split h, m, l of float(M[k][c])),
 // rows c < prow, columns k < pk, zero outside p x p: the transposed, padded
 // operand layout the split-bf16 row-block product reads with 16-byte loads.
@@ -718,7 +865,8 @@ __device__ __forceinline__ void body_residual_bf6(
     if (!APPLY) {
         const int k = st->iter;
         iterate = (mode == RES_ITERATE);
-        kkt_due = (mode == RES_KKT_ONLY) || (k % prm->kkt_every == 0) || (k >= prm->max_iter);
+        kkt_due = PS && ((mode == RES_KKT_ONLY) || (k % prm->kkt_every == 0) ||
+                         (k >= prm->max_iter));
         have_prev = iterate && (k >= 1);
         eta_prev = st->eta;
     }
@@ -874,6 +1022,232 @@ __global__ __launch_bounds__(256) void k_residual_bf6(
     int64_t nrt, double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
     body_residual_bf6<APPLY>(X, G, Gprev, MS, PS, prow, pk, nu, n, p, nrb, ncb, nrt, part_col, part_scal, prm, st, mode, blockIdx.x, gridDim.x);
+}
+
+
+// MIXED residual pass with M_L resident in LDS.  A workgroup owns a column
+// block of 64 and keeps its slice of the split M_L^T (3 x 64 x pk bf16) in LDS
+// for all its row tiles; four waves of 64 rows x 64 columns walk row tiles of
+// 256 rows.  X fragments come straight from global memory (8 consecutive
+// columns of one row per lane, two 16-byte loads), prefetched one K-step
+// ahead and split into h + m + l in registers; the six products
+// sum_{a+b<=2} X_a M_b give float32-level accuracy.  G and gradL^{k-1} of the
+// row tile are loaded before its K loop so that their latency hides behind the
+// MFMAs.  Epilogue, partials and BB pair as in k_residual (stop test by the
+// p x p identity, so no product with Psi).
+template <int PKMAX>
+__device__ __forceinline__ void body_residual_bf6_lds(
+    const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
+    const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
+    int p, int nrb, int ncb, int64_t nrt, double* __restrict__ part_col,
+    double* __restrict__ part_scal, const DevParams* __restrict__ prm,
+    const DevState* __restrict__ st, int bid_, int nblk_) {
+    if (st->done) return;
+    constexpr int LP = PKMAX + 8;  // LDS pitch (bf16) of one column's K run
+    __shared__ __attribute__((aligned(16))) __bf16 Ms[3 * 64 * LP];
+    __shared__ double sh[8];
+    __shared__ double scol[4][2][64];
+    const int lid = xcd_remap(bid_, nblk_);
+    const int rb = lid / ncb, cb = lid % ncb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int cblk = cb * 64;
+    const size_t tot = (size_t)prow * pk;
+    {
+        const int nv = pk / 8;
+        for (int e = tid; e < 3 * 64 * nv; e += 256) {
+            const int sp = e / (64 * nv), rem = e % (64 * nv), cc = rem / nv, kv = rem % nv;
+            *(bf8*)&Ms[(sp * 64 + cc) * LP + kv * 8] =
+                *(const bf8*)(MS + sp * tot + (size_t)(cblk + cc) * pk + kv * 8);
+        }
+    }
+    __syncthreads();
+    const int k = st->iter;
+    const bool have_prev = k >= 1;
+    const double rinv_eta = 1.0 / st->eta;
+    bool cok[4];
+    double onu[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = cblk + j * 16 + lr;
+        cok[j] = c < p;
+        onu[j] = (have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
+    }
+    double cxg[4] = {0.0, 0.0, 0.0, 0.0}, cgg[4] = {0.0, 0.0, 0.0, 0.0};
+    double sss = 0.0, ssy = 0.0, syy = 0.0;
+    const bool vec = (p % 4) == 0;
+    for (int64_t rt = rb; rt < nrt; rt += nrb) {
+        const int64_t r0 = rt * 256 + wave * 64;
+        // G and gradL^{k-1} of this wave's 64 x 64 block, in the MFMA output layout
+        float gv[4][4][4], gpv[4][4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = r0 + i * 16 + Mma<float>::row(g, q);
+                    const bool ok = (r < n) && cok[j];
+                    const size_t idx = (size_t)r * p + cblk + j * 16 + lr;
+                    gv[i][j][q] = ok ? G[idx] : 0.f;
+                    gpv[i][j][q] = (ok && have_prev) ? Gprev[idx] : 0.f;
+                }
+        float xa[4][8];
+        auto load_x = [&](int kc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t r = r0 + i * 16 + lr;
+                const int c = kc + 8 * g;
+                const float* src = X + (size_t)r * p + c;
+                if (vec && r < n && c + 8 <= p) {
+                    const f4 u = *(const f4*)src;
+                    const f4 v = *(const f4*)(src + 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        xa[i][e] = u[e];
+                        xa[i][4 + e] = v[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) xa[i][e] = (r < n && c + e < p) ? src[e] : 0.f;
+                }
+            }
+        };
+        f4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
+        load_x(0);
+        for (int kc = 0; kc < pk; kc += 32) {
+            bf8 xh[4], xm[4], xl[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) split3(xa[i], xh[i], xm[i], xl[i]);
+            if (kc + 32 < pk) load_x(kc + 32);
+            bf8 mh[4], mm[4], ml[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = (j * 16 + lr) * LP + kc + 8 * g;
+                mh[j] = *(const bf8*)&Ms[o];
+                mm[j] = *(const bf8*)&Ms[64 * LP + o];
+                ml[j] = *(const bf8*)&Ms[2 * 64 * LP + o];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], mh[j], acc[i][j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], mm[j], acc[i][j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xm[i], mh[j], acc[i][j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], ml[j], acc[i][j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xl[i], mh[j], acc[i][j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xm[i], mm[j], acc[i][j]);
+        }
+        // gradL = G - X M_L over G; the rows of X for the dots come from L2
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t r = r0 + i * 16 + Mma<float>::row(g, q);
+                    if (r >= n || !cok[j]) continue;
+                    const size_t idx = (size_t)r * p + cblk + j * 16 + lr;
+                    const float glt = (float)((double)gv[i][j][q] - (double)acc[i][j][q]);
+                    G[idx] = glt;
+                    const double gl = (double)glt;
+                    const double x = (double)X[idx];
+                    cxg[j] += x * gl;
+                    cgg[j] += gl * gl;
+                    if (have_prev) {
+                        const double glp = (double)gpv[i][j][q];
+                        const double sd = onu[j] * x - glp * rinv_eta;
+                        const double yd = gl - glp;
+                        sss += sd * sd;
+                        ssy += sd * yd;
+                        syy += yd * yd;
+                    }
+                }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cxg[j] += __shfl_xor(cxg[j], 16, 64);
+        cxg[j] += __shfl_xor(cxg[j], 32, 64);
+        cgg[j] += __shfl_xor(cgg[j], 16, 64);
+        cgg[j] += __shfl_xor(cgg[j], 32, 64);
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            scol[wave][0][j * 16 + lr] = cxg[j];
+            scol[wave][1][j * 16 + lr] = cgg[j];
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int c = cblk + tid;
+        if (c < p) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                a += scol[w][0][tid];
+                b += scol[w][1][tid];
+            }
+            double* pc = part_col + ((size_t)rb * p + c) * 2;
+            pc[0] = a;
+            pc[1] = b;
+        }
+    }
+    // scalar partials: {||R||^2 (unused: identity), <S,S>, <S,Y>, <Y,Y>}
+    double v[3] = {sss, ssy, syy};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();
+    if (lane == 0) {
+        scol[wave][0][0] = v[0];
+        scol[wave][0][1] = v[1];
+        scol[wave][0][2] = v[2];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) t[q] += scol[w][0][q];
+        double* ps = part_scal + (size_t)lid * 4;
+        ps[0] = 0.0;
+        ps[1] = t[0];
+        ps[2] = t[1];
+        ps[3] = t[2];
+    }
+    (void)sh;
+    (void)prm;
+}
+template <int PKMAX>
+__global__ __launch_bounds__(256) void k_residual_bf6_lds(
+    const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
+    const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
+    int p, int nrb, int ncb, int64_t nrt, double* __restrict__ part_col,
+    double* __restrict__ part_scal, const DevParams* __restrict__ prm,
+    const DevState* __restrict__ st) {
+    body_residual_bf6_lds<PKMAX>(X, G, Gprev, MS, prow, pk, nu, n, p, nrb, ncb, nrt, part_col,
+                                 part_scal, prm, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -1427,6 +1801,10 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
             } else if (st->kkt0 == 0.0 || kkt <= prm->tol * st->kkt0) {
                 st->status = STF_OK;
                 stop = 1;
+            } else if (prm->switch_tol > 0.0 && kkt <= prm->switch_tol * st->kkt0) {
+                // hand over to float64: the state is left as it was before this stage
+                st->status = STF_SWITCH;
+                stop = 1;
             }
         }
         if (!stop && k >= prm->max_iter) {
@@ -1681,6 +2059,7 @@ static inline unsigned grid_rows(int64_t n) {
 }
 
 void launch_init_state(DevState* st, hipStream_t s) { k_init_state<<<1, 1, 0, s>>>(st); }
+void launch_resume_state(DevState* st, hipStream_t s) { k_resume_state<<<1, 1, 0, s>>>(st); }
 
 void launch_rowsq(int dtype, const void* X, int64_t n, int p, double* rho, const DevState* st,
                   hipStream_t s) {
@@ -1819,7 +2198,8 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
         else if (gp.wm == 2)
             k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
         else
-            k_gram_bf3<4><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
+            k_gram_bf3_lds<<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part,
+                                               st);
     } else if (dtype == STF_F64) {
         gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles);
     } else {
@@ -1850,17 +2230,32 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     if (dtype == STF_F32 && precision == STF_PREC_MIXED && mode == RES_ITERATE) {
         const int prow = rp.ncb * 64, pk = (p + 31) / 32 * 32;
         __bf16* MS = (__bf16*)mix;
-        __bf16* PS = MS + (size_t)3 * prow * pk;
         const unsigned gs = (unsigned)(((size_t)prow * pk + 255) / 256);
         k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
-        k_split3_t<<<gs, 256, 0, s>>>(Psi, PS, p, prow, pk, st);
+        if (rp.tile == 256) {
+            // M_L slice resident in LDS (plans of this shape only exist for pk <= 384)
+            if (pk <= 128)
+                k_residual_bf6_lds<128><<<nwg, 256, 0, s>>>(
+                    (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
+                    rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
+            else if (pk <= 256)
+                k_residual_bf6_lds<256><<<nwg, 256, 0, s>>>(
+                    (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
+                    rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
+            else
+                k_residual_bf6_lds<384><<<nwg, 256, 0, s>>>(
+                    (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
+                    rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
+            return;
+        }
+        // the stop test comes from the p x p identity: no product with Psi
         k_residual_bf6<false><<<nwg, 256, 0, s>>>(
-            (const float*)X, (float*)G, (const float*)Gprev, MS, PS, prow, pk, nu, n, p, rp.nrb,
+            (const float*)X, (float*)G, (const float*)Gprev, MS, nullptr, prow, pk, nu, n, p, rp.nrb,
             rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
         return;
     }
-    // float64 iterations evaluate the stop test by the p x p identity (no second product)
-    const bool kkt_prod = (mode == RES_KKT_ONLY) || (dtype == STF_F32);
+    // iterations evaluate the stop test by the p x p identity (no second product)
+    const bool kkt_prod = (mode == RES_KKT_ONLY);
     if (dtype == STF_F64) {
         if (kkt_prod)
             k_residual<double, false, true><<<nwg, 256, 0, s>>>(
@@ -1870,8 +2265,12 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
             k_residual<double, false, false><<<nwg, 256, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
                 rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
-    } else {
+    } else if (kkt_prod) {
         k_residual<float, false, true><<<nwg, 256, 0, s>>>(
+            (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
+            rp.nrt, part_col, part_scal, prm, st, mode);
+    } else {
+        k_residual<float, false, false><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
     }

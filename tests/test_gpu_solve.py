@@ -205,3 +205,58 @@ def test_fp32_form_error_stated():
     err = rel(X, ref.iterates[50])
     print(f"fp32 form: relative iterate error after 50 steps = {err:.3e}")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_switch_at_start_is_the_fp64_form(precision):
+    """switch_tol >= 1 hands over at k = 0: the solve is then the float64 form
+    started from the float32-rounded X0, bit for bit, and so matches the oracle."""
+    prob, x0 = _problem("ks3d")
+    x0r = x0.astype(np.float32).astype(np.float64)
+    o, g = _pair(prob, beta=4.0, max_iter=40, precision=precision)
+    g.switch_tol = 2.0
+    res, _, X64, _ = _gpu_solve(prob, x0r, g)
+    _, g64 = _pair(prob, beta=4.0, max_iter=40)
+    res64, _, X64b, _ = _gpu_solve(prob, x0r, g64)
+    assert res["switch_iter"] == 0 and res64["switch_iter"] == -1
+    assert res["iters"] == res64["iters"] == 40
+    assert np.array_equal(X64, X64b)
+    o.record_iterates = [40]
+    ref = O.solve(OracleProblem(prob), x0r, o)
+    assert rel(X64, ref.iterates[40]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_switch_reaches_fp64_tolerance(precision):
+    """A reduced-precision solve handed over to float64 at 1e-4 reaches a
+    tolerance below what float32 arithmetic can resolve, at the oracle's minimum."""
+    prob, x0 = _problem("ks3d")
+    op = OracleProblem(prob)
+    o, g = _pair(prob, beta=4.0, max_iter=3000, tol=1e-9, orth=True, precision=precision)
+    g.switch_tol = 1e-4
+    ref = O.solve(op, x0, o)
+    res, _, X64, lam = _gpu_solve(prob, x0, g)
+    print(f"{precision}: switched to float64 at k={res['switch_iter']}, "
+          f"converged at {res['iters']} (oracle {ref.iters}), kkt_rel {res['kkt_rel']:.2e}")
+    assert ref.status == 0 and res["rc"] == 0
+    assert 0 < res["switch_iter"] < res["iters"]
+    assert res["kkt_rel"] <= 1.01e-9
+    assert abs(res["fval"] - ref.f) <= 1e-8 * abs(ref.f)
+    _check_returned_point(op, res, X64, lam)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+@pytest.mark.parametrize("grid,p", [((20, 18, 16), 100), ((16, 16, 12), 300)])
+def test_reduced_precision_iterates_wide(precision, grid, p):
+    """Column blocks beyond one tile and ragged p (100: two 64-column blocks,
+    the second partly empty; 300: K padded to 320) in the float32 forms."""
+    prob, x0, _ = W.ks3d(grid=grid, p=p)
+    k = 5
+    o, g = _pair(prob, beta=4.0, max_iter=k, precision=precision)
+    o.record_iterates = [k]
+    ref = O.solve(OracleProblem(prob), x0, o)
+    res, X, _, _ = _gpu_solve(prob, x0, g)
+    err = rel(X, ref.iterates[k])
+    print(f"{precision} form {grid} p={p}: relative iterate error after {k} steps = {err:.3e}")
+    assert res["iters"] == k
+    assert err <= 1e-5 * k

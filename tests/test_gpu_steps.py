@@ -118,7 +118,8 @@ def test_gram_fp32(n, p):
     assert rel(to_np(Wg), Xd.T @ Gd) <= 2e-6
 
 
-@pytest.mark.parametrize("n,p", [(1000, 37), (5003, 100), (4096, 256), (700, 20)])
+@pytest.mark.parametrize("n,p", [(1000, 37), (5003, 100), (4096, 256), (700, 20), (2600, 300),
+                                 (9001, 129)])
 def test_gram_mixed_split_bf16(n, p):
     """Split-bf16 Gram (three bf16 products, float32 tiles, float64 across tiles).
     Each product carries a relative error of order 2^-16 (x = hi + lo leaves
