@@ -4,12 +4,15 @@ One "step" is one PCAL iteration (Algorithm 3): Hartree solve, gradient,
 Gram products, p x p multiplier stage, residual / step-size pass, update.
 
 Reported (one JSON line on stdout):
-  value        PCAL iterations/s of the fast (reduced-precision) form, inputs
+  value        PCAL iterations/s of the fast form (mixed: split-bf16 MFMA
+               products, float32 storage, float64 master iterate), inputs
                resident in HBM, over exactly `--steps` iterations after
-               `--warmup` untimed ones
-  forms        per form (fp64 and the fast form): iterations/s, time to
-               relative KKT <= 1e-6 (loop + CholeskyQR2 + float64 check),
-               iterations to that point, f, KKT and feasibility at the end
+               `--warmup` untimed ones (device events around the loop)
+  forms        per form (fp64 and the fast form): iterations/s, per-kernel
+               average times, time to relative KKT <= 1e-6 (loop +
+               CholeskyQR2 + float64 check; the fast form hands over to
+               float64 at relative KKT 2e-5), iterations to that point, f,
+               KKT and feasibility at the end
   speedup      time-to-KKT of the fp64 form / that of the fast form
   roofline     the dominant kernel of the fast form's timed steps
   cpu_baseline the float64 oracle on this host's cores, on a bounded sample
@@ -31,8 +34,9 @@ if ROOT not in sys.path:
 GRID = (64, 64, 64)
 P = 256
 ALPHA = 1.0
-BETA = 2.0          # PCAL penalty for the 3D KS workloads (see the design notes)
+BETA = 4.0          # PCAL penalty for the 3D KS workload (above its p-th eigenvalue)
 TOL = 1e-6
+SWITCH_TOL = 2e-5   # relative KKT at which the fast form continues in float64
 MAX_ITER = 3000
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed_bf16": 2500.0}
@@ -42,28 +46,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_algorithmic(name, n, p, s, kkt_every=1):
-    """Algorithmic (bytes, flops) of one launch of a kernel group per iteration.
+def kernel_algorithmic(name, n, p, precision):
+    """Algorithmic (bytes, flops) of one launch of a kernel per iteration.
 
-    s = bytes per element of X / G.  Bytes count each operand read or written
-    once; flops count multiply-adds as 2.
+    Bytes count each operand read or written once (neighbour rows of the
+    stencil count once); flops count a multiply-add as 2 and only the
+    mathematical products (not the extra split-bf16 products).
     """
-    nps = float(n) * p * s
-    if name == "grad":        # read X (+ neighbours, cached), v, phi; write G
-        return 2 * nps + 16.0 * n, 15.0 * n * p
-    if name == "gram":        # read X, G; S upper half + W full
-        return 2 * nps, 3.0 * n * p * p
-    if name == "residual":    # read X, G, gradL_prev; write gradL; X M_L (+ X Psi)
-        return 4 * nps, (2.0 + 2.0 / kkt_every) * n * p * p
-    if name == "update":      # read X, gradL; write X and rho
-        return 3 * nps + 8.0 * n, 4.0 * n * p
+    npe = float(n) * p
+    s = 8 if precision == "fp64" else 4
+    if name == "grad":        # read X (float64 master in the float32 forms) + v, phi; write G
+        return npe * (8 + s) + 16.0 * n, 14.0 * npe
+    if name == "gram":        # read X, G: S (upper half) and W
+        return 2 * npe * s, 2.0 * n * (p * (p + 1) / 2.0 + p * p)
+    if name == "residual":    # read X, G, gradL^{k-1}; write gradL over G: G - X M_L
+        return 4 * npe * s, 2.0 * n * p * p
+    if name == "update":      # read X (+ master), gradL; write X (+ master), rho
+        return (3 * npe * 8 if precision == "fp64" else npe * (8 + 4 + 8 + 4)) + 8.0 * n, 4.0 * npe
     if name == "hartree":     # six 1D sine transforms over the grid
         return 7 * 8.0 * n, 6 * 2.0 * n * max(GRID)
     return 0.0, 0.0
 
 
-def run_form(dp, x0, precision, steps, warmup, S, torch):
-    """Timed steps (profiled per kernel) and a time-to-KKT solve for one form."""
+def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True):
+    """Timed steps, a per-kernel profile and a time-to-KKT solve for one form."""
     dt = S.storage_dtype(precision)
     eta0 = BETA + dp.s_bound
     common = dict(variant="pcal", mult="psi_phi", eta_rule="abb", precision=precision,
@@ -83,26 +89,37 @@ def run_form(dp, x0, precision, steps, warmup, S, torch):
         S.solve(dp, X, S.SolveOptions(**common, tol=0.0, max_iter=max(1, warmup),
                                       orth_final=False, check_every=max(1, warmup),
                                       use_graph=False), workspace=ws, stream=stream)
-        # timed: exactly `steps` iterations, every kernel group bracketed by events
+        # timed: exactly `steps` iterations (plus the stop test at k = steps);
+        # HIP events on the solver's stream bracket the loop
         fresh()
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         res, _, _ = S.solve(dp, X, S.SolveOptions(**common, tol=0.0, max_iter=steps,
                                                   orth_final=False, check_every=steps,
-                                                  use_graph=False, profile=True),
+                                                  use_graph=False),
                             workspace=ws, stream=stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        # the loop also evaluates the stop test at k = steps (one extra partial pass)
         ms_step = res["ms_loop"] / steps
-        prof_n = max(1, res["prof_iters"])
-        kernel_avg_ms = {k: v / prof_n for k, v in res["kernel_ms"].items()}
+        # per-kernel averages: the same iterations with every kernel bracketed by events
+        fresh()
+        prof, _, _ = S.solve(dp, X, S.SolveOptions(**common, tol=0.0, max_iter=steps,
+                                                   orth_final=False, check_every=steps,
+                                                   use_graph=False, profile=True),
+                             workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        prof_n = max(1, prof["prof_iters"])
+        kernel_avg_ms = {k: v / prof_n for k, v in prof["kernel_ms"].items()}
+        if not ttk:
+            return {"iters_per_s": 1000.0 / ms_step, "ms_per_step": ms_step,
+                    "timed_wall_s": wall, "kernel_avg_ms": kernel_avg_ms,
+                    "kernel_sum_ms": sum(kernel_avg_ms.values())}, None
         # time to relative KKT <= TOL from X0 resident in HBM, graph-replayed loop
         fresh()
         t0 = time.perf_counter()
+        sw = SWITCH_TOL if precision != "fp64" else 0.0
         conv, x64, _ = S.solve(dp, X, S.SolveOptions(**common, tol=TOL, max_iter=MAX_ITER,
                                                      orth_final=True, check_every=50,
-                                                     use_graph=True),
+                                                     use_graph=True, switch_tol=sw),
                                workspace=ws, stream=stream, want_x64=True)
         torch.cuda.synchronize()
         wall_kkt = time.perf_counter() - t0
@@ -111,9 +128,11 @@ def run_form(dp, x0, precision, steps, warmup, S, torch):
         "ms_per_step": ms_step,
         "timed_wall_s": wall,
         "kernel_avg_ms": kernel_avg_ms,
+        "kernel_sum_ms": sum(kernel_avg_ms.values()),
         "time_to_kkt_s": (conv["ms_loop"] + conv["ms_orth"]) / 1000.0,
         "time_to_kkt_wall_s": wall_kkt,
         "iters_to_kkt": conv["iters"],
+        "switch_iter": conv["switch_iter"],
         "status": conv["rc"],
         "kkt_rel": conv["kkt_rel"],
         "kkt_abs": conv["kkt_abs"],
@@ -124,25 +143,57 @@ def run_form(dp, x0, precision, steps, warmup, S, torch):
     return out, x64
 
 
+KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_residual",
+                "update": "k_update", "hartree": "k_dst_axis"}
+
+
+def traffic_for(kernel, precision):
+    """Measured HBM bytes per launch from committed counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    with open(path) as f:
+        tab = json.load(f)
+    src = os.path.join(ROOT, "paper_1810_03930_amd", "csrc", "stf_kernels.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    ent = tab.get(f"{precision}/{kernel}")
+    if not ent or ent.get("source_sha256") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
 def roofline_for(form, precision, n, p):
-    s = 8 if precision == "fp64" else 4
-    ka = form["kernel_avg_ms"]
+    ka = {k: v for k, v in form["kernel_avg_ms"].items() if k in KERNEL_NAMES}
     name = max(ka, key=lambda k: ka[k])
     ms = ka[name]
-    by, fl = kernel_algorithmic(name, n, p, s)
-    peak_key = "fp64" if precision == "fp64" else ("fp32" if precision == "fp32" else "mixed_bf16")
+    by, fl = kernel_algorithmic(name, n, p, precision)
+    # the arithmetic that bounds each kernel: the float64 MFMA/vector peak, or
+    # the split-bf16 products (3 for the Gram, 6 for the residual) at bf16 peak
+    mults = {"gram": 3.0, "residual": 6.0}
+    if precision == "fp64":
+        t_mma = fl / (PEAK_TFLOPS["fp64"] * 1e12)
+        peak_f = PEAK_TFLOPS["fp64"]
+    elif precision == "fp32":
+        t_mma = fl / (PEAK_TFLOPS["fp32"] * 1e12)
+        peak_f = PEAK_TFLOPS["fp32"]
+    else:
+        t_mma = fl * mults.get(name, 0.0) / (PEAK_TFLOPS["mixed_bf16"] * 1e12)
+        peak_f = PEAK_TFLOPS["mixed_bf16"] / mults.get(name, 1.0)
     t_mem = by / (HBM_PEAK_GBS * 1e9)
-    t_mma = fl / (PEAK_TFLOPS[peak_key] * 1e12)
-    if t_mma > t_mem:
+    traffic = traffic_for(name, precision)
+    common = {"kernel": KERNEL_NAMES[name], "group": name, "avg_launch_ms": ms,
+              "algorithmic_bytes": by, "algorithmic_flops": fl,
+              "traffic": traffic}
+    if t_mma > t_mem and name in mults:
         ach = fl / (ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[peak_key]
-        return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "avg_launch_ms": ms, "algorithmic_flops": fl}
+        return {"bound": "mfma", "achieved": ach, "peak": peak_f, "unit": "TFLOP/s",
+                "frac": ach / peak_f, **common}
     ach = by / (ms * 1e-3) / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": ms,
-            "algorithmic_bytes": by}
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, **common}
 
 
 def cpu_baseline(prob, x0):
@@ -172,8 +223,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fast-form", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--fast-form", default="mixed", choices=["fp32", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-ttk", action="store_true",
+                    help="skip the time-to-KKT solves (short runs under hardware counters)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="first run a plain 512 MiB device copy 3 times: the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -188,13 +244,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_ref:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log("generating the 64^3 p=256 workload (seeded)")
     prob, x0, _ = W.ks3d(grid=GRID, p=P, alpha=ALPHA)
     dp = S.DeviceProblem.from_host(prob)
     forms = {}
     for prec in ["fp64", args.fast_form]:
         log(f"form {prec}: {args.warmup} warmup + {args.steps} timed steps, then time-to-KKT")
-        forms[prec], _ = run_form(dp, x0, prec, args.steps, args.warmup, S, torch)
+        forms[prec], _ = run_form(dp, x0, prec, args.steps, args.warmup, S, torch,
+                                  ttk=not args.skip_ttk)
         log(f"form {prec}: {json.dumps(forms[prec])}")
     fast = forms[args.fast_form]
     base = forms["fp64"]
@@ -215,14 +279,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.fast_form == "fp32" else "f32+bf16x3",
+        "dtype": "f32" if args.fast_form == "fp32" else "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
         "data": "synthetic",
         "config": {"workload": "3D Kohn-Sham-shaped PCAL, 7-point Dirichlet Laplacian on a "
-                               "64^3 grid + Diag(V), V~U(0,1), alpha=1, beta=2, ABB steps",
+                               "64^3 grid + Diag(V), V~U(0,1), alpha=1, beta=4, ABB steps",
                    "n": prob.n, "p": P, "grid": list(GRID), "tol_rel_kkt": TOL,
-                   "fast_form": args.fast_form},
-        "time_to_kkt_s": {"fp64": base["time_to_kkt_s"], args.fast_form: fast["time_to_kkt_s"]},
-        "speedup_time_to_kkt": base["time_to_kkt_s"] / fast["time_to_kkt_s"],
+                   "fast_form": args.fast_form, "switch_tol": SWITCH_TOL},
+        "time_to_kkt_s": None if args.skip_ttk else
+        {"fp64": base["time_to_kkt_s"], args.fast_form: fast["time_to_kkt_s"]},
+        "speedup_time_to_kkt": None if args.skip_ttk else
+        base["time_to_kkt_s"] / fast["time_to_kkt_s"],
         "forms": forms,
         "roofline": roof,
         "roofline_fp64": roof64,

@@ -177,7 +177,12 @@ typedef struct stf_options {
  * ms_loop : wall time of the iteration loop (device events)
  * ms_orth : wall time of CholeskyQR2 + the float64 final evaluation
  * kernel_ms[STF_NPROF] : with opt->profile, summed device time of each
- *           kernel group (STF_PROF_*) over prof_iters iterations
+ *           kernel group (STF_PROF_*) over prof_iters iterations.  GRAD, GRAM,
+ *           RESIDUAL and UPDATE each bracket exactly one kernel launch;
+ *           HARTREE brackets the six sine-transform passes; STAGE1 the
+ *           reduction of the Gram partials, the p x p stage, the p x p KKT
+ *           products (and the split of M_L in the mixed form); STAGE2 the
+ *           column-dot reduction and the step-size / stop stage
  * switch_iter : iteration at which a float32 / mixed solve continued in
  *           float64 (see switch_tol), or -1                                 */
 #define STF_PROF_HARTREE  0

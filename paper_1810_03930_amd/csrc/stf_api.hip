@@ -271,19 +271,19 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     launch_grad(prob, c.dtype, c.X, Gc, w.at<double>(w.L.phi), c.st, s,
                 prob->kind == STF_KIND_DENSE ? nullptr : c.Xm);
     mark(2);
+    // groups 2..4: the Gram kernel | chunk reduction, p x p stage, KKT products,
+    // split of M_L | the residual kernel (events 3 and 4 recorded by the launchers)
     launch_gram(c.dtype, c.precision, w.L.gram, c.X, Gc, n, p, w.at<double>(w.L.gram_part),
-                w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s);
-    mark(3);
+                w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s, ev ? ev[3] : nullptr);
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
                   w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
     launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
                         w.at<double>(w.L.T1), w.at<double>(w.L.T2), p, c.st, s);
-    mark(4);
     const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.mixed_plan() : w.L.res;
     launch_residual(c.dtype, c.precision, rp, c.X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
                     w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
-                    RES_ITERATE, w.base + w.L.mix, s);
+                    RES_ITERATE, w.base + w.L.mix, s, ev ? ev[4] : nullptr);
     mark(5);
     launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
                   w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Bm),

@@ -105,7 +105,8 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
 // S = X^T X (if S) and W = X^T G (if W), float64 p x p, full
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
-                 double* W, const DevState* st, hipStream_t s);
+                 double* W, const DevState* st, hipStream_t s,
+                 hipEvent_t after_main = nullptr);
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
                    DevState* st, hipStream_t s);
@@ -115,7 +116,7 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      void* G, const void* Gprev, const double* ML, const double* Psi,
                      const double* nu, int64_t n, int p, double* part_col,
                      double* part_scal, const DevParams* prm, DevState* st,
-                     int mode, void* mix, hipStream_t s);
+                     int mode, void* mix, hipStream_t s, hipEvent_t before_main = nullptr);
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* W,
                    const double* Bm, const double* T1, const double* T2,

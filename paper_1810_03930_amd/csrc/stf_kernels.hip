@@ -247,58 +247,88 @@ __global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
 }
 
 // ------------------------------------------------------------ gradient ----
-// G = (L + Diag v + alpha Diag phi) X for the 1D / 3D Dirichlet stencils,
-// computed in the arithmetic of the input X and stored as TO.  One wave per
-// grid point (row), lanes stride over the p columns.
-template <typename T, typename TO>
+// G = (L + Diag v + alpha Diag phi) X for the 1D (ND = 2 neighbours) and 3D
+// (ND = 6) Dirichlet stencils, computed in the arithmetic of the input X and
+// stored as TO.  One wave per grid point (row) at a time; lanes take 16-byte
+// vectors of the row, and the loads of the row and of all its neighbours are
+// issued before any use (a neighbour missing at the boundary reads the row
+// itself with weight 0).  Workgroups keep the hardware round-robin over the
+// XCDs, so the y- and z-neighbours of a row (nx and nx*ny rows away) are read
+// by the same XCD a few hundred rows later and come from its L2.
+template <typename T, typename TO, int ND>
 __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                                                       TO* __restrict__ G, int64_t n, int p,
-                                                      int nx, int ny, int nz, int dim3d,
+                                                      int nx, int ny, int nz,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
                                                       double alpha,
                                                       const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
+    constexpr int V = 16 / (int)sizeof(T);
+    typedef T tv __attribute__((ext_vector_type(V)));
     const int lane = threadIdx.x & 63;
+    const bool vec = (p % V) == 0;
     for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
          r += (int64_t)nblk_ * 4) {
-        double dg = dim3d ? 6.0 : 2.0;
+        double dg = (ND == 6) ? 6.0 : 2.0;
         if (v) dg += v[r];
         if (phi) dg += alpha * phi[r];
-        int64_t nb[6];
-        int nn = 0;
-        if (!dim3d) {
-            if (r > 0) nb[nn++] = r - 1;
-            if (r + 1 < n) nb[nn++] = r + 1;
+        int64_t nb[ND];
+        T w[ND];
+        if (ND == 2) {
+            nb[0] = r > 0 ? r - 1 : r;
+            w[0] = r > 0 ? (T)1 : (T)0;
+            nb[1] = r + 1 < n ? r + 1 : r;
+            w[1] = r + 1 < n ? (T)1 : (T)0;
         } else {
             const int64_t sxy = (int64_t)nx * ny;
             const int64_t x = r % nx, y = (r / nx) % ny, z = r / sxy;
-            if (x > 0) nb[nn++] = r - 1;
-            if (x + 1 < nx) nb[nn++] = r + 1;
-            if (y > 0) nb[nn++] = r - nx;
-            if (y + 1 < ny) nb[nn++] = r + nx;
-            if (z > 0) nb[nn++] = r - sxy;
-            if (z + 1 < nz) nb[nn++] = r + sxy;
+            const bool has[6] = {x > 0, x + 1 < nx, y > 0, y + 1 < ny, z > 0, z + 1 < nz};
+            const int64_t d[6] = {-1, 1, -(int64_t)nx, (int64_t)nx, -sxy, sxy};
+#pragma unroll
+            for (int q = 0; q < ND; ++q) {
+                nb[q] = has[q] ? r + d[q] : r;
+                w[q] = has[q] ? (T)1 : (T)0;
+            }
         }
         const T tdg = (T)dg;
         const T* xr = X + (size_t)r * p;
         TO* gr = G + (size_t)r * p;
-        for (int c = lane; c < p; c += 64) {
-            T s = tdg * xr[c];
-            for (int q = 0; q < nn; ++q) s -= X[(size_t)nb[q] * p + c];
-            gr[c] = (TO)s;
+        if (vec) {
+            for (int c = lane * V; c < p; c += 64 * V) {
+                tv xc = *(const tv*)(xr + c);
+                tv xn[ND];
+#pragma unroll
+                for (int q = 0; q < ND; ++q) xn[q] = *(const tv*)(X + (size_t)nb[q] * p + c);
+                tv acc = tdg * xc;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) acc -= w[q] * xn[q];
+                typedef TO ov __attribute__((ext_vector_type(V)));
+                ov o;
+#pragma unroll
+                for (int e = 0; e < V; ++e) o[e] = (TO)acc[e];
+                *(ov*)(gr + c) = o;
+            }
+        } else {
+            for (int c = lane; c < p; c += 64) {
+                T acc = tdg * xr[c];
+#pragma unroll
+                for (int q = 0; q < ND; ++q) acc -= w[q] * X[(size_t)nb[q] * p + c];
+                gr[c] = (TO)acc;
+            }
         }
     }
 }
-template <typename T, typename TO>
+template <typename T, typename TO, int ND>
 __global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
                                                       TO* __restrict__ G, int64_t n, int p,
-                                                      int nx, int ny, int nz, int dim3d,
+                                                      int nx, int ny, int nz,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
                                                       double alpha,
                                                       const DevState* __restrict__ st) {
-    body_grad_stencil<T, TO>(X, G, n, p, nx, ny, nz, dim3d, v, phi, alpha, st, blockIdx.x, gridDim.x);
+    body_grad_stencil<T, TO, ND>(X, G, n, p, nx, ny, nz, v, phi, alpha, st, blockIdx.x,
+                                 gridDim.x);
 }
 
 
@@ -2138,21 +2168,29 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
         }
         return;
     }
-    const int dim3d = prob->kind == STF_KIND_STENCIL3D;
     const double* ph = (prob->alpha != 0.0) ? phi : nullptr;
-    if (dtype == STF_F64)
-        k_grad_stencil<double, double><<<grid_rows(n), 256, 0, s>>>(
-            (const double*)X, (double*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
-            dim3d, prob->v, ph, prob->alpha, st);
-    else if (Xm)
-        // float32 G of the float64 master iterate, stencil evaluated in float64
-        k_grad_stencil<double, float><<<grid_rows(n), 256, 0, s>>>(
-            Xm, (float*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2], dim3d, prob->v,
-            ph, prob->alpha, st);
-    else
-        k_grad_stencil<float, float><<<grid_rows(n), 256, 0, s>>>(
-            (const float*)X, (float*)G, n, p, prob->grid[0], prob->grid[1], prob->grid[2],
-            dim3d, prob->v, ph, prob->alpha, st);
+    const int nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
+    const unsigned g = grid_rows(n);
+#define STF_GRAD(TI, TO, ND, XP)                                                             \
+    k_grad_stencil<TI, TO, ND><<<g, 256, 0, s>>>((const TI*)(XP), (TO*)G, n, p, nx, ny, nz, \
+                                                 prob->v, ph, prob->alpha, st)
+    if (prob->kind == STF_KIND_STENCIL3D) {
+        if (dtype == STF_F64)
+            STF_GRAD(double, double, 6, X);
+        else if (Xm)
+            // float32 G of the float64 master iterate, stencil evaluated in float64
+            STF_GRAD(double, float, 6, Xm);
+        else
+            STF_GRAD(float, float, 6, X);
+    } else {
+        if (dtype == STF_F64)
+            STF_GRAD(double, double, 2, X);
+        else if (Xm)
+            STF_GRAD(double, float, 2, Xm);
+        else
+            STF_GRAD(float, float, 2, X);
+    }
+#undef STF_GRAD
 }
 
 template <typename T>
@@ -2182,7 +2220,7 @@ static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n,
 
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, const void* G,
                  int64_t n, int p, double* part, double* S, double* W, const DevState* st,
-                 hipStream_t s) {
+                 hipStream_t s, hipEvent_t after_main) {
     // tiles: the upper blocks of S (when S is wanted) followed by all blocks of W
     const int nst = S ? gp.n_s_tiles : 0;
     const int n_tiles = nst + (W ? gp.nb * gp.nb : 0);
@@ -2205,6 +2243,7 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
     } else {
         gram_dispatch<float>(g2, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles);
     }
+    if (after_main) (void)hipEventRecord(after_main, s);
     const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
     k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
                                                                  gp.nb, nst, p, S, W, st);
@@ -2225,13 +2264,18 @@ void launch_kkt_products(const double* S, const double* ML, const double* Bm, do
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X, void* G,
                      const void* Gprev, const double* ML, const double* Psi, const double* nu,
                      int64_t n, int p, double* part_col, double* part_scal,
-                     const DevParams* prm, DevState* st, int mode, void* mix, hipStream_t s) {
+                     const DevParams* prm, DevState* st, int mode, void* mix, hipStream_t s,
+                     hipEvent_t before_main) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
+    auto mark = [&]() {
+        if (before_main) (void)hipEventRecord(before_main, s);
+    };
     if (dtype == STF_F32 && precision == STF_PREC_MIXED && mode == RES_ITERATE) {
         const int prow = rp.ncb * 64, pk = (p + 31) / 32 * 32;
         __bf16* MS = (__bf16*)mix;
         const unsigned gs = (unsigned)(((size_t)prow * pk + 255) / 256);
         k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
+        mark();
         if (rp.tile == 256) {
             // M_L slice resident in LDS (plans of this shape only exist for pk <= 384)
             if (pk <= 128)
@@ -2256,6 +2300,7 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     }
     // iterations evaluate the stop test by the p x p identity (no second product)
     const bool kkt_prod = (mode == RES_KKT_ONLY);
+    mark();
     if (dtype == STF_F64) {
         if (kkt_prod)
             k_residual<double, false, true><<<nwg, 256, 0, s>>>(
