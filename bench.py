@@ -145,22 +145,40 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True):
 
 KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_residual",
                 "update": "k_update", "hartree": "k_dst_axis"}
+# the device function that does the work of each timed kernel, per form
+KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gram_lds",
+               ("fp64", "grad"): "body_grad_stencil", ("fp64", "update"): "body_update",
+               ("mixed", "residual"): "body_residual_bf6_lds",
+               ("mixed", "gram"): "body_gram_bf3_lds", ("mixed", "grad"): "body_grad_stencil",
+               ("mixed", "update"): "body_update"}
+
+
+def body_digest(name):
+    """sha256 of a device function's source text in the kernel file (from its
+    definition line to the closing brace in column 0)."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1810_03930_amd", "csrc", "stf_kernels.hip")
+    with open(src) as f:
+        text = f.read()
+    m = re.search(r"^__device__ __forceinline__ void " + re.escape(name) + r"\(", text, re.M)
+    if not m:
+        return None
+    end = text.find("\n}\n", m.start())
+    return hashlib.sha256(text[m.start():end + 3].encode()).hexdigest()
 
 
 def traffic_for(kernel, precision):
-    """Measured HBM bytes per launch from committed counter runs, if they were
-    taken on the current kernel source (else None)."""
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter
+    runs, when they were taken on the kernel's current source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    body = KERNEL_BODY.get((precision, kernel))
+    if not body or not os.path.exists(path):
         return None
-    import hashlib
     with open(path) as f:
         tab = json.load(f)
-    src = os.path.join(ROOT, "paper_1810_03930_amd", "csrc", "stf_kernels.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
     ent = tab.get(f"{precision}/{kernel}")
-    if not ent or ent.get("source_sha256") != digest:
+    if not ent or ent.get("body") != body or ent.get("source_sha256") != body_digest(body):
         return None
     return ent.get("bytes_per_launch")
 
