@@ -288,6 +288,54 @@ int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* L
                    void* ws, size_t ws_bytes, int32_t* cg_iters, double* cg_relres,
                    hipStream_t stream);
 
+/* ---- batched solve: many independent problems of uneven n and p --------
+ * Each problem runs the iteration of stf_solve (Algorithms 2 / 3 with the
+ * step-size rules of Section 5.1) on its own; the library advances all of them
+ * together, every stage of an iteration being one grouped launch over the
+ * whole batch, captured in a HIP graph (opt->use_graph) and replayed.  A
+ * problem that meets its stop test stops; the others go on.
+ *   nprob  : number of problems (>= 1)
+ *   probs  : host array of nprob descriptors; kind STF_KIND_STENCIL1D only
+ *            (STF_E_UNSUPPORTED otherwise)
+ *   X      : host array of nprob device pointers, each n_b x p_b row-major,
+ *            float64 (STF_PREC_FP64) or float32 (STF_PREC_FP32 / MIXED);
+ *            X^0 on entry, the returned iterate on exit (CholeskyQR2'd when
+ *            opt->orth_final)
+ *   opts   : host array of nprob option sets, one per problem (beta, eta0,
+ *            tol, step rule, variant, max_iter may differ); precision must
+ *            be the same for all, use_graph and check_every are taken from
+ *            opts[0]; history is ignored; switch_tol must be 0; MIXED needs
+ *            p <= 384
+ *   ws     : device workspace of ws_bytes >= stf_batched_workspace_size()
+ *   res    : host array of nprob results (ms_loop / ms_orth: the whole batch)
+ * Returns the lowest per-problem status: STF_OK when every problem converged,
+ * STF_MAX_ITER when some reached max_iter, else the first STF_E_* met. */
+size_t stf_batched_workspace_size(int32_t nprob, const stf_problem* probs,
+                                  const stf_options* opts);
+int stf_solve_batched(int32_t nprob, const stf_problem* probs, void* const* X,
+                      const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                      hipStream_t stream);
+/* The same with every variant = STF_PCAL. */
+int pcal_solve_batched(int32_t nprob, const stf_problem* probs, void* const* X,
+                       const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                       hipStream_t stream);
+/* stf_solve_batched with explicit batch-wide workgroup budgets of the Gram
+ * pass and of the residual pass (<= 0: defaults), which set every problem's
+ * split-K chunk count and residual row blocks in proportion to its n p^2;
+ * ms_per_iter (host, may be NULL) receives the loop time per iteration. */
+int stf_solve_batched_ex(int32_t nprob, const stf_problem* probs, void* const* X,
+                         const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                         int32_t budget_gram, int32_t budget_res, double* ms_per_iter,
+                         hipStream_t stream);
+/* Autotuner of the two budgets: times `iters` iterations of the batch for each
+ * candidate pair and returns the fastest in *best_gram / *best_res.  The
+ * iterations are real: X is advanced by 9 * iters iterations (reload X^0
+ * before solving). */
+int stf_batched_tune(int32_t nprob, const stf_problem* probs, void* const* X,
+                     const stf_options* opts, void* ws, size_t ws_bytes, int32_t iters,
+                     int32_t* best_gram, int32_t* best_res, double* best_ms_per_iter,
+                     hipStream_t stream);
+
 /* Human-readable name of a return code (static string). */
 const char* stf_strerror(int code);
 

@@ -103,6 +103,15 @@ SIGNATURES = {
     "pcal_adjoint_v": (ctypes.c_int, [_P(StfProblem), _VP, _VP, _VP, _VP, ctypes.c_double,
                                       ctypes.c_int32, _VP, _SZ, _P(ctypes.c_int32),
                                       _P(ctypes.c_double), _VP]),
+    "stf_batched_workspace_size": (_SZ, [ctypes.c_int32, _VP, _VP]),
+    "stf_solve_batched": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
+    "pcal_solve_batched": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
+    "stf_solve_batched_ex": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ,
+                                            _VP, ctypes.c_int32, ctypes.c_int32,
+                                            _P(ctypes.c_double), _VP]),
+    "stf_batched_tune": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ,
+                                        ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                        _P(ctypes.c_double), _VP]),
     "stf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stf_version": (ctypes.c_char_p, []),
 }

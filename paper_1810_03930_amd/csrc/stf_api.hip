@@ -17,14 +17,13 @@ namespace stf {
 
 int elem_size(int dtype) { return dtype == STF_F64 ? 8 : 4; }
 
-GramPlan make_gram_plan(int64_t n, int p) {
+GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg) {
     GramPlan g;
     g.wm = (p <= 32) ? 1 : (p <= 64 ? 2 : 4);
     g.bt = 32 * g.wm;
     g.nb = (p + g.bt - 1) / g.bt;
     g.n_s_tiles = g.nb * (g.nb + 1) / 2;
     g.n_tiles = g.n_s_tiles + g.nb * g.nb;
-    const int64_t target_wg = 1024;
     int64_t nch = (target_wg + g.n_tiles - 1) / g.n_tiles;
     const int64_t max_ch = std::max<int64_t>(1, n / 256);
     nch = std::min(nch, max_ch);
@@ -36,7 +35,7 @@ GramPlan make_gram_plan(int64_t n, int p) {
     return g;
 }
 
-ResPlan make_res_plan(int64_t n, int p, int tile) {
+ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg) {
     ResPlan r;
     r.tile = tile;
     if (tile == 256) {
@@ -48,21 +47,21 @@ ResPlan make_res_plan(int64_t n, int p, int tile) {
             r.nrb = 0;
             return r;
         }
-        int64_t nrb = (256 + r.ncb - 1) / r.ncb;
+        int64_t nrb = ((target_wg > 0 ? target_wg : 256) + r.ncb - 1) / r.ncb;
         nrb = std::min<int64_t>(nrb, r.nrt);
         r.nrb = (int)std::max<int64_t>(nrb, 1);
         return r;
     }
     r.ncb = (p + tile - 1) / tile;
     r.nrt = (n + tile - 1) / tile;
-    const int64_t target = (tile == 128) ? 1024 : 2048;
+    const int64_t target = target_wg > 0 ? target_wg : ((tile == 128) ? 1024 : 2048);
     int64_t nrb = (target + r.ncb - 1) / r.ncb;
     nrb = std::min<int64_t>(nrb, r.nrt);
     r.nrb = (int)std::max<int64_t>(nrb, 1);
     return r;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout make_layout(const stf_problem* prob, int precision) {
     Layout L;
@@ -137,13 +136,8 @@ Layout make_layout(const stf_problem* prob, int precision) {
 }
 
 // ------------------------------------------------------------ helpers ----
-struct Ws {
-    char* base;
-    Layout L;
-    template <typename T> T* at(size_t o) const { return (T*)(base + o); }
-};
 
-static int check_problem(const stf_problem* prob) {
+int check_problem(const stf_problem* prob) {
     if (!prob) return STF_E_INVALID;
     if (prob->p <= 0 || prob->p > 1024) return STF_E_INVALID;
     if (prob->n < 2 * (int64_t)prob->p) return STF_E_INVALID;
@@ -165,7 +159,7 @@ static int check_problem(const stf_problem* prob) {
     return STF_OK;
 }
 
-static bool has_hartree(const stf_problem* prob) {
+bool has_hartree(const stf_problem* prob) {
     return prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
 }
 
@@ -174,7 +168,7 @@ static bool has_hartree(const stf_problem* prob) {
         if ((x) != hipSuccess) return STF_E_HIP;   \
     } while (0)
 
-static int last_launch() { return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP; }
+int last_launch() { return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP; }
 
 // G = grad f(X) using the workspace's rho / phi (no device state).
 static int enqueue_gradient(const stf_problem* prob, const Ws& w, int dtype, const void* X,
@@ -189,7 +183,7 @@ static int enqueue_gradient(const stf_problem* prob, const Ws& w, int dtype, con
 }
 
 // In-place CholeskyQR2 of a float64 X using tmp (n x p float64).
-static int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp,
+int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp,
                            DevState* st, hipStream_t s) {
     const int64_t n = prob->n;
     const int p = prob->p;
@@ -207,7 +201,7 @@ static int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, doub
 }
 
 // f, KKT and feasibility of a float64 X in float64 (G64 is overwritten).
-static int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* G64,
+int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* G64,
                         hipStream_t s) {
     const int64_t n = prob->n;
     const int p = prob->p;

@@ -1,0 +1,552 @@
+// Batched PLAM / PCAL driver (declared in include/stiefel.h): many independent
+// 1D Kohn-Sham-type problems of uneven n and p solved together.
+//
+// Every stage of an iteration is ONE grouped launch over all problems (the
+// Gram pass and the mixed residual pass: one launch per tile-shape bucket);
+// workgroups find their problem through a prefix table, and each problem keeps
+// its own device state, so a converged problem's workgroups return at once.
+// A chunk of iterations is captured once as a HIP graph and replayed; the host
+// reads every problem's state once per chunk and stops when all are done.
+// Tile shapes per problem: the Gram bucket (MFMA tiles per wave) follows p;
+// the number of split-K chunks and residual row blocks follows the problem's
+// share of the batch's n p^2 work, from a batch-wide workgroup budget that
+// stf_batched_tune() can pick by timing.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "stf_internal.h"
+
+namespace stf {
+
+namespace {
+
+constexpr int kGramBudget = 2048;   // default batch-wide Gram workgroups
+constexpr int kResBudget = 2048;    // default batch-wide residual workgroups (tile 128)
+constexpr int kMixBudget = 512;     // default batch-wide mixed residual workgroups (tile 256)
+
+struct Group {
+    std::vector<int32_t> list, off;
+    int key = 0;
+    size_t dev_list = 0, dev_off = 0;  // workspace offsets of the tables
+};
+
+struct BatchPlan {
+    int nprob = 0;
+    int precision = STF_PREC_FP64;
+    int dtype = STF_F64;
+    std::vector<size_t> pbase;      // workspace offset of each problem's share
+    std::vector<Layout> L;          // per-problem single-problem layouts
+    std::vector<GramPlan> gram;     // batched plans
+    std::vector<ResPlan> res;
+    std::vector<int32_t> nblk_rows;
+    std::vector<Group> groups[BS_ROWSQ + 1];
+    size_t desc = 0;                // BDesc[nprob]
+    size_t states = 0;              // DevState[nprob]: gathered device states
+    size_t tables = 0, table_bytes = 0;
+    size_t total = 0;
+};
+
+// opts: host array of nprob option sets, or null (sizes only).
+int batch_check(int32_t nprob, const stf_problem* probs, const stf_options* opts) {
+    if (nprob <= 0 || !probs) return STF_E_INVALID;
+    for (int b = 0; b < nprob; ++b) {
+        const int rc = check_problem(&probs[b]);
+        if (rc) return rc;
+        // the grouped Hartree and gradient passes are the 1D ones
+        if (probs[b].kind != STF_KIND_STENCIL1D) return STF_E_UNSUPPORTED;
+    }
+    if (opts) {
+        const int prec = opts[0].precision;
+        if (prec < STF_PREC_FP64 || prec > STF_PREC_MIXED) return STF_E_INVALID;
+        for (int b = 0; b < nprob; ++b) {
+            const stf_options& o = opts[b];
+            // one storage dtype and kernel set for the whole batch
+            if (o.precision != prec) return STF_E_INVALID;
+            if (o.switch_tol > 0.0) return STF_E_UNSUPPORTED;
+            if (o.variant != STF_PLAM && o.variant != STF_PCAL) return STF_E_INVALID;
+            if (o.mult_rule != STF_MULT_PSI && o.mult_rule != STF_MULT_PSI_PHI)
+                return STF_E_INVALID;
+            if (o.mult_rule == STF_MULT_PSI_PHI && o.variant != STF_PCAL) return STF_E_UNSUPPORTED;
+            if (o.eta_rule < STF_ETA_CONST || o.eta_rule > STF_ETA_ABB) return STF_E_INVALID;
+            if (o.bb_index != STF_BB_STANDARD && o.bb_index != STF_BB_LAGGED) return STF_E_INVALID;
+            if (o.max_iter < 0 || o.kkt_every < 1 || o.check_every < 1) return STF_E_INVALID;
+            if (!(o.eta0 > 0.0) || !(o.tol >= 0.0) || !isfinite(o.beta)) return STF_E_INVALID;
+            if (o.eta_rule == STF_ETA_CONST && !(o.eta_const > 0.0)) return STF_E_INVALID;
+            if (prec == STF_PREC_MIXED && (probs[b].p + 31) / 32 * 32 > 384)
+                return STF_E_UNSUPPORTED;
+        }
+    }
+    return STF_OK;
+}
+
+// Shapes and workspace of a batch.  budget_* <= 0 selects the defaults.
+BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision,
+                          int budget_gram, int budget_res) {
+    BatchPlan P;
+    P.nprob = nprob;
+    P.precision = precision;
+    P.dtype = (precision == STF_PREC_FP64) ? STF_F64 : STF_F32;
+    const bool mixed = precision == STF_PREC_MIXED;
+    const int bg = budget_gram > 0 ? budget_gram : kGramBudget;
+    const int br = budget_res > 0 ? budget_res : (mixed ? kMixBudget : kResBudget);
+    double wsum = 0.0;
+    for (int b = 0; b < nprob; ++b) wsum += (double)probs[b].n * probs[b].p * probs[b].p;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    P.desc = take(sizeof(BDesc) * (size_t)nprob);
+    P.states = take(sizeof(DevState) * (size_t)nprob);
+    P.L.resize(nprob);
+    P.gram.resize(nprob);
+    P.res.resize(nprob);
+    P.nblk_rows.resize(nprob);
+    P.pbase.resize(nprob);
+    for (int b = 0; b < nprob; ++b) {
+        const stf_problem& pr = probs[b];
+        const double share = (double)pr.n * pr.p * pr.p / wsum;
+        P.L[b] = make_layout(&pr, precision);
+        // batched plans never exceed the single-problem ones the layout is sized for
+        const GramPlan g0 = make_gram_plan(pr.n, pr.p);
+        const int64_t tg = std::max<int64_t>(g0.n_tiles, (int64_t)llround(bg * share));
+        P.gram[b] = make_gram_plan(pr.n, pr.p, std::min<int64_t>(tg, 1024));
+        if (mixed) {
+            const ResPlan r0 = make_res_plan(pr.n, pr.p, 256);
+            const int64_t tr = std::max<int64_t>(r0.ncb, (int64_t)llround(br * share));
+            P.res[b] = make_res_plan(pr.n, pr.p, 256, std::min<int64_t>(tr, 256));
+        } else {
+            const ResPlan r0 = make_res_plan(pr.n, pr.p, 128);
+            const int64_t tr = std::max<int64_t>(r0.ncb, (int64_t)llround(br * share));
+            P.res[b] = make_res_plan(pr.n, pr.p, 128, std::min<int64_t>(tr, 1024));
+        }
+        const int64_t rows4 = std::max<int64_t>(1, (pr.n + 3) / 4);
+        const int64_t want = std::max<int64_t>(1, ((int64_t)pr.n * pr.p + 8191) / 8192);
+        P.nblk_rows[b] = (int32_t)std::min<int64_t>(std::min<int64_t>(rows4, want), 65536);
+    }
+    // grouped-launch tables
+    auto add = [&](int stage, int key, const std::vector<int>& members,
+                   const std::vector<int32_t>& wgs) {
+        Group g;
+        g.key = key;
+        g.off.push_back(0);
+        for (size_t i = 0; i < members.size(); ++i) {
+            if (wgs[i] <= 0) continue;
+            g.list.push_back(members[i]);
+            g.off.push_back(g.off.back() + wgs[i]);
+        }
+        if (!g.list.empty()) P.groups[stage].push_back(g);
+    };
+    std::vector<int> all(nprob), hart;
+    std::iota(all.begin(), all.end(), 0);
+    for (int b = 0; b < nprob; ++b)
+        if (probs[b].alpha != 0.0) hart.push_back(b);
+    auto wg_of = [&](const std::vector<int>& m, auto f) {
+        std::vector<int32_t> w;
+        for (int b : m) w.push_back((int32_t)f(b));
+        return w;
+    };
+    add(BS_HARTREE, 0, hart, wg_of(hart, [&](int) { return 1; }));
+    add(BS_ROWSQ, 0, hart, wg_of(hart, [&](int b) { return P.nblk_rows[b]; }));
+    add(BS_GRAD, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
+    for (int wm : {1, 2, 4}) {
+        std::vector<int> m;
+        for (int b = 0; b < nprob; ++b)
+            if (P.gram[b].wm == wm) m.push_back(b);
+        add(BS_GRAM, wm, m, wg_of(m, [&](int b) { return P.gram[b].n_tiles * P.gram[b].nchunks; }));
+    }
+    add(BS_REDUCE, 0, all, wg_of(all, [&](int b) {
+            const GramPlan& g = P.gram[b];
+            return ((int64_t)g.n_tiles * g.bt * g.bt + 255) / 256;
+        }));
+    add(BS_STAGE1, 0, all, wg_of(all, [&](int b) { return probs[b].p; }));
+    add(BS_PPGEMM, 0, all, wg_of(all, [&](int b) {
+            const int t = (probs[b].p + 15) / 16;
+            return 2 * t * t;
+        }));
+    if (mixed) {
+        add(BS_SPLIT, 0, all, wg_of(all, [&](int b) {
+                const int64_t prow = (int64_t)P.res[b].ncb * 64, pk = (probs[b].p + 31) / 32 * 32;
+                return (prow * pk + 255) / 256;
+            }));
+        for (int pkmax : {128, 256, 384}) {
+            std::vector<int> m;
+            for (int b = 0; b < nprob; ++b) {
+                const int pk = (probs[b].p + 31) / 32 * 32;
+                const int key = pk <= 128 ? 128 : (pk <= 256 ? 256 : 384);
+                if (key == pkmax) m.push_back(b);
+            }
+            add(BS_RESID, pkmax, m, wg_of(m, [&](int b) { return P.res[b].nrb * P.res[b].ncb; }));
+        }
+    } else {
+        add(BS_RESID, 0, all, wg_of(all, [&](int b) { return P.res[b].nrb * P.res[b].ncb; }));
+    }
+    add(BS_COLRED, 0, all, wg_of(all, [&](int b) { return (2 * probs[b].p + 31) / 32; }));
+    add(BS_STAGE2, 0, all, wg_of(all, [&](int) { return 1; }));
+    add(BS_UPDATE, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
+    // table storage
+    P.tables = off;
+    size_t tb = 0;
+    for (auto& gs : P.groups)
+        for (auto& g : gs) {
+            g.dev_list = P.tables + tb;
+            tb += g.list.size() * 4;
+            g.dev_off = P.tables + tb;
+            tb += g.off.size() * 4;
+        }
+    P.table_bytes = tb;
+    off = align256(P.tables + tb);
+    for (int b = 0; b < nprob; ++b) P.pbase[b] = take(P.L[b].total);
+    P.total = off;
+    return P;
+}
+
+void enqueue_batched_iteration(const BatchPlan& P, char* ws, int parity, hipStream_t s) {
+    const BDesc* d = (const BDesc*)(ws + P.desc);
+    auto run = [&](int stage) {
+        for (const Group& g : P.groups[stage]) {
+            BGroup bg;
+            bg.list = (const int32_t*)(ws + g.dev_list);
+            bg.off = (const int32_t*)(ws + g.dev_off);
+            bg.cnt = (int32_t)g.list.size();
+            bg.total = g.off.back();
+            launch_batched(stage, P.dtype, P.precision, g.key, d, bg, parity, s);
+        }
+    };
+    run(BS_HARTREE);
+    run(BS_GRAD);
+    run(BS_GRAM);
+    run(BS_REDUCE);
+    run(BS_STAGE1);
+    run(BS_PPGEMM);
+    if (P.precision == STF_PREC_MIXED) run(BS_SPLIT);
+    run(BS_RESID);
+    run(BS_COLRED);
+    run(BS_STAGE2);
+    run(BS_UPDATE);
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return STF_E_HIP;   \
+    } while (0)
+
+// Host copies of the per-problem descriptors and tables, and device parameters.
+int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
+                const stf_options* opts, char* ws, std::vector<BDesc>& hd,
+                std::vector<int32_t>& htab, std::vector<DevParams>& hp, hipStream_t s) {
+    hd.resize(P.nprob);
+    for (int b = 0; b < P.nprob; ++b) {
+        const Layout& L = P.L[b];
+        char* base = ws + P.pbase[b];
+        auto at = [&](size_t o) { return (double*)(base + o); };
+        BDesc& d = hd[b];
+        memset(&d, 0, sizeof(d));
+        d.n = probs[b].n;
+        d.p = probs[b].p;
+        d.alpha = probs[b].alpha;
+        d.v = probs[b].v;
+        d.X = X[b];
+        d.Xm = (P.dtype == STF_F32) ? at(L.x64) : nullptr;
+        d.g[0] = base + L.g[0];
+        d.g[1] = base + L.g[1];
+        d.rho = at(L.rho);
+        d.phi = at(L.phi);
+        d.S = at(L.S);
+        d.W = at(L.W);
+        d.Psi = at(L.Psi);
+        d.ML = at(L.ML);
+        d.Bm = at(L.Bm);
+        d.T1 = at(L.T1);
+        d.T2 = at(L.T2);
+        d.fpart = at(L.fpart);
+        d.nu = at(L.nu);
+        d.colxg = at(L.colxg);
+        d.colgg = at(L.colgg);
+        d.gram_part = at(L.gram_part);
+        d.res_col = at(L.res_col);
+        d.res_scal = at(L.res_scal);
+        d.mix = (__bf16*)(base + L.mix);
+        d.st = (DevState*)(base + L.state);
+        d.prm = (DevParams*)(base + L.params);
+        d.gram = P.gram[b];
+        d.res = P.res[b];
+        d.nblk_rows = P.nblk_rows[b];
+    }
+    HIPCHK(hipMemcpyAsync(ws + P.desc, hd.data(), sizeof(BDesc) * hd.size(),
+                          hipMemcpyHostToDevice, s));
+    htab.assign(P.table_bytes / 4, 0);
+    for (const auto& gs : P.groups)
+        for (const auto& g : gs) {
+            memcpy((char*)htab.data() + (g.dev_list - P.tables), g.list.data(), g.list.size() * 4);
+            memcpy((char*)htab.data() + (g.dev_off - P.tables), g.off.data(), g.off.size() * 4);
+        }
+    if (P.table_bytes)
+        HIPCHK(hipMemcpyAsync(ws + P.tables, htab.data(), P.table_bytes, hipMemcpyHostToDevice,
+                              s));
+    hp.assign(P.nprob, DevParams{});
+    for (int b = 0; b < P.nprob; ++b) {
+        const stf_options* opt = &opts[b];
+        DevParams& q = hp[b];
+        memset(&q, 0, sizeof(q));
+        q.beta = opt->beta;
+        q.eta0 = opt->eta0;
+        q.eta_const = opt->eta_const;
+        q.tol = opt->tol;
+        q.feas_blowup = opt->feas_blowup > 0.0 ? opt->feas_blowup : INFINITY;
+        q.variant = opt->variant;
+        q.mult_rule = opt->mult_rule;
+        q.eta_rule = opt->eta_rule;
+        q.bb_index = opt->bb_index;
+        q.max_iter = opt->max_iter;
+        q.kkt_every = opt->kkt_every;
+        q.kkt_identity = 1;
+        q.switch_tol = 0.0;
+        q.history = nullptr;
+        HIPCHK(hipMemcpyAsync(hd[b].prm, &q, sizeof(q), hipMemcpyHostToDevice, s));
+        launch_init_state(hd[b].st, s);
+        if (hd[b].Xm)
+            launch_convert(STF_F64, X[b], STF_F32, hd[b].Xm, (size_t)hd[b].n * hd[b].p, s);
+    }
+    // row sums of squares of X^0 for the first Hartree solve
+    {
+        const char* w = ws;
+        for (const Group& g : P.groups[BS_ROWSQ]) {
+            BGroup bg;
+            bg.list = (const int32_t*)(w + g.dev_list);
+            bg.off = (const int32_t*)(w + g.dev_off);
+            bg.cnt = (int32_t)g.list.size();
+            bg.total = g.off.back();
+            launch_batched(BS_ROWSQ, P.dtype, P.precision, 0, (const BDesc*)(ws + P.desc), bg,
+                           0, s);
+        }
+    }
+    // the host arrays are read by the copies above: finish them before returning
+    HIPCHK(hipStreamSynchronize(s));
+    return last_launch();
+}
+
+int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
+                 const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                 hipStream_t s, int budget_gram, int budget_res, double* ms_per_iter) {
+    if (!opts) return STF_E_INVALID;
+    int rc = batch_check(nprob, probs, opts);
+    if (rc) return rc;
+    if (!X || !ws || !res) return STF_E_INVALID;
+    for (int b = 0; b < nprob; ++b)
+        if (!X[b]) return STF_E_INVALID;
+    // loop-level settings come from the first option set
+    const stf_options* opt = &opts[0];
+    const BatchPlan P = make_batch_plan(nprob, probs, opt->precision, budget_gram, budget_res);
+    if (ws_bytes < P.total) return STF_E_WORKSPACE;
+    char* w = (char*)ws;
+    for (int b = 0; b < nprob; ++b) memset(&res[b], 0, sizeof(stf_result));
+    std::vector<BDesc> hd;
+    std::vector<int32_t> htab;
+    std::vector<DevParams> hpv;
+    if ((rc = setup_batch(P, probs, X, opts, w, hd, htab, hpv, s))) return rc;
+
+    hipEvent_t e0, e1, e2;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventCreate(&e2));
+    HIPCHK(hipEventRecord(e0, s));
+    int chunk = std::max(1, opt->check_every);
+    if (opt->use_graph && (chunk & 1)) chunk += 1;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (opt->use_graph && s != nullptr) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < chunk; ++i) enqueue_batched_iteration(P, w, i & 1, s);
+        if (hipStreamEndCapture(s, &graph) != hipSuccess) return STF_E_HIP;
+        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return STF_E_HIP;
+        }
+    }
+    std::vector<DevState> hs(nprob);
+    int64_t limit = 1;
+    for (int b = 0; b < nprob; ++b) limit = std::max<int64_t>(limit, (int64_t)opts[b].max_iter + 1);
+    int64_t enq = 0;
+    int err = 0;
+    int64_t iters_run = 0;
+    while (true) {
+        if (gexec) {
+            if (hipGraphLaunch(gexec, s) != hipSuccess) { err = 1; break; }
+            enq += chunk;
+        } else {
+            const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
+            for (int i = 0; i < todo; ++i) enqueue_batched_iteration(P, w, (int)((enq + i) & 1), s);
+            enq += todo;
+            if (last_launch()) { err = 1; break; }
+        }
+        bool all = true;
+        launch_gather_states((const BDesc*)(w + P.desc), nprob, (DevState*)(w + P.states), s);
+        if (hipMemcpyAsync(hs.data(), w + P.states, sizeof(DevState) * (size_t)nprob,
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            err = 1;
+            break;
+        }
+        int64_t mx = 0;
+        for (int b = 0; b < nprob; ++b) {
+            all = all && hs[b].done;
+            mx = std::max<int64_t>(mx, hs[b].done ? hs[b].final_iter : hs[b].iter);
+        }
+        iters_run = mx;
+        if (all) break;
+        if (enq > limit + 2 * chunk) { err = 1; break; }
+    }
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    if (err) return STF_E_HIP;
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms_loop = 0.f;
+    hipEventElapsedTime(&ms_loop, e0, e1);
+    if (ms_per_iter) *ms_per_iter = iters_run > 0 ? ms_loop / (double)iters_run : 0.0;
+
+    // per problem: CholeskyQR2 and the float64 evaluation, as in a single solve
+    int worst = STF_OK;
+    for (int b = 0; b < nprob; ++b) {
+        stf_result& r = res[b];
+        r.status = hs[b].status;
+        r.iters = hs[b].final_iter;
+        r.kkt0 = hs[b].kkt0;
+        r.eta_last = hs[b].eta;
+        r.ms_loop = ms_loop;
+        r.switch_iter = -1;
+        if (hs[b].status == STF_E_DIVERGED) {
+            r.kkt_abs = r.kkt_rel = r.feas = r.fval = NAN;
+            worst = STF_E_DIVERGED;
+            continue;
+        }
+        Ws pw;
+        pw.base = w + P.pbase[b];
+        pw.L = P.L[b];
+        const int64_t n = probs[b].n;
+        const int p = probs[b].p;
+        double* Xd = (P.dtype == STF_F64) ? (double*)X[b] : hd[b].Xm;
+        double* tmp = (P.dtype == STF_F64) ? pw.at<double>(pw.L.g[1]) : pw.at<double>(pw.L.g64);
+        DevState* st_eval = pw.at<DevState>(pw.L.state_eval);
+        launch_init_state(st_eval, s);
+        const bool orth = opts[b].orth_final != 0;
+        if (orth && (rc = enqueue_cholqr2(&probs[b], pw, Xd, tmp, st_eval, s))) return rc;
+        DevState he;
+        HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (orth && he.info != 0) {
+            r.status = STF_E_CHOLESKY;
+            worst = std::min(worst, (int)STF_E_CHOLESKY);
+            continue;
+        }
+        double* G64 = (P.dtype == STF_F64) ? pw.at<double>(pw.L.g[0]) : pw.at<double>(pw.L.g64);
+        if ((rc = enqueue_eval(&probs[b], pw, Xd, G64, s))) return rc;
+        if (P.dtype == STF_F32) launch_convert(STF_F32, Xd, STF_F64, X[b], (size_t)n * p, s);
+        HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        r.fval = he.red[0];
+        r.kkt_abs = he.red[1];
+        r.feas = he.red[2];
+        r.kkt_rel = (hs[b].kkt0 > 0.0) ? he.red[1] / hs[b].kkt0 : 0.0;
+        if (r.status == STF_MAX_ITER && worst == STF_OK) worst = STF_MAX_ITER;
+    }
+    HIPCHK(hipEventRecord(e2, s));
+    HIPCHK(hipEventSynchronize(e2));
+    float ms_orth = 0.f;
+    hipEventElapsedTime(&ms_orth, e1, e2);
+    for (int b = 0; b < nprob; ++b) res[b].ms_orth = ms_orth;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipEventDestroy(e2);
+    if ((rc = last_launch())) return rc;
+    return worst;
+}
+
+}  // namespace
+
+}  // namespace stf
+
+using namespace stf;
+
+extern "C" {
+
+size_t stf_batched_workspace_size(int32_t nprob, const stf_problem* probs,
+                                  const stf_options* opts) {
+    if (batch_check(nprob, probs, opts) != STF_OK) return 0;
+    if (opts) return make_batch_plan(nprob, probs, opts[0].precision, 0, 0).total;
+    size_t m = 0;
+    for (int prec : {STF_PREC_FP64, STF_PREC_FP32, STF_PREC_MIXED}) {
+        bool ok = true;
+        if (prec == STF_PREC_MIXED)
+            for (int b = 0; b < nprob; ++b)
+                ok = ok && (probs[b].p + 31) / 32 * 32 <= 384;
+        if (ok) m = std::max(m, make_batch_plan(nprob, probs, prec, 0, 0).total);
+    }
+    return m;
+}
+
+int stf_solve_batched(int32_t nprob, const stf_problem* probs, void* const* X,
+                      const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                      hipStream_t stream) {
+    return batched_impl(nprob, probs, X, opts, ws, ws_bytes, res, stream, 0, 0, nullptr);
+}
+
+int stf_solve_batched_ex(int32_t nprob, const stf_problem* probs, void* const* X,
+                         const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                         int32_t budget_gram, int32_t budget_res, double* ms_per_iter,
+                         hipStream_t stream) {
+    return batched_impl(nprob, probs, X, opts, ws, ws_bytes, res, stream, budget_gram,
+                        budget_res, ms_per_iter);
+}
+
+int stf_batched_tune(int32_t nprob, const stf_problem* probs, void* const* X,
+                     const stf_options* opts, void* ws, size_t ws_bytes, int32_t iters,
+                     int32_t* best_gram, int32_t* best_res, double* best_ms_per_iter,
+                     hipStream_t stream) {
+    if (!opts || !best_gram || !best_res || iters < 1 || nprob <= 0) return STF_E_INVALID;
+    std::vector<stf_options> ov(opts, opts + nprob);
+    for (auto& o : ov) {
+        o.tol = 0.0;
+        o.max_iter = iters;
+        o.orth_final = 0;
+        o.check_every = iters;
+        o.history = nullptr;
+    }
+    std::vector<stf_result> r((size_t)nprob);
+    const bool mixed = opts[0].precision == STF_PREC_MIXED;
+    const int gram_c[] = {1024, 2048, 4096};
+    const int res_c[] = {mixed ? 256 : 1024, mixed ? 512 : 2048, mixed ? 1024 : 4096};
+    double best = INFINITY;
+    for (int bg : gram_c)
+        for (int br : res_c) {
+            double ms = 0.0;
+            // every candidate starts from the iterate the previous one left: same work per iteration
+            const int rc = batched_impl(nprob, probs, X, ov.data(), ws, ws_bytes, r.data(),
+                                        stream, bg, br, &ms);
+            if (rc < 0) return rc;
+            if (ms > 0.0 && ms < best) {
+                best = ms;
+                *best_gram = bg;
+                *best_res = br;
+            }
+        }
+    if (best_ms_per_iter) *best_ms_per_iter = best;
+    return STF_OK;
+}
+
+int pcal_solve_batched(int32_t nprob, const stf_problem* probs, void* const* X,
+                       const stf_options* opts, void* ws, size_t ws_bytes, stf_result* res,
+                       hipStream_t stream) {
+    if (!opts || nprob <= 0) return STF_E_INVALID;
+    std::vector<stf_options> ov(opts, opts + nprob);
+    for (auto& o : ov) o.variant = STF_PCAL;
+    return batched_impl(nprob, probs, X, ov.data(), ws, ws_bytes, res, stream, 0, 0, nullptr);
+}
+
+}  // extern "C"

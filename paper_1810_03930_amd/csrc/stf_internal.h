@@ -86,10 +86,68 @@ struct Layout {
     const ResPlan& mixed_plan() const { return resmx.nrb > 0 ? resmx : res64; }
 };
 
+// One problem of a batched solve, as the grouped kernels see it: its sizes,
+// operator data, plans and the addresses inside its share of the workspace.
+struct BDesc {
+    int64_t n;
+    int32_t p, pad0;
+    double alpha;
+    const double* v;
+    void* X;           // iterate in the storage dtype (caller's buffer)
+    double* Xm;        // float64 master iterate (float32 forms), else null
+    void* g[2];        // G / gradL double buffer
+    double *rho, *phi, *S, *W, *Psi, *ML, *Bm, *T1, *T2, *fpart;
+    double *nu, *colxg, *colgg, *gram_part, *res_col, *res_scal;
+    __bf16* mix;
+    DevState* st;
+    DevParams* prm;
+    GramPlan gram;
+    ResPlan res;
+    int32_t nblk_rows;  // workgroups of the row-parallel passes (gradient, update)
+    int32_t pad1;
+};
+
+// A grouped launch: workgroups [off[j], off[j+1]) belong to problem list[j].
+struct BGroup {
+    const int32_t* list;
+    const int32_t* off;
+    int32_t cnt;
+    int32_t total;     // off[cnt]
+};
+
+// Grouped launches of one batched iteration stage (stf_kernels.hip).
+enum BStage {
+    BS_HARTREE = 0, BS_GRAD, BS_GRAM, BS_REDUCE, BS_STAGE1, BS_PPGEMM, BS_SPLIT, BS_RESID,
+    BS_COLRED, BS_STAGE2, BS_UPDATE, BS_ROWSQ
+};
+void launch_batched(int stage, int dtype, int precision, int variant_key, const BDesc* d,
+                    const BGroup& grp, int parity, hipStream_t s);
+void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t s);
+
 int elem_size(int dtype);
-GramPlan make_gram_plan(int64_t n, int p);
-ResPlan make_res_plan(int64_t n, int p, int tile);
+// target_wg: workgroups the plan aims at (the single-problem defaults when omitted)
+GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 1024);
+ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
 Layout make_layout(const stf_problem* prob, int precision);
+size_t align256(size_t x);
+
+// A problem's workspace: base address and layout.
+struct Ws {
+    char* base;
+    Layout L;
+    template <typename T> T* at(size_t o) const { return (T*)(base + o); }
+};
+
+// Shared by the single-problem and batched drivers (stf_api.hip).
+int check_problem(const stf_problem* prob);
+bool has_hartree(const stf_problem* prob);
+int last_launch();
+// In-place CholeskyQR2 of a float64 X (tmp: n x p float64 scratch).
+int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp,
+                    DevState* st, hipStream_t s);
+// f, KKT and feasibility of a float64 X into w's evaluation state (G64 overwritten).
+int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* G64,
+                 hipStream_t s);
 
 // ---- launchers (stf_kernels.hip); all enqueue on `s` -----------------------
 void launch_rowsq(int dtype, const void* X, int64_t n, int p, double* rho,

@@ -1742,18 +1742,18 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
 
 // T1 = S M_L and T2 = S B for p x p float64 matrices (blockIdx.z selects),
 // the two products of the float64 KKT identity evaluated in stage 2.
-__global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
-                                                  const double* __restrict__ M1,
-                                                  const double* __restrict__ M2,
-                                                  double* __restrict__ T1,
-                                                  double* __restrict__ T2, int p,
-                                                  const DevState* __restrict__ st) {
+__device__ __forceinline__ void body_pp_gemm2(const double* __restrict__ S,
+                                              const double* __restrict__ M1,
+                                              const double* __restrict__ M2,
+                                              double* __restrict__ T1, double* __restrict__ T2,
+                                              int p, const DevState* __restrict__ st, int bx,
+                                              int by, int bz) {
     if (st->done) return;
     __shared__ double As[16][17], Bs[16][17];
-    const double* B = blockIdx.z ? M2 : M1;
-    double* C = blockIdx.z ? T2 : T1;
+    const double* B = bz ? M2 : M1;
+    double* C = bz ? T2 : T1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+    const int row = by * 16 + ty, col = bx * 16 + tx;
     double acc = 0.0;
     for (int k0 = 0; k0 < p; k0 += 16) {
         As[ty][tx] = (row < p && k0 + tx < p) ? S[(size_t)row * p + k0 + tx] : 0.0;
@@ -1764,6 +1764,14 @@ __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
         __syncthreads();
     }
     if (row < p && col < p) C[(size_t)row * p + col] = acc;
+}
+__global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
+                                                  const double* __restrict__ M1,
+                                                  const double* __restrict__ M2,
+                                                  double* __restrict__ T1,
+                                                  double* __restrict__ T2, int p,
+                                                  const DevState* __restrict__ st) {
+    body_pp_gemm2(S, M1, M2, T1, T2, p, st, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // -------------------------------------------------------- p x p stage 2 ----
@@ -2080,6 +2088,164 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
     }
 }
 
+// ================================================================ batched ===
+// Grouped launches for many independent problems: one launch per stage covers
+// every problem of a group; workgroup x belongs to the problem whose range
+// [off[j], off[j+1]) contains x and runs that problem's body with its own
+// sizes, plan, buffers and device state (a finished problem's workgroups
+// return at once).  `parity` selects G / gradL^{k-1} in the double buffer:
+// all problems of a batch take their iterations in lockstep.
+
+// Index j of the range [off[j], off[j+1]) holding x (off[0] = 0 <= x < off[cnt]).
+__device__ __forceinline__ int group_find(const int32_t* __restrict__ off, int cnt, int x) {
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+#define STF_BATCH_PROLOGUE                                              \
+    const int j_ = group_find(off, cnt, (int)blockIdx.x);              \
+    const BDesc& d = D[list[j_]];                                      \
+    const int lid_ = (int)blockIdx.x - off[j_];                        \
+    const int nb_ = off[j_ + 1] - off[j_];                             \
+    (void)lid_;                                                        \
+    (void)nb_;
+
+#define STF_BATCH_ARGS                                                              \
+    const BDesc* __restrict__ D, const int32_t* __restrict__ list,                  \
+        const int32_t* __restrict__ off, int cnt, int parity
+
+__global__ __launch_bounds__(1024) void kb_hartree1d(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    if (d.alpha == 0.0) return;
+    body_hartree1d(d.rho, d.phi, d.n, d.st, 0, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_rowsq(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const T* x = d.Xm ? (const T*)d.Xm : (const T*)d.X;
+    body_rowsq<T>(x, d.n, d.p, d.rho, nullptr, lid_, nb_);
+}
+
+// 1D stencil gradient; the float32 forms read the float64 master iterate
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void kb_grad(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const T* x = d.Xm ? (const T*)d.Xm : (const T*)d.X;
+    body_grad_stencil<T, TO, 2>(x, (TO*)d.g[parity], d.n, d.p, (int)d.n, 1, 1, d.v,
+                                d.alpha != 0.0 ? d.phi : nullptr, d.alpha, d.st, lid_, nb_);
+}
+
+template <typename T, int WM>
+__global__ __launch_bounds__(256) void kb_gram(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const GramPlan& g = d.gram;
+    body_gram<T, WM>((const T*)d.X, (const T*)d.g[parity], d.n, d.p, g.nb, g.n_s_tiles,
+                     g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_gram_lds64(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const GramPlan& g = d.gram;
+    body_gram_lds<double>((const double*)d.X, (const double*)d.g[parity], d.n, d.p, g.nb,
+                          g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+}
+
+template <int WM>
+__global__ __launch_bounds__(256) void kb_gram_bf3(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const GramPlan& g = d.gram;
+    body_gram_bf3<WM>((const float*)d.X, (const float*)d.g[parity], d.n, d.p, g.nb,
+                      g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_gram_bf3_lds(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const GramPlan& g = d.gram;
+    body_gram_bf3_lds((const float*)d.X, (const float*)d.g[parity], d.n, d.p, g.nb,
+                      g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_gram_reduce(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const GramPlan& g = d.gram;
+    body_gram_reduce(d.gram_part, g.nchunks, g.n_tiles, g.bt, g.nb, g.n_s_tiles, d.p, d.S, d.W,
+                     d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_stage1(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    body_stage1(d.prm, d.S, d.W, d.Psi, d.ML, d.Bm, d.fpart, d.p, d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_pp_gemm2(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const int t = (d.p + 15) / 16;
+    body_pp_gemm2(d.S, d.ML, d.Bm, d.T1, d.T2, d.p, d.st, lid_ % t, (lid_ / t) % t,
+                  lid_ / (t * t));
+}
+
+__global__ __launch_bounds__(256) void kb_split3(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const int prow = d.res.ncb * 64, pk = (d.p + 31) / 32 * 32;
+    body_split3_t(d.ML, d.mix, d.p, prow, pk, d.st, lid_, nb_);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_residual(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const ResPlan& r = d.res;
+    body_residual<T, false, false>((const T*)d.X, (T*)d.g[parity], (const T*)d.g[parity ^ 1],
+                                   d.ML, d.Psi, d.nu, d.n, d.p, r.nrb, r.ncb, r.nrt, d.res_col,
+                                   d.res_scal, d.prm, d.st, RES_ITERATE, lid_, nb_);
+}
+
+template <int PKMAX>
+__global__ __launch_bounds__(256) void kb_residual_bf6_lds(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    const ResPlan& r = d.res;
+    const int prow = r.ncb * 64, pk = (d.p + 31) / 32 * 32;
+    body_residual_bf6_lds<PKMAX>((const float*)d.X, (float*)d.g[parity],
+                                 (const float*)d.g[parity ^ 1], d.mix, prow, pk, d.nu, d.n,
+                                 d.p, r.nrb, r.ncb, r.nrt, d.res_col, d.res_scal, d.prm, d.st,
+                                 lid_, nb_);
+}
+
+__global__ __launch_bounds__(256) void kb_colreduce(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    body_colreduce(d.res_col, d.res.nrb, d.p, d.colxg, d.colgg, d.st, lid_, nb_);
+}
+
+__global__ __launch_bounds__(1024) void kb_stage2(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.W, d.Bm, d.T1, d.T2, d.fpart,
+                d.colxg, d.colgg, d.nu, d.p, d.st, 0, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_update(STF_BATCH_ARGS) {
+    STF_BATCH_PROLOGUE
+    body_update<T>((T*)d.X, d.Xm, (const T*)d.g[parity], d.n, d.p, d.nu,
+                   d.alpha != 0.0 ? d.rho : nullptr, d.st, lid_, nb_);
+}
+
+#undef STF_BATCH_PROLOGUE
+#undef STF_BATCH_ARGS
+
+// Copy every problem's device state into one array (one read-back per check).
+__global__ void kb_gather_states(const BDesc* __restrict__ D, int nprob,
+                                 DevState* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nprob) out[b] = *D[b].st;
+}
+
 // =================================================================== host ===
 
 static inline unsigned grid_rows(int64_t n) {
@@ -2382,6 +2548,104 @@ void launch_eval_finish(const stf_problem* prob, const double* X, const double* 
     k_dots<<<nd, 256, 0, s>>>(X, G, (size_t)n * p, hart ? rho : nullptr, hart ? phi : nullptr,
                               n, dots);
     k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, S, p, hart ? prob->alpha : 0.0, st);
+}
+
+
+void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t s) {
+    kb_gather_states<<<(nprob + 63) / 64, 64, 0, s>>>(d, nprob, out);
+}
+
+// One grouped launch of a batched stage; variant_key selects the template of
+// the stages that have several (Gram: 1/2/4 = MFMA tiles per wave dimension;
+// mixed residual: PKMAX).  Grid size is grp.total workgroups.
+void launch_batched(int stage, int dtype, int precision, int variant_key, const BDesc* d,
+                    const BGroup& grp, int parity, hipStream_t s) {
+    if (grp.cnt <= 0 || grp.total <= 0) return;
+    const unsigned g = (unsigned)grp.total;
+    const int32_t* L = grp.list;
+    const int32_t* O = grp.off;
+    const int c = grp.cnt;
+    const bool f64 = dtype == STF_F64;
+    const bool mixed = (dtype == STF_F32) && (precision == STF_PREC_MIXED);
+    switch (stage) {
+        case BS_HARTREE:
+            kb_hartree1d<<<g, 1024, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_ROWSQ:
+            // the float32 forms keep their float64 master in Xm: rows of squares in float64
+            kb_rowsq<double><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_GRAD:
+            if (f64)
+                kb_grad<double, double><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            else
+                kb_grad<double, float><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_GRAM:
+            if (mixed) {
+                if (variant_key == 1)
+                    kb_gram_bf3<1><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else if (variant_key == 2)
+                    kb_gram_bf3<2><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else
+                    kb_gram_bf3_lds<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            } else if (f64) {
+                if (variant_key == 1)
+                    kb_gram<double, 1><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else if (variant_key == 2)
+                    kb_gram<double, 2><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else
+                    kb_gram_lds64<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            } else {
+                if (variant_key == 1)
+                    kb_gram<float, 1><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else if (variant_key == 2)
+                    kb_gram<float, 2><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else
+                    kb_gram<float, 4><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            }
+            break;
+        case BS_REDUCE:
+            kb_gram_reduce<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_STAGE1:
+            kb_stage1<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_PPGEMM:
+            kb_pp_gemm2<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_SPLIT:
+            kb_split3<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_RESID:
+            if (mixed) {
+                if (variant_key <= 128)
+                    kb_residual_bf6_lds<128><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else if (variant_key <= 256)
+                    kb_residual_bf6_lds<256><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                else
+                    kb_residual_bf6_lds<384><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            } else if (f64) {
+                kb_residual<double><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            } else {
+                kb_residual<float><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            }
+            break;
+        case BS_COLRED:
+            kb_colreduce<<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_STAGE2:
+            kb_stage2<<<g, 1024, 0, s>>>(d, L, O, c, parity);
+            break;
+        case BS_UPDATE:
+            if (f64)
+                kb_update<double><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            else
+                kb_update<float><<<g, 256, 0, s>>>(d, L, O, c, parity);
+            break;
+        default:
+            break;
+    }
 }
 
 }  // namespace stf

@@ -167,12 +167,98 @@ def solve(dp: DeviceProblem, X: torch.Tensor, opts: SolveOptions,
                        ctypes.c_void_p(_ptr(x64)) if x64 is not None else None,
                        ctypes.c_void_p(_ptr(lam)) if lam is not None else None,
                        ctypes.byref(res), _stream_handle(stream))
-    out = {k: getattr(res, k) for k, _ in L.StfResult._fields_ if k not in ("kernel_ms", "reserved")}
-    out["kernel_ms"] = {name: float(res.kernel_ms[i]) for i, name in enumerate(L.PROF_NAMES)}
+    out = _result_dict(res)
     out["rc"] = rc
     if rc < 0 and rc != L.E_DIVERGED and raise_on_error:
         raise StiefelError(rc, "stf_solve")
     return out, x64, lam
+
+
+def _result_dict(res) -> dict:
+    out = {k: getattr(res, k) for k, _ in L.StfResult._fields_ if k != "kernel_ms"}
+    out["kernel_ms"] = {name: float(res.kernel_ms[i]) for i, name in enumerate(L.PROF_NAMES)}
+    return out
+
+
+def _opt_list(dps, opts):
+    """One SolveOptions per problem (a single one is repeated)."""
+    if isinstance(opts, SolveOptions):
+        return [opts] * len(dps)
+    if len(opts) != len(dps):
+        raise ValueError("one SolveOptions per problem")
+    return list(opts)
+
+
+def _batch_args(dps, Xs, opts):
+    if len(dps) != len(Xs) or not dps:
+        raise ValueError("one X per problem, at least one problem")
+    ol = _opt_list(dps, opts)
+    cps = (L.StfProblem * len(dps))(*[dp.c() for dp in dps])
+    cos = (L.StfOptions * len(dps))(*[o.c() for o in ol])
+    for dp, X, o in zip(dps, Xs, ol):
+        if X.dtype != storage_dtype(o.precision) or not X.is_contiguous() or not X.is_cuda:
+            raise ValueError("each X must be a contiguous device tensor of the iteration dtype")
+        if tuple(X.shape) != (dp.n, dp.p):
+            raise ValueError("an X has the wrong shape")
+    ptrs = (ctypes.c_void_p * len(Xs))(*[X.data_ptr() for X in Xs])
+    return cps, cos, ptrs
+
+
+def _vp(a):
+    return ctypes.cast(a, ctypes.c_void_p)
+
+
+def batched_workspace_size(dps, opts=None) -> int:
+    """Workspace bytes of a batched solve; opts: one SolveOptions, a list, or None."""
+    lib = L.load()
+    cps = (L.StfProblem * len(dps))(*[dp.c() for dp in dps])
+    cos = None if opts is None else (L.StfOptions * len(dps))(
+        *[o.c() for o in _opt_list(dps, opts)])
+    size = lib.stf_batched_workspace_size(len(dps), _vp(cps),
+                                          _vp(cos) if cos is not None else None)
+    if size == 0:
+        raise StiefelError(L.E_INVALID, "stf_batched_workspace_size")
+    return int(size)
+
+
+def solve_batched(dps, Xs, opts, workspace: Optional[torch.Tensor] = None,
+                  budgets=None, stream=None, raise_on_error: bool = True):
+    """Solve many 1D problems together in place on their Xs (stf_solve_batched_ex).
+
+    opts: one SolveOptions for all problems or a list with one per problem.
+    budgets: optional (gram, residual) batch-wide workgroup budgets.
+    Returns (list of result dicts, return code, loop ms per iteration)."""
+    lib = L.load()
+    cps, cos, ptrs = _batch_args(dps, Xs, opts)
+    ws = workspace if workspace is not None else torch.empty(
+        batched_workspace_size(dps, opts), dtype=torch.uint8, device="cuda")
+    res = (L.StfResult * len(dps))()
+    msi = ctypes.c_double(0.0)
+    bg, br = budgets if budgets is not None else (0, 0)
+    rc = lib.stf_solve_batched_ex(len(dps), _vp(cps), _vp(ptrs), _vp(cos),
+                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                  _vp(res), int(bg), int(br), ctypes.byref(msi),
+                                  _stream_handle(stream))
+    if rc < 0 and rc != L.E_DIVERGED and raise_on_error:
+        raise StiefelError(rc, "stf_solve_batched_ex")
+    return [_result_dict(r) for r in res], rc, float(msi.value)
+
+
+def tune_batched(dps, Xs, opts, iters: int = 10, workspace: Optional[torch.Tensor] = None,
+                 stream=None):
+    """Pick the (gram, residual) budgets by timing (stf_batched_tune); Xs are advanced."""
+    lib = L.load()
+    cps, cos, ptrs = _batch_args(dps, Xs, opts)
+    ws = workspace if workspace is not None else torch.empty(
+        batched_workspace_size(dps, opts), dtype=torch.uint8, device="cuda")
+    bg, br, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    rc = lib.stf_batched_tune(len(dps), _vp(cps), _vp(ptrs), _vp(cos),
+                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                              int(iters), ctypes.byref(bg), ctypes.byref(br), ctypes.byref(ms),
+                              _stream_handle(stream))
+    if rc < 0:
+        raise StiefelError(rc, "stf_batched_tune")
+    return (int(bg.value), int(br.value)), float(ms.value)
 
 
 def gradient(dp: DeviceProblem, X: torch.Tensor, workspace=None, stream=None) -> torch.Tensor:

@@ -112,3 +112,37 @@ def test_strerror_and_version():
         assert len(L.strerror(code)) > 5
     assert L.strerror(12345) == "unknown status"
     assert L.load().stf_version().decode().startswith("stiefel")
+
+
+def _valid_options(prec=L.PREC_FP64):
+    o = L.StfOptions()
+    o.variant, o.mult_rule, o.eta_rule, o.precision = L.PCAL, L.MULT_PSI_PHI, L.ETA_ABB, prec
+    o.max_iter, o.kkt_every, o.check_every = 10, 1, 5
+    o.beta, o.eta0, o.tol = 10.0, 14.0, 1e-8
+    return o
+
+
+def test_batched_host_checks():
+    lib = L.load()
+    vp = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    probs = (L.StfProblem * 2)(_problem(n=1000, p=10), _problem(n=1500, p=40))
+    assert lib.stf_batched_workspace_size(2, vp(probs), None) > 0
+    opts = (L.StfOptions * 2)(_valid_options(), _valid_options())
+    s64 = lib.stf_batched_workspace_size(2, vp(probs), vp(opts))
+    assert s64 > 1000 * 10 * 8 + 1500 * 40 * 8
+    # the grouped passes are the 1D ones
+    p3 = (L.StfProblem * 1)(_problem(kind=L.KIND_STENCIL3D, n=1000, grid=(10, 10, 10)))
+    assert lib.stf_batched_workspace_size(1, vp(p3), None) == 0
+    # one storage dtype per batch
+    mixed = (L.StfOptions * 2)(_valid_options(), _valid_options(L.PREC_FP32))
+    assert lib.stf_batched_workspace_size(2, vp(probs), vp(mixed)) == 0
+    res = (L.StfResult * 2)()
+    ptrs = (ctypes.c_void_p * 2)(1, 1)
+    assert lib.stf_solve_batched(0, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
+                                 vp(res), None) == L.E_INVALID
+    sw = (L.StfOptions * 2)(_valid_options(), _valid_options())
+    sw[1].switch_tol = 1e-3
+    assert lib.stf_solve_batched(2, vp(probs), vp(ptrs), vp(sw), ctypes.c_void_p(1), 1,
+                                 vp(res), None) == L.E_UNSUPPORTED
+    assert lib.stf_solve_batched(2, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
+                                 vp(res), None) == L.E_WORKSPACE

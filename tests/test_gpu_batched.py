@@ -1,0 +1,136 @@
+"""GPU parity of the batched solver (many 1D problems of uneven n, p, alpha).
+
+* FP64 iterates of every problem after k steps match the oracle's to 1e-10
+  relative (the Gram tiles cover all three MFMA tile buckets: p <= 32, <= 64, > 64);
+* a batch run to tolerance stops each problem on its own stop test and every
+  problem's objective matches the oracle's converged one to 1e-8;
+* graph replay and uncaptured enqueueing give bitwise equal iterates;
+* the float32 storage forms follow the oracle within their stated error;
+* the autotuner returns budgets from its candidate set and a solve with them
+  gives the same float64 iterates as the defaults up to rounding.
+The penalty beta of each problem is scaled to its Hartree term (alpha p n / 8,
+the size of alpha L^{-1} rho for rho ~ p / n) so that every problem converges.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.problems import OracleProblem
+from oracle import solver as O
+from paper_1810_03930_amd import stiefel as S
+from tests.helpers import rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(600, 6, 1.0), (900, 12, 0.5), (1500, 20, 0.1), (700, 40, 0.05), (1100, 70, 0.02),
+         (800, 130, 0.01)]
+
+
+def _batch(cases=CASES):
+    probs, x0s = [], []
+    for i, (n, p, a) in enumerate(cases):
+        prob, x0 = W.ks1d(n=n, p=p, alpha=a, config=40 + i)
+        probs.append(prob)
+        x0s.append(x0)
+    return probs, x0s
+
+
+def _beta(prob):
+    return prob.alpha * prob.p * prob.n / 8.0 + 10.0
+
+
+def _opts(probs, precision="fp64", max_iter=20, tol=0.0, orth=False, use_graph=True,
+          check_every=16):
+    ol, gl = [], []
+    for prob in probs:
+        b = _beta(prob)
+        ol.append(O.Options(variant="pcal", beta=b, eta0=b + prob.s_bound, tol=tol,
+                            max_iter=max_iter, mult="psi_phi", orth_final=orth))
+        gl.append(S.SolveOptions(variant="pcal", mult="psi_phi", precision=precision, beta=b,
+                                 eta0=b + prob.s_bound, tol=tol, max_iter=max_iter,
+                                 orth_final=orth, use_graph=use_graph, check_every=check_every))
+    return ol, gl
+
+
+def _run(probs, x0s, gl, budgets=None):
+    dps = [S.DeviceProblem.from_host(p) for p in probs]
+    Xs = [to_dev(x0, S.storage_dtype(gl[0].precision)) for x0 in x0s]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        res, rc, msi = S.solve_batched(dps, Xs, gl, budgets=budgets, stream=s)
+    torch.cuda.synchronize()
+    return res, rc, [to_np(X) for X in Xs], msi
+
+
+@pytest.mark.parametrize("k", [1, 20])
+def test_batched_iterates_fp64(k):
+    probs, x0s = _batch()
+    ol, gl = _opts(probs, max_iter=k)
+    res, rc, Xs, _ = _run(probs, x0s, gl)
+    assert rc == 1
+    for prob, x0, o, r, X in zip(probs, x0s, ol, res, Xs):
+        o.record_iterates = [k]
+        ref = O.solve(OracleProblem(prob), x0, o)
+        err = rel(X, ref.iterates[k])
+        print(f"n={prob.n} p={prob.p}: iterate error after {k} steps {err:.2e}")
+        assert r["iters"] == k and r["status"] == 1
+        assert err <= 1e-10
+
+
+def test_batched_converged_parity():
+    probs, x0s = _batch()
+    ol, gl = _opts(probs, max_iter=3000, tol=1e-8, orth=True, check_every=50)
+    res, rc, Xs, _ = _run(probs, x0s, gl)
+    assert rc == 0
+    iters = [r["iters"] for r in res]
+    print("iterations per problem:", iters)
+    assert len(set(iters)) > 1          # each problem stops on its own test
+    for prob, x0, o, r, X in zip(probs, x0s, ol, res, Xs):
+        ref = O.solve(OracleProblem(prob), x0, o)
+        assert ref.status == 0 and r["status"] == 0
+        assert r["kkt_rel"] <= 1.01e-8
+        assert abs(r["fval"] - ref.f) <= 1e-8 * abs(ref.f)
+        assert r["feas"] <= 1e-13 * prob.p
+
+
+def test_batched_graph_matches_uncaptured():
+    probs, x0s = _batch()
+    _, g1 = _opts(probs, max_iter=23, use_graph=True, check_every=6)
+    _, g2 = _opts(probs, max_iter=23, use_graph=False, check_every=1)
+    _, _, X1, _ = _run(probs, x0s, g1)
+    _, _, X2, _ = _run(probs, x0s, g2)
+    for a, b in zip(X1, X2):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_batched_reduced_precision(precision):
+    probs, x0s = _batch()
+    k = 5
+    ol, gl = _opts(probs, precision=precision, max_iter=k)
+    res, rc, Xs, _ = _run(probs, x0s, gl)
+    for prob, x0, o, r, X in zip(probs, x0s, ol, res, Xs):
+        o.record_iterates = [k]
+        ref = O.solve(OracleProblem(prob), x0, o)
+        err = rel(X, ref.iterates[k])
+        print(f"{precision} n={prob.n} p={prob.p}: iterate error after {k} steps {err:.2e}")
+        assert r["iters"] == k
+        assert err <= 1e-5 * k
+
+
+def test_batched_tuner_and_budgets():
+    probs, x0s = _batch()
+    _, gl = _opts(probs, max_iter=4)
+    dps = [S.DeviceProblem.from_host(p) for p in probs]
+    Xs = [to_dev(x0, torch.float64) for x0 in x0s]
+    (bg, br), ms = S.tune_batched(dps, Xs, gl, iters=4)
+    torch.cuda.synchronize()
+    print(f"tuned budgets gram {bg} residual {br}: {ms:.3f} ms per iteration")
+    assert bg in (1024, 2048, 4096) and br in (1024, 2048, 4096) and ms > 0
+    _, gl = _opts(probs, max_iter=20)
+    _, _, Xa, _ = _run(probs, x0s, gl)
+    _, _, Xb, _ = _run(probs, x0s, gl, budgets=(bg, br))
+    for a, b in zip(Xa, Xb):
+        assert rel(a, b) <= 1e-10
