@@ -236,6 +236,91 @@ def cpu_baseline(prob, x0):
             "s_per_iter": per_iter, "host_cores_visible": cores, "blas_threads": threads}
 
 
+def batched_main(args, torch, S, W):
+    """Config 4: 256 independent 1D Kohn-Sham problems (uneven n, p, alpha),
+    batched vs one problem after another."""
+    probs, x0s = W.batched_ks1d(nprob=256)
+    dps = [S.DeviceProblem.from_host(p) for p in probs]
+
+    def opts(prec, max_iter, tol, use_graph=True, check_every=50):
+        out = []
+        for prob in probs:
+            b = prob.alpha * prob.p * prob.n / 8.0 + 10.0   # above the Hartree scale
+            out.append(S.SolveOptions(variant="pcal", mult="psi_phi", eta_rule="abb",
+                                      precision=prec, beta=b, eta0=b + prob.s_bound, tol=tol,
+                                      max_iter=max_iter, orth_final=tol > 0,
+                                      use_graph=use_graph, check_every=check_every))
+        return out
+
+    stream = torch.cuda.Stream()
+    out = {}
+    for prec in ["fp64", args.fast_form]:
+        dt = S.storage_dtype(prec)
+        Xs = [torch.as_tensor(x0, device="cuda").to(dt).contiguous() for x0 in x0s]
+        x0d = [X.clone() for X in Xs]
+        ws = torch.empty(S.batched_workspace_size(dps, opts(prec, 1, 0.0)), dtype=torch.uint8,
+                         device="cuda")
+
+        def reload():
+            for X, X0 in zip(Xs, x0d):
+                X.copy_(X0)
+            torch.cuda.synchronize()
+
+        with torch.cuda.stream(stream):
+            log(f"batched {prec}: autotune")
+            budgets, _ = S.tune_batched(dps, Xs, opts(prec, 4, 0.0), iters=4, workspace=ws,
+                                        stream=stream)
+            reload()
+            S.solve_batched(dps, Xs, opts(prec, args.warmup, 0.0, check_every=args.warmup),
+                            workspace=ws, budgets=budgets, stream=stream)
+            reload()
+            log(f"batched {prec}: {args.steps} timed iterations, budgets {budgets}")
+            res, rc, msi = S.solve_batched(dps, Xs, opts(prec, args.steps, 0.0,
+                                                         check_every=args.steps),
+                                           workspace=ws, budgets=budgets, stream=stream)
+            torch.cuda.synchronize()
+            agg = len(probs) * 1000.0 / msi
+            # the same iterations one problem after another (single-problem solver)
+            log(f"batched {prec}: serial reference")
+            reload()
+            t_serial = 0.0
+            for dp, X, o in zip(dps, Xs, opts(prec, args.steps, 0.0, check_every=args.steps)):
+                r, _, _ = S.solve(dp, X, o, stream=stream)
+                t_serial += r["ms_loop"]
+            torch.cuda.synchronize()
+            agg_serial = len(probs) * args.steps * 1000.0 / t_serial
+            # every problem to relative KKT <= TOL (or MAX_ITER)
+            reload()
+            log(f"batched {prec}: time to KKT")
+            rk, rck, _ = S.solve_batched(dps, Xs, opts(prec, MAX_ITER, TOL), workspace=ws,
+                                         budgets=budgets, stream=stream)
+            torch.cuda.synchronize()
+        conv = sum(1 for r in rk if r["status"] == 0)
+        out[prec] = {"aggregate_iters_per_s": agg, "ms_per_batch_iter": msi,
+                     "serial_aggregate_iters_per_s": agg_serial,
+                     "speedup_vs_serial": agg / agg_serial, "budgets": list(budgets),
+                     "time_to_kkt_s": (rk[0]["ms_loop"] + rk[0]["ms_orth"]) / 1000.0,
+                     "converged": conv, "max_iters": max(r["iters"] for r in rk),
+                     "worst_kkt_rel": max(r["kkt_rel"] for r in rk)}
+        log(f"batched {prec}: {json.dumps(out[prec])}")
+        del Xs, x0d, ws
+    fast = out[args.fast_form]
+    line = {
+        "metric": "batched PCAL aggregate iters/s, 256 x 1D KS (uneven n, p, alpha)",
+        "value": fast["aggregate_iters_per_s"], "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": fast["ms_per_batch_iter"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.fast_form == "fp32" else "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
+        "data": "synthetic",
+        "config": {"workload": "256 x 1D Kohn-Sham-shaped PCAL, n~U[1000,20000], "
+                               "p~U[8,128], alpha~U[0.5,2], beta = alpha p n / 8 + 10",
+                   "nprob": len(probs), "sum_np": int(sum(p.n * p.p for p in probs))},
+        "forms": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +330,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-ttk", action="store_true",
                     help="skip the time-to-KKT solves (short runs under hardware counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure the batched solver on the 256-problem 1D workload instead")
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times: the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -269,6 +356,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.batched:
+        batched_main(args, torch, S, W)
+        return
     log("generating the 64^3 p=256 workload (seeded)")
     prob, x0, _ = W.ks3d(grid=GRID, p=P, alpha=ALPHA)
     dp = S.DeviceProblem.from_host(prob)
