@@ -24,7 +24,9 @@ GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg) {
     g.nb = (p + g.bt - 1) / g.bt;
     g.n_s_tiles = g.nb * (g.nb + 1) / 2;
     g.n_tiles = g.n_s_tiles + g.nb * g.nb;
-    int64_t nch = (target_wg + g.n_tiles - 1) / g.n_tiles;
+    // whole rounds of workgroups: never more than target_wg (a few extra
+    // workgroups would cost a whole extra round of the longest ones)
+    int64_t nch = target_wg / g.n_tiles;
     const int64_t max_ch = std::max<int64_t>(1, n / 256);
     nch = std::min(nch, max_ch);
     nch = std::max<int64_t>(nch, 1);

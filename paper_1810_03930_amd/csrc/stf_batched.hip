@@ -520,8 +520,8 @@ int stf_batched_tune(int32_t nprob, const stf_problem* probs, void* const* X,
     }
     std::vector<stf_result> r((size_t)nprob);
     const bool mixed = opts[0].precision == STF_PREC_MIXED;
-    const int gram_c[] = {1024, 2048, 4096};
-    const int res_c[] = {mixed ? 256 : 1024, mixed ? 512 : 2048, mixed ? 1024 : 4096};
+    const int gram_c[] = {2048, 4096, 8192};
+    const int res_c[] = {mixed ? 512 : 2048, mixed ? 1024 : 4096, mixed ? 2048 : 8192};
     double best = INFINITY;
     for (int bg : gram_c)
         for (int br : res_c) {

@@ -96,6 +96,21 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return r;
 }
 
+// Sum over the NW waves of a workgroup; the result is valid in thread 0.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) r += sh[w];
+    return r;
+}
+
 // Map a hardware workgroup id to a logical id so that consecutive logical ids
 // run on the same XCD (workgroups are dealt to the 8 XCDs round-robin).
 __device__ __forceinline__ int xcd_remap(int b, int nwg) {
@@ -1424,7 +1439,7 @@ __global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ pr
 // identity X^{k-1} = nu^{k-1} X^k + gradL^{k-1} / eta^{k-1} (the PCAL scaling
 // undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
-template <typename T, bool APPLY, bool KKT>
+template <typename T, bool APPLY, bool KKT, int WC>
 __device__ __forceinline__ void body_residual(
     const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
@@ -1435,38 +1450,42 @@ __device__ __forceinline__ void body_residual(
     constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
     constexpr int XS = KC + 1;
     constexpr int MST = 128 + 4;
+    constexpr int NT = 128 * WC;       // threads: 2 x WC waves
+    constexpr int WTC = 128 / WC;      // columns per wave
+    constexpr int JT = WTC / 16;       // 16-column MFMA tiles per wave
     __shared__ T Xs[128 * XS];
     __shared__ T Ms[KC * MST];
-    __shared__ T Ps[KKT ? KC * MST : 1];
-    __shared__ double sh[4];
+    __shared__ double sh[2 * WC];
     __shared__ double scol[2][2][128];
     const int nwg = nblk_;
     const int lid = xcd_remap(bid_, nwg);
     const int rb = lid / ncb, cb = lid % ncb;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+    const int lane = tid & 63, wave = tid >> 6, wr = wave / WC, wc = wave % WC;
     const int lr = lane & 15, lk = lane >> 4;
     const int cblk = cb * 128;
-    const int c0 = cblk + wc * 64;
+    const int c0 = cblk + wc * WTC;
 
-    bool kkt_due = false, have_prev = false, iterate = APPLY;
+    // KKT instantiations run only the stop-test product R = G - X Psi
+    // (mode RES_KKT_ONLY); the others apply (APPLY) or iterate with M_L
+    bool have_prev = false;
+    const bool iterate = !APPLY && !KKT && (mode == RES_ITERATE);
     double eta_prev = 1.0;
-    if (!APPLY) {
-        const int k = st->iter;
-        iterate = (mode == RES_ITERATE);
-        kkt_due = KKT && ((mode == RES_KKT_ONLY) || (k % prm->kkt_every == 0) ||
-                          (k >= prm->max_iter));
-        have_prev = iterate && (k >= 1);
+    if (!APPLY && !KKT) {
+        have_prev = iterate && (st->iter >= 1);
         eta_prev = st->eta;
     }
-    double cxg[4] = {0.0, 0.0, 0.0, 0.0}, cgg[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* Mp = KKT ? Psi : ML;
+    double cxg[JT], cgg[JT];
+#pragma unroll
+    for (int j = 0; j < JT; ++j) cxg[j] = cgg[j] = 0.0;
     double skk = 0.0, sss = 0.0, ssy = 0.0, syy = 0.0;
     const double rinv_eta = 1.0 / eta_prev;
     // per-column constants of this lane's four output columns
-    bool cok[4];
-    double onu[4];
+    bool cok[JT];
+    double onu[JT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JT; ++j) {
         const int c = c0 + j * 16 + lr;
         cok[j] = c < p;
         onu[j] = (!APPLY && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
@@ -1474,15 +1493,15 @@ __device__ __forceinline__ void body_residual(
     // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x 128),
     // 16-byte vectors when the row pitch allows it, prefetched one chunk ahead
     constexpr int VX = 16 / (int)sizeof(T);          // elements of X per 16-byte load
-    constexpr int NXV = 128 * KC / VX / 256;         // X vectors per thread
-    constexpr int NMV = KC * 128 / 2 / 256;          // float64 pairs of M per thread
+    constexpr int NXV = 128 * KC / VX / NT;          // X vectors per thread
+    constexpr int NMV = KC * 128 / 2 / NT;           // float64 pairs of M per thread
     const bool vec = ((p % VX) == 0);
     T xr[NXV][VX];
-    T mr[NMV][2], pr[KKT ? NMV : 1][2];
+    T mr[NMV][2];
     auto load_chunk = [&](int64_t r0, int kc) {
 #pragma unroll
         for (int s2 = 0; s2 < NXV; ++s2) {
-            const int e = tid + 256 * s2;
+            const int e = tid + NT * s2;
             const int rr = e / (KC / VX), kv = e % (KC / VX);
             const int64_t r = r0 + rr;
             const int k = kc + kv * VX;
@@ -1500,28 +1519,21 @@ __device__ __forceinline__ void body_residual(
         }
 #pragma unroll
         for (int s2 = 0; s2 < NMV; ++s2) {
-            const int e = tid + 256 * s2;
+            const int e = tid + NT * s2;
             const int kk = e >> 6, cc = (e & 63) * 2;
             const int k = kc + kk, c = cblk + cc;
             if ((p & 1) == 0 && k < p && c + 2 <= p) {
                 typedef double dv2 __attribute__((ext_vector_type(2)));
                 const size_t idx = (size_t)k * p + c;
-                const dv2 z = {0.0, 0.0};
-                const dv2 m = iterate ? *(const dv2*)(ML + idx) : z;
+                const dv2 m = *(const dv2*)(Mp + idx);
                 mr[s2][0] = (T)m[0];
                 mr[s2][1] = (T)m[1];
-                if (KKT) {
-                    const dv2 q = kkt_due ? *(const dv2*)(Psi + idx) : z;
-                    pr[KKT ? s2 : 0][0] = (T)q[0];
-                    pr[KKT ? s2 : 0][1] = (T)q[1];
-                }
             } else {
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
                     const bool ok = (k < p) && (c + v < p);
                     const size_t idx = (size_t)k * p + c + v;
-                    mr[s2][v] = (iterate && ok) ? (T)ML[idx] : (T)0;
-                    if (KKT) pr[KKT ? s2 : 0][v] = (kkt_due && ok) ? (T)Psi[idx] : (T)0;
+                    mr[s2][v] = ok ? (T)Mp[idx] : (T)0;
                 }
             }
         }
@@ -1529,20 +1541,17 @@ __device__ __forceinline__ void body_residual(
     auto store_chunk = [&]() {
 #pragma unroll
         for (int s2 = 0; s2 < NXV; ++s2) {
-            const int e = tid + 256 * s2;
+            const int e = tid + NT * s2;
             const int rr = e / (KC / VX), kv = e % (KC / VX);
 #pragma unroll
             for (int v = 0; v < VX; ++v) Xs[rr * XS + kv * VX + v] = xr[s2][v];
         }
 #pragma unroll
         for (int s2 = 0; s2 < NMV; ++s2) {
-            const int e = tid + 256 * s2;
+            const int e = tid + NT * s2;
             const int kk = e >> 6, cc = (e & 63) * 2;
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                Ms[kk * MST + cc + v] = mr[s2][v];
-                if (KKT) Ps[kk * MST + cc + v] = pr[KKT ? s2 : 0][v];
-            }
+            for (int v = 0; v < 2; ++v) Ms[kk * MST + cc + v] = mr[s2][v];
         }
     };
 
@@ -1550,19 +1559,13 @@ __device__ __forceinline__ void body_residual(
     if (rt < nrt) load_chunk(rt * 128, 0);
     for (; rt < nrt; rt += nrb) {
         const int64_t r0 = rt * 128;
-        typename Mma<T>::acc a1[4][4], a2[KKT ? 4 : 1][4];
+        typename Mma<T>::acc a1[4][JT];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JT; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a1[i][j][q] = 0;
-#pragma unroll
-        for (int i = 0; i < (KKT ? 4 : 1); ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a2[i][j][q] = 0;
         for (int kc = 0; kc < p; kc += KC) {
             __syncthreads();
             store_chunk();
@@ -1574,34 +1577,24 @@ __device__ __forceinline__ void body_residual(
                 load_chunk((rt + nrb) * 128, 0);
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 4) {
-                T a[4], b[4];
+                T a[4], b[JT];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) a[i] = Xs[(wr * 64 + i * 16 + lr) * XS + kk + lk];
-                if (iterate) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) b[j] = Ms[(kk + lk) * MST + wc * 64 + j * 16 + lr];
+                for (int j = 0; j < JT; ++j) b[j] = Ms[(kk + lk) * MST + wc * WTC + j * 16 + lr];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) a1[i][j] = Mma<T>::run(a[i], b[j], a1[i][j]);
-                }
-                if (KKT && kkt_due) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) b[j] = Ps[(kk + lk) * MST + wc * 64 + j * 16 + lr];
-#pragma unroll
-                    for (int i = 0; i < (KKT ? 4 : 1); ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) a2[i][j] = Mma<T>::run(a[i], b[j], a2[i][j]);
-                }
+                    for (int j = 0; j < JT; ++j) a1[i][j] = Mma<T>::run(a[i], b[j], a1[i][j]);
             }
         }
-        // epilogue, one 16-row sub-tile at a time with all its loads issued first
+        // epilogue, one 16-row sub-tile at a time
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (APPLY) {
                 // mode 0: Out = X M; mode 1: Out -= X M
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < JT; ++j)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
@@ -1615,38 +1608,38 @@ __device__ __forceinline__ void body_residual(
                     }
                 continue;
             }
-            T gv[4][4], xv[4][4], gpv[4][4];
+            // loads of one 16-column group issued together (enough to keep
+            // the register count at two waves per SIMD)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JT; ++j) {
+                T gv[4], xv[4], gpv[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
                     const bool ok = (r < n) && cok[j];
                     const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
-                    gv[j][q] = ok ? G[idx] : (T)0;
-                    xv[j][q] = (ok && iterate) ? X[idx] : (T)0;
-                    gpv[j][q] = (ok && have_prev) ? Gprev[idx] : (T)0;
+                    gv[q] = ok ? G[idx] : (T)0;
+                    xv[q] = (ok && iterate) ? X[idx] : (T)0;
+                    gpv[q] = (ok && have_prev) ? Gprev[idx] : (T)0;
                 }
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
                     if (r >= n || !cok[j]) continue;
-                    const double g = (double)gv[j][q];
-                    if (KKT && kkt_due) {
-                        const double rk = g - (double)a2[KKT ? i : 0][j][q];
+                    const double g = (double)gv[q];
+                    if (KKT) {
+                        const double rk = g - (double)a1[i][j][q];
                         skk += rk * rk;
                     }
                     if (!iterate) continue;
                     const T glt = (T)(g - (double)a1[i][j][q]);
                     G[(size_t)r * p + c0 + j * 16 + lr] = glt;
                     const double gl = (double)glt;
-                    const double x = (double)xv[j][q];
+                    const double x = (double)xv[q];
                     cxg[j] += x * gl;
                     cgg[j] += gl * gl;
                     if (have_prev) {
-                        const double glp = (double)gpv[j][q];
+                        const double glp = (double)gpv[q];
                         const double sd = onu[j] * x - glp * rinv_eta;
                         const double yd = gl - glp;
                         sss += sd * sd;
@@ -1654,12 +1647,13 @@ __device__ __forceinline__ void body_residual(
                         syy += yd * yd;
                     }
                 }
+            }
         }
     }
     if (APPLY) return;
     // column partials: reduce over the 4 row groups of a wave, then the 2 wave rows
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JT; ++j) {
         cxg[j] += __shfl_xor(cxg[j], 16, 64);
         cxg[j] += __shfl_xor(cxg[j], 32, 64);
         cgg[j] += __shfl_xor(cgg[j], 16, 64);
@@ -1668,9 +1662,9 @@ __device__ __forceinline__ void body_residual(
     if (iterate) {
         if (lk == 0) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                scol[wr][0][wc * 64 + j * 16 + lr] = cxg[j];
-                scol[wr][1][wc * 64 + j * 16 + lr] = cgg[j];
+            for (int j = 0; j < JT; ++j) {
+                scol[wr][0][wc * WTC + j * 16 + lr] = cxg[j];
+                scol[wr][1][wc * WTC + j * 16 + lr] = cgg[j];
             }
         }
         __syncthreads();
@@ -1683,10 +1677,10 @@ __device__ __forceinline__ void body_residual(
             }
         }
     }
-    const double t0 = block_sum256(skk, sh);
-    const double t1 = block_sum256(sss, sh);
-    const double t2 = block_sum256(ssy, sh);
-    const double t3 = block_sum256(syy, sh);
+    const double t0 = block_sum<2 * WC>(skk, sh);
+    const double t1 = block_sum<2 * WC>(sss, sh);
+    const double t2 = block_sum<2 * WC>(ssy, sh);
+    const double t3 = block_sum<2 * WC>(syy, sh);
     if (tid == 0) {
         double* ps = part_scal + (size_t)lid * 4;
         ps[0] = t0;
@@ -1695,14 +1689,15 @@ __device__ __forceinline__ void body_residual(
         ps[3] = t3;
     }
 }
-template <typename T, bool APPLY, bool KKT>
-__global__ __launch_bounds__(256) void k_residual(
+template <typename T, bool APPLY, bool KKT, int WC>
+__global__ __launch_bounds__(128 * WC) void k_residual(
     const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
-    body_residual<T, APPLY, KKT>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col, part_scal, prm, st, mode, blockIdx.x, gridDim.x);
+    body_residual<T, APPLY, KKT, WC>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col,
+                                     part_scal, prm, st, mode, blockIdx.x, gridDim.x);
 }
 
 
@@ -2199,10 +2194,10 @@ __global__ __launch_bounds__(256) void kb_split3(STF_BATCH_ARGS) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kb_residual(STF_BATCH_ARGS) {
+__global__ __launch_bounds__(512) void kb_residual(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const ResPlan& r = d.res;
-    body_residual<T, false, false>((const T*)d.X, (T*)d.g[parity], (const T*)d.g[parity ^ 1],
+    body_residual<T, false, false, 4>((const T*)d.X, (T*)d.g[parity], (const T*)d.g[parity ^ 1],
                                    d.ML, d.Psi, d.nu, d.n, d.p, r.nrb, r.ncb, r.nrt, d.res_col,
                                    d.res_scal, d.prm, d.st, RES_ITERATE, lid_, nb_);
 }
@@ -2469,19 +2464,19 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     mark();
     if (dtype == STF_F64) {
         if (kkt_prod)
-            k_residual<double, false, true><<<nwg, 256, 0, s>>>(
+            k_residual<double, false, true, 2><<<nwg, 256, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
                 rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
         else
-            k_residual<double, false, false><<<nwg, 256, 0, s>>>(
+            k_residual<double, false, false, 4><<<nwg, 512, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
                 rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
     } else if (kkt_prod) {
-        k_residual<float, false, true><<<nwg, 256, 0, s>>>(
+        k_residual<float, false, true, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
     } else {
-        k_residual<float, false, false><<<nwg, 256, 0, s>>>(
+        k_residual<float, false, false, 4><<<nwg, 512, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
     }
@@ -2510,11 +2505,11 @@ void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const 
                   int64_t n, int p, hipStream_t s, int subtract) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     if (dtype == STF_F64)
-        k_residual<double, true, false><<<nwg, 256, 0, s>>>(
+        k_residual<double, true, false, 2><<<nwg, 256, 0, s>>>(
             (const double*)X, (double*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
             rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
     else
-        k_residual<float, true, false><<<nwg, 256, 0, s>>>(
+        k_residual<float, true, false, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
             rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
 }
@@ -2626,9 +2621,9 @@ void launch_batched(int stage, int dtype, int precision, int variant_key, const 
                 else
                     kb_residual_bf6_lds<384><<<g, 256, 0, s>>>(d, L, O, c, parity);
             } else if (f64) {
-                kb_residual<double><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                kb_residual<double><<<g, 512, 0, s>>>(d, L, O, c, parity);
             } else {
-                kb_residual<float><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                kb_residual<float><<<g, 512, 0, s>>>(d, L, O, c, parity);
             }
             break;
         case BS_COLRED:

@@ -128,7 +128,7 @@ def test_batched_tuner_and_budgets():
     (bg, br), ms = S.tune_batched(dps, Xs, gl, iters=4)
     torch.cuda.synchronize()
     print(f"tuned budgets gram {bg} residual {br}: {ms:.3f} ms per iteration")
-    assert bg in (1024, 2048, 4096) and br in (1024, 2048, 4096) and ms > 0
+    assert bg in (2048, 4096, 8192) and br in (2048, 4096, 8192) and ms > 0
     _, gl = _opts(probs, max_iter=20)
     _, _, Xa, _ = _run(probs, x0s, gl)
     _, _, Xb, _ = _run(probs, x0s, gl, budgets=(bg, br))
