@@ -17,13 +17,14 @@ namespace stf {
 
 int elem_size(int dtype) { return dtype == STF_F64 ? 8 : 4; }
 
-GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg) {
+GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg, bool wup) {
     GramPlan g;
     g.wm = (p <= 32) ? 1 : (p <= 64 ? 2 : 4);
     g.bt = 32 * g.wm;
     g.nb = (p + g.bt - 1) / g.bt;
     g.n_s_tiles = g.nb * (g.nb + 1) / 2;
-    g.n_tiles = g.n_s_tiles + g.nb * g.nb;
+    g.wup = wup ? 1 : 0;
+    g.n_tiles = g.n_s_tiles + (wup ? g.n_s_tiles : g.nb * g.nb);
     // whole rounds of workgroups: never more than target_wg (a few extra
     // workgroups would cost a whole extra round of the longest ones)
     int64_t nch = target_wg / g.n_tiles;
@@ -110,9 +111,15 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.nu = take((size_t)p * 8);
     L.colxg = take((size_t)p * 8);
     L.colgg = take((size_t)p * 8);
-    L.gram = make_gram_plan(n, p);
-    L.gram64 = L.gram;
-    L.gram_part = take((size_t)L.gram.nchunks * L.gram.n_tiles * L.gram.bt * L.gram.bt * 8);
+    // iterations: W symmetric (upper blocks); evaluation / CholeskyQR2 / step API: full
+    L.gram = make_gram_plan(n, p, 1024, true);
+    L.gram64 = make_gram_plan(n, p);
+    {
+        // room for any tile set (S upper + all of W) at either plan's chunk count
+        const size_t tiles = (size_t)L.gram64.n_s_tiles + (size_t)L.gram64.nb * L.gram64.nb;
+        const size_t nch = (size_t)std::max(L.gram.nchunks, L.gram64.nchunks);
+        L.gram_part = take(nch * tiles * L.gram64.bt * L.gram64.bt * 8);
+    }
     L.res = make_res_plan(n, p, 128);
     L.res64 = make_res_plan(n, p, 64);
     L.resmx = make_res_plan(n, p, 256);
@@ -270,7 +277,8 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     // groups 2..4: the Gram kernel | chunk reduction, p x p stage, KKT products,
     // split of M_L | the residual kernel (events 3 and 4 recorded by the launchers)
     launch_gram(c.dtype, c.precision, w.L.gram, c.X, Gc, n, p, w.at<double>(w.L.gram_part),
-                w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s, ev ? ev[3] : nullptr);
+                w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s, ev ? ev[3] : nullptr,
+                /*w_sym=*/true);
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
                   w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
     launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
@@ -615,7 +623,7 @@ int stf_gram(const stf_problem* prob, const void* X, const void* G, int32_t dtyp
     if (dtype != STF_F64 && dtype != STF_F32) return STF_E_INVALID;
     if (precision < STF_PREC_FP64 || precision > STF_PREC_MIXED) return STF_E_INVALID;
     if ((precision == STF_PREC_FP64) != (dtype == STF_F64)) return STF_E_UNSUPPORTED;
-    launch_gram(dtype, precision, w.L.gram, X, G, prob->n, prob->p,
+    launch_gram(dtype, precision, w.L.gram64, X, G, prob->n, prob->p,
                 w.at<double>(w.L.gram_part), S, W, nullptr, stream);
     return hipStreamSynchronize(stream) == hipSuccess ? last_launch() : STF_E_HIP;
 }

@@ -113,9 +113,10 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         const double share = (double)pr.n * pr.p * pr.p / wsum;
         P.L[b] = make_layout(&pr, precision);
         // batched plans never exceed the single-problem ones the layout is sized for
-        const GramPlan g0 = make_gram_plan(pr.n, pr.p);
+        // W = X^T grad f(X) is symmetric here: upper blocks only
+        const GramPlan g0 = make_gram_plan(pr.n, pr.p, 1024, true);
         const int64_t tg = std::max<int64_t>(g0.n_tiles, (int64_t)llround(bg * share));
-        P.gram[b] = make_gram_plan(pr.n, pr.p, std::min<int64_t>(tg, 1024));
+        P.gram[b] = make_gram_plan(pr.n, pr.p, std::min<int64_t>(tg, 1024), true);
         if (mixed) {
             const ResPlan r0 = make_res_plan(pr.n, pr.p, 256);
             const int64_t tr = std::max<int64_t>(r0.ncb, (int64_t)llround(br * share));

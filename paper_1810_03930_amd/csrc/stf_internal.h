@@ -50,7 +50,8 @@ struct GramPlan {
     int bt;          // workgroup tile = 32 * wm
     int nb;          // ceil(p / bt)
     int n_s_tiles;   // upper-triangular blocks of S
-    int n_tiles;     // n_s_tiles + nb*nb (W blocks)
+    int n_tiles;     // n_s_tiles + the W blocks (nb*nb, or n_s_tiles when wup)
+    int wup;         // 1: W symmetric, only its upper blocks are computed
     int nchunks;     // split-K chunks over the n rows
     int64_t chunk;   // rows per chunk (multiple of 4)
 };
@@ -126,7 +127,7 @@ void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t 
 
 int elem_size(int dtype);
 // target_wg: workgroups the plan aims at (the single-problem defaults when omitted)
-GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 1024);
+GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 1024, bool wup = false);
 ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
 Layout make_layout(const stf_problem* prob, int precision);
 size_t align256(size_t x);
@@ -164,7 +165,7 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
                  double* W, const DevState* st, hipStream_t s,
-                 hipEvent_t after_main = nullptr);
+                 hipEvent_t after_main = nullptr, bool w_sym = false);
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
                    DevState* st, hipStream_t s);

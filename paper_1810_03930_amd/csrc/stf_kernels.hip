@@ -403,20 +403,27 @@ __device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int
     }
 }
 
-// Decode tile index t of the Gram pass into (bi, bj, is_S).
-__device__ __forceinline__ void gram_tile(int t, int nb, int n_s_tiles, int& bi, int& bj,
-                                          bool& isS) {
-    if (t < n_s_tiles) {
-        isS = true;
-        int row = 0, rem = t;
-        while (rem >= nb - row) {
-            rem -= nb - row;
-            ++row;
-        }
-        bi = row;
-        bj = row + rem;
+// Decode tile index t of the Gram pass into (bi, bj, is_S): the upper blocks
+// of S first, then the blocks of W (only the upper ones when wup: W is
+// symmetric in exact arithmetic for every f here, grad f(X) = H(X) X with H
+// symmetric, so its lower blocks are mirrored from the upper ones).
+__device__ __forceinline__ void upper_block(int u, int nb, int& bi, int& bj) {
+    int row = 0;
+    while (u >= nb - row) {
+        u -= nb - row;
+        ++row;
+    }
+    bi = row;
+    bj = row + u;
+}
+__device__ __forceinline__ void gram_tile(int t, int nb, int n_s_tiles, int wup, int& bi,
+                                          int& bj, bool& isS) {
+    isS = t < n_s_tiles;
+    if (isS) {
+        upper_block(t, nb, bi, bj);
+    } else if (wup) {
+        upper_block(t - n_s_tiles, nb, bi, bj);
     } else {
-        isS = false;
         const int u = t - n_s_tiles;
         bi = u / nb;
         bj = u % nb;
@@ -428,7 +435,7 @@ __device__ __forceinline__ void gram_tile(int t, int nb, int n_s_tiles, int& bi,
 template <typename T, int WM>
 __device__ __forceinline__ void body_gram(const T* __restrict__ X, const T* __restrict__ G,
                                               int64_t n, int p, int nb, int n_s_tiles,
-                                              int n_tiles, int64_t chunk,
+                                              int n_tiles, int wup, int64_t chunk,
                                               double* __restrict__ part,
                                               const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
@@ -439,9 +446,11 @@ __device__ __forceinline__ void body_gram(const T* __restrict__ X, const T* __re
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
     bool isS;
-    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
     const T* Y = isS ? X : G;
     const int wave = threadIdx.x >> 6, wi = wave >> 1, wj = wave & 1;
+    // below the diagonal of a diagonal block of a symmetric result: nothing to do
+    if ((bi == bj) && (isS || wup) && (wi > wj)) return;
     const int zc0 = bi * BT + wi * WT, yc0 = bj * BT + wj * WT;
     const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
     typename Mma<T>::acc acc[WM][WM];
@@ -468,10 +477,10 @@ __device__ __forceinline__ void body_gram(const T* __restrict__ X, const T* __re
 template <typename T, int WM>
 __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* __restrict__ G,
                                               int64_t n, int p, int nb, int n_s_tiles,
-                                              int n_tiles, int64_t chunk,
+                                              int n_tiles, int wup, int64_t chunk,
                                               double* __restrict__ part,
                                               const DevState* __restrict__ st) {
-    body_gram<T, WM>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+    body_gram<T, WM>(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, const T* 
 template <typename T>
 __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
                                                   const T* __restrict__ G, int64_t n, int p,
-                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
@@ -499,7 +508,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
     bool isS;
-    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
     const T* Y = isS ? X : G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
@@ -552,6 +561,9 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
                 for (int q = 0; q < 4; ++q) dacc[i][j][q] = 0.0;
     }
     const bool active = (zc < p) && (yc < p) && (k0 < k1);
+    // in a diagonal block of a symmetric result the wave below the diagonal has
+    // nothing to compute (it still stages its share of the panels)
+    const bool below = (bi == bj) && (isS || wup) && (wi > wj);
     if (active) load(k0);
     int step = 0;
     for (int64_t kb = k0; active && kb < k1; kb += KC, ++step) {
@@ -568,6 +580,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
         }
         __syncthreads();
         if (kb + KC < k1) load(kb + KC);
+        if (below) continue;
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             T a[4], b[4];
@@ -594,6 +607,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
             }
         }
     }
+    if (below) return;
     double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -612,10 +626,10 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_lds(const T* __restrict__ X,
                                                   const T* __restrict__ G, int64_t n, int p,
-                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st) {
-    body_gram_lds<T>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+    body_gram_lds<T>(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -625,7 +639,7 @@ __global__ __launch_bounds__(256) void k_gram_lds(const T* __restrict__ X,
 template <int WM>
 __device__ __forceinline__ void body_gram_bf3(const float* __restrict__ X,
                                                   const float* __restrict__ G, int64_t n, int p,
-                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
@@ -635,9 +649,11 @@ __device__ __forceinline__ void body_gram_bf3(const float* __restrict__ X,
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
     bool isS;
-    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
     const float* Y = isS ? X : G;
     const int wave = threadIdx.x >> 6, wi = wave >> 1, wj = wave & 1;
+    // below the diagonal of a diagonal block of a symmetric result: nothing to do
+    if ((bi == bj) && (isS || wup) && (wi > wj)) return;
     const int zc0 = bi * BT + wi * WT, yc0 = bj * BT + wj * WT;
     const int64_t k0 = (int64_t)c * chunk, k1 = min(n, k0 + chunk);
     const int lane = threadIdx.x & 63, lr = lane & 15, g = lane >> 4;
@@ -711,10 +727,10 @@ __device__ __forceinline__ void body_gram_bf3(const float* __restrict__ X,
 template <int WM>
 __global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
                                                   const float* __restrict__ G, int64_t n, int p,
-                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st) {
-    body_gram_bf3<WM>(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x, gridDim.x);
+    body_gram_bf3<WM>(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -722,27 +738,28 @@ __global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
 // The workgroup walks its chunk of rows KS at a time.  Each thread loads KS/2
 // rows of one column of Z (= X) and of Y (= X or G) -- 256-byte coalesced
 // loads per wave, prefetched one step ahead -- splits them into bf16 pairs
-// h + l and stores them transposed (K contiguous, 144-byte pitch, so that the
+// h + l and stores them transposed (K contiguous, 80-byte pitch, so that the
 // 16-byte operand reads of 16 lanes hit distinct banks).  Four waves of 64 x 64
-// accumulate hh + hl + lh in float32, added into float64 every 256 rows.
-// Partials as in k_gram.
+// accumulate hh + hl + lh in float32 over the whole chunk (one rounding per
+// 32-row MFMA step, ~56 per entry: ~5e-7 relative on a chunk's partial, below
+// the 2^-16 of the split); with no float64 accumulators two workgroups fit on
+// a CU.  Partials as in k_gram.
 __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
                                                   const float* __restrict__ G, int64_t n, int p,
-                                                  int nb, int n_s_tiles, int n_tiles,
+                                                  int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st, int bid_,
                                                   int nblk_) {
     if (st && st->done) return;
-    constexpr int KS = 64;            // rows per step
+    constexpr int KS = 32;            // rows per step
     constexpr int KP = KS + 8;        // LDS pitch in bf16
     constexpr int RH = KS / 2;        // rows per loader thread
-    constexpr int FLUSH = 256 / KS;   // steps between float64 flushes
     __shared__ __attribute__((aligned(16))) __bf16 Ls[4][128 * KP];  // Zh, Zl, Yh, Yl
     const int lid = xcd_remap(bid_, nblk_);
     const int tile = lid % n_tiles, c = lid / n_tiles;
     int bi, bj;
     bool isS;
-    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
     const float* Y = isS ? X : G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
     const int lr = lane & 15, g = lane >> 4;
@@ -783,24 +800,23 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
         }
     };
     f4 acc[4][4];
-    double dacc[4][4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc[i][j][q] = 0.f;
-                dacc[i][j][q] = 0.0;
-            }
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
     const bool active = (zc < p) && (yc < p) && (k0 < k1);
+    // in a diagonal block of a symmetric result the wave below the diagonal has
+    // nothing to compute (it still stages its share of the panels)
+    const bool below = (bi == bj) && (isS || wup) && (wi > wj);
     if (active) load(k0);
-    int step = 0;
-    for (int64_t kb = k0; active && kb < k1; kb += KS, ++step) {
+    for (int64_t kb = k0; active && kb < k1; kb += KS) {
         __syncthreads();
         store();
         __syncthreads();
         if (kb + KS < k1) load(kb + KS);
+        if (below) continue;
 #pragma unroll
         for (int ks = 0; ks < KS; ks += 32) {
             bf8 ah[4], al[4];
@@ -823,18 +839,8 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
                 for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
             }
         }
-        if (step % FLUSH == FLUSH - 1) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        dacc[i][j][q] += (double)acc[i][j][q];
-                        acc[i][j][q] = 0.f;
-                    }
-        }
     }
+    if (below) return;
     double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -844,15 +850,15 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
             for (int q = 0; q < 4; ++q) {
                 const int ii = wi * 64 + i * 16 + Mma<float>::row(g, q);
                 const int jj = wj * 64 + j * 16 + lr;
-                out[ii * 128 + jj] = dacc[i][j][q] + (double)acc[i][j][q];
+                out[ii * 128 + jj] = (double)acc[i][j][q];
             }
 }
-__global__ __launch_bounds__(256) void k_gram_bf3_lds(const float* __restrict__ X,
+__global__ __launch_bounds__(256, 2) void k_gram_bf3_lds(const float* __restrict__ X,
                                                       const float* __restrict__ G, int64_t n,
-                                                      int p, int nb, int n_s_tiles, int n_tiles,
+                                                      int p, int nb, int n_s_tiles, int n_tiles, int wup,
                                                       int64_t chunk, double* __restrict__ part,
                                                       const DevState* __restrict__ st) {
-    body_gram_bf3_lds(X, G, n, p, nb, n_s_tiles, n_tiles, chunk, part, st, blockIdx.x,
+    body_gram_bf3_lds(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x,
                       gridDim.x);
 }
 
@@ -1070,17 +1076,20 @@ __global__ __launch_bounds__(256) void k_residual_bf6(
 }
 
 
+// Rows per wave of the LDS-resident split-bf16 residual pass (64: four waves
+// and one wave per SIMD; 32: eight waves, two per SIMD).
+constexpr int kMixRW = 32;
+
 // MIXED residual pass with M_L resident in LDS.  A workgroup owns a column
 // block of 64 and keeps its slice of the split M_L^T (3 x 64 x pk bf16) in LDS
-// for all its row tiles; four waves of 64 rows x 64 columns walk row tiles of
-// 256 rows.  X fragments come straight from global memory (8 consecutive
+// for all its row tiles; 256 / RW waves of RW rows x 64 columns walk row tiles
+// of 256 rows.  X fragments come straight from global memory (8 consecutive
 // columns of one row per lane, two 16-byte loads), prefetched one K-step
 // ahead and split into h + m + l in registers; the six products
-// sum_{a+b<=2} X_a M_b give float32-level accuracy.  G and gradL^{k-1} of the
-// row tile are loaded before its K loop so that their latency hides behind the
-// MFMAs.  Epilogue, partials and BB pair as in k_residual (stop test by the
-// p x p identity, so no product with Psi).
-template <int PKMAX>
+// sum_{a+b<=2} X_a M_b give float32-level accuracy.  Epilogue, partials and BB
+// pair as in k_residual (stop test by the p x p identity, so no product with
+// Psi).
+template <int PKMAX, int RW>
 __device__ __forceinline__ void body_residual_bf6_lds(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
     const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
@@ -1089,9 +1098,12 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
     constexpr int LP = PKMAX + 8;  // LDS pitch (bf16) of one column's K run
+    constexpr int NW = 256 / RW;   // waves
+    constexpr int NT = 64 * NW;    // threads
+    constexpr int IT = RW / 16;    // 16-row MFMA tiles per wave
     __shared__ __attribute__((aligned(16))) __bf16 Ms[3 * 64 * LP];
     __shared__ double sh[8];
-    __shared__ double scol[4][2][64];
+    __shared__ double scol[NW][2][64];
     const int lid = xcd_remap(bid_, nblk_);
     const int rb = lid / ncb, cb = lid % ncb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1100,7 +1112,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const size_t tot = (size_t)prow * pk;
     {
         const int nv = pk / 8;
-        for (int e = tid; e < 3 * 64 * nv; e += 256) {
+        for (int e = tid; e < 3 * 64 * nv; e += NT) {
             const int sp = e / (64 * nv), rem = e % (64 * nv), cc = rem / nv, kv = rem % nv;
             *(bf8*)&Ms[(sp * 64 + cc) * LP + kv * 8] =
                 *(const bf8*)(MS + sp * tot + (size_t)(cblk + cc) * pk + kv * 8);
@@ -1122,25 +1134,11 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     double sss = 0.0, ssy = 0.0, syy = 0.0;
     const bool vec = (p % 4) == 0;
     for (int64_t rt = rb; rt < nrt; rt += nrb) {
-        const int64_t r0 = rt * 256 + wave * 64;
-        // G and gradL^{k-1} of this wave's 64 x 64 block, in the MFMA output layout
-        float gv[4][4][4], gpv[4][4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = r0 + i * 16 + Mma<float>::row(g, q);
-                    const bool ok = (r < n) && cok[j];
-                    const size_t idx = (size_t)r * p + cblk + j * 16 + lr;
-                    gv[i][j][q] = ok ? G[idx] : 0.f;
-                    gpv[i][j][q] = (ok && have_prev) ? Gprev[idx] : 0.f;
-                }
-        float xa[4][8];
+        const int64_t r0 = rt * 256 + wave * RW;
+        float xa[IT][8];
         auto load_x = [&](int kc) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const int64_t r = r0 + i * 16 + lr;
                 const int c = kc + 8 * g;
                 const float* src = X + (size_t)r * p + c;
@@ -1158,18 +1156,18 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                 }
             }
         };
-        f4 acc[4][4];
+        f4 acc[IT][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < IT; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
         load_x(0);
         for (int kc = 0; kc < pk; kc += 32) {
-            bf8 xh[4], xm[4], xl[4];
+            bf8 xh[IT], xm[IT], xl[IT];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) split3(xa[i], xh[i], xm[i], xl[i]);
+            for (int i = 0; i < IT; ++i) split3(xa[i], xh[i], xm[i], xl[i]);
             if (kc + 32 < pk) load_x(kc + 32);
             bf8 mh[4], mm[4], ml[4];
 #pragma unroll
@@ -1182,53 +1180,81 @@ __device__ __forceinline__ void body_residual_bf6_lds(
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], mh[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mh[j], acc[i][j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], mm[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mm[j], acc[i][j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xm[i], mh[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mh[j], acc[i][j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xh[i], ml[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], ml[j], acc[i][j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xl[i], mh[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xl[i], mh[j], acc[i][j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(xm[i], mm[j], acc[i][j]);
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mm[j], acc[i][j]);
         }
-        // gradL = G - X M_L over G; the rows of X for the dots come from L2
+        // gradL = G - X M_L over G (G, X and gradL^{k-1} of the block are read
+        // here; the second wave of the SIMD covers their latency);
+        // the BB and column dots of the block are summed in float32 per lane
+        // (at most 4 IT terms per column, 16 IT per BB dot) and added in float64
+        const size_t tb = (size_t)r0 * p + cblk;
+        float* Gt = G + tb;
+        const float* Xt = X + tb;
+        const float* Pt = Gprev + tb;
+        const float rinv_f = (float)rinv_eta;
+        float tss = 0.f, tsy = 0.f, tyy = 0.f;
+        float txg[4] = {0.f, 0.f, 0.f, 0.f}, tgg[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < IT; ++i) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j) {
+                const float onu_f = (float)onu[j];
+                float gv[4], xv[4], gpv[4];
+                int off[4];
+                bool ok[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int64_t r = r0 + i * 16 + Mma<float>::row(g, q);
-                    if (r >= n || !cok[j]) continue;
-                    const size_t idx = (size_t)r * p + cblk + j * 16 + lr;
-                    const float glt = (float)((double)gv[i][j][q] - (double)acc[i][j][q]);
-                    G[idx] = glt;
-                    const double gl = (double)glt;
-                    const double x = (double)X[idx];
-                    cxg[j] += x * gl;
-                    cgg[j] += gl * gl;
+                    const int rr = i * 16 + Mma<float>::row(g, q);
+                    ok[q] = (r0 + rr < n) && cok[j];
+                    off[q] = rr * p + j * 16 + lr;
+                    gv[q] = ok[q] ? Gt[off[q]] : 0.f;
+                    xv[q] = ok[q] ? Xt[off[q]] : 0.f;
+                    gpv[q] = (ok[q] && have_prev) ? Pt[off[q]] : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!ok[q]) continue;
+                    const float gl = gv[q] - acc[i][j][q];
+                    Gt[off[q]] = gl;
+                    txg[j] += xv[q] * gl;
+                    tgg[j] += gl * gl;
                     if (have_prev) {
-                        const double glp = (double)gpv[i][j][q];
-                        const double sd = onu[j] * x - glp * rinv_eta;
-                        const double yd = gl - glp;
-                        sss += sd * sd;
-                        ssy += sd * yd;
-                        syy += yd * yd;
+                        const float sd = onu_f * xv[q] - gpv[q] * rinv_f;
+                        const float yd = gl - gpv[q];
+                        tss += sd * sd;
+                        tsy += sd * yd;
+                        tyy += yd * yd;
                     }
                 }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cxg[j] += (double)txg[j];
+            cgg[j] += (double)tgg[j];
+        }
+        sss += (double)tss;
+        ssy += (double)tsy;
+        syy += (double)tyy;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1250,7 +1276,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
         if (c < p) {
             double a = 0.0, b = 0.0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 a += scol[w][0][tid];
                 b += scol[w][1][tid];
             }
@@ -1272,7 +1298,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     __syncthreads();
     if (tid == 0) {
         double t[3] = {0.0, 0.0, 0.0};
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
             for (int q = 0; q < 3; ++q) t[q] += scol[w][0][q];
         double* ps = part_scal + (size_t)lid * 4;
@@ -1284,15 +1310,15 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     (void)sh;
     (void)prm;
 }
-template <int PKMAX>
-__global__ __launch_bounds__(256) void k_residual_bf6_lds(
+template <int PKMAX, int RW>
+__global__ __launch_bounds__(64 * (256 / RW)) void k_residual_bf6_lds(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
     const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
     int p, int nrb, int ncb, int64_t nrt, double* __restrict__ part_col,
     double* __restrict__ part_scal, const DevParams* __restrict__ prm,
     const DevState* __restrict__ st) {
-    body_residual_bf6_lds<PKMAX>(X, G, Gprev, MS, prow, pk, nu, n, p, nrb, ncb, nrt, part_col,
-                                 part_scal, prm, st, blockIdx.x, gridDim.x);
+    body_residual_bf6_lds<PKMAX, RW>(X, G, Gprev, MS, prow, pk, nu, n, p, nrb, ncb, nrt,
+                                     part_col, part_scal, prm, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -1300,7 +1326,7 @@ __global__ __launch_bounds__(256) void k_residual_bf6_lds(
 // (entries with row <= col) and mirrored, so it is exactly symmetric.
 __device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
-                                                     int n_s_tiles, int p,
+                                                     int n_s_tiles, int wup, int p,
                                                      double* __restrict__ S,
                                                      double* __restrict__ W,
                                                      const DevState* __restrict__ st, int bid_, int nblk_) {
@@ -1312,28 +1338,26 @@ __device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part
     const int ii = (int)((e % per) / bt), jj = (int)(e % bt);
     int bi, bj;
     bool isS;
-    gram_tile(tile, nb, n_s_tiles, bi, bj, isS);
+    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
     const int r = bi * bt + ii, c = bj * bt + jj;
     if (r >= p || c >= p) return;
-    if (isS && r > c) return;
+    const bool mirrored = isS || wup;
+    if (mirrored && r > c) return;
     if (!isS && !W) return;
     double s = 0.0;
     const size_t stride = (size_t)n_tiles * per;
     for (int q = 0; q < nchunks; ++q) s += part[(size_t)q * stride + e];
-    if (isS) {
-        S[(size_t)r * p + c] = s;
-        S[(size_t)c * p + r] = s;
-    } else {
-        W[(size_t)r * p + c] = s;
-    }
+    double* M = isS ? S : W;
+    M[(size_t)r * p + c] = s;
+    if (mirrored) M[(size_t)c * p + r] = s;
 }
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
-                                                     int n_s_tiles, int p,
+                                                     int n_s_tiles, int wup, int p,
                                                      double* __restrict__ S,
                                                      double* __restrict__ W,
                                                      const DevState* __restrict__ st) {
-    body_gram_reduce(part, nchunks, n_tiles, bt, nb, n_s_tiles, p, S, W, st, blockIdx.x, gridDim.x);
+    body_gram_reduce(part, nchunks, n_tiles, bt, nb, n_s_tiles, wup, p, S, W, st, blockIdx.x, gridDim.x);
 }
 
 
@@ -2143,14 +2167,14 @@ __global__ __launch_bounds__(256) void kb_gram(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
     body_gram<T, WM>((const T*)d.X, (const T*)d.g[parity], d.n, d.p, g.nb, g.n_s_tiles,
-                     g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+                     g.n_tiles, g.wup, g.chunk, d.gram_part, d.st, lid_, nb_);
 }
 
 __global__ __launch_bounds__(256) void kb_gram_lds64(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
     body_gram_lds<double>((const double*)d.X, (const double*)d.g[parity], d.n, d.p, g.nb,
-                          g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+                          g.n_s_tiles, g.n_tiles, g.wup, g.chunk, d.gram_part, d.st, lid_, nb_);
 }
 
 template <int WM>
@@ -2158,20 +2182,21 @@ __global__ __launch_bounds__(256) void kb_gram_bf3(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
     body_gram_bf3<WM>((const float*)d.X, (const float*)d.g[parity], d.n, d.p, g.nb,
-                      g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+                      g.n_s_tiles, g.n_tiles, g.wup, g.chunk, d.gram_part, d.st, lid_, nb_);
 }
 
 __global__ __launch_bounds__(256) void kb_gram_bf3_lds(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
     body_gram_bf3_lds((const float*)d.X, (const float*)d.g[parity], d.n, d.p, g.nb,
-                      g.n_s_tiles, g.n_tiles, g.chunk, d.gram_part, d.st, lid_, nb_);
+                      g.n_s_tiles, g.n_tiles, g.wup, g.chunk, d.gram_part, d.st, lid_, nb_);
 }
 
 __global__ __launch_bounds__(256) void kb_gram_reduce(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
-    body_gram_reduce(d.gram_part, g.nchunks, g.n_tiles, g.bt, g.nb, g.n_s_tiles, d.p, d.S, d.W,
+    body_gram_reduce(d.gram_part, g.nchunks, g.n_tiles, g.bt, g.nb, g.n_s_tiles, g.wup, d.p,
+                     d.S, d.W,
                      d.st, lid_, nb_);
 }
 
@@ -2203,11 +2228,11 @@ __global__ __launch_bounds__(512) void kb_residual(STF_BATCH_ARGS) {
 }
 
 template <int PKMAX>
-__global__ __launch_bounds__(256) void kb_residual_bf6_lds(STF_BATCH_ARGS) {
+__global__ __launch_bounds__(64 * (256 / kMixRW)) void kb_residual_bf6_lds(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const ResPlan& r = d.res;
     const int prow = r.ncb * 64, pk = (d.p + 31) / 32 * 32;
-    body_residual_bf6_lds<PKMAX>((const float*)d.X, (float*)d.g[parity],
+    body_residual_bf6_lds<PKMAX, kMixRW>((const float*)d.X, (float*)d.g[parity],
                                  (const float*)d.g[parity ^ 1], d.mix, prow, pk, d.nu, d.n,
                                  d.p, r.nrb, r.ncb, r.nrt, d.res_col, d.res_scal, d.prm, d.st,
                                  lid_, nb_);
@@ -2356,35 +2381,38 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
 
 template <typename T>
 static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n, int p,
-                          double* part, const DevState* st, hipStream_t s, int n_tiles) {
+                          double* part, const DevState* st, hipStream_t s, int n_tiles,
+                          int wup) {
     const unsigned nwg = (unsigned)(n_tiles * gp.nchunks);
     switch (gp.wm) {
         case 1:
-            k_gram<T, 1><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+            k_gram<T, 1><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, wup, gp.chunk,
                                               part, st);
             break;
         case 2:
-            k_gram<T, 2><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, gp.chunk,
+            k_gram<T, 2><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles, wup, gp.chunk,
                                               part, st);
             break;
         default:
             // float64: LDS-staged with prefetch; float32: direct fragment loads measured faster
             if (sizeof(T) == 8)
                 k_gram_lds<T><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles,
-                                                   gp.chunk, part, st);
+                                                   wup, gp.chunk, part, st);
             else
                 k_gram<T, 4><<<nwg, 256, 0, s>>>(X, G, n, p, gp.nb, gp.n_s_tiles, n_tiles,
-                                                  gp.chunk, part, st);
+                                                  wup, gp.chunk, part, st);
             break;
     }
 }
 
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, const void* G,
                  int64_t n, int p, double* part, double* S, double* W, const DevState* st,
-                 hipStream_t s, hipEvent_t after_main) {
-    // tiles: the upper blocks of S (when S is wanted) followed by all blocks of W
+                 hipStream_t s, hipEvent_t after_main, bool w_sym) {
+    // tiles: the upper blocks of S (when S is wanted) followed by the blocks of W
+    // (the upper ones only when W is known to be symmetric)
     const int nst = S ? gp.n_s_tiles : 0;
-    const int n_tiles = nst + (W ? gp.nb * gp.nb : 0);
+    const int wup = (W && w_sym) ? 1 : 0;
+    const int n_tiles = nst + (W ? (wup ? gp.n_s_tiles : gp.nb * gp.nb) : 0);
     if (n_tiles == 0) return;
     GramPlan g2 = gp;
     g2.n_s_tiles = nst;
@@ -2393,21 +2421,25 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
         const float* x = (const float*)X;
         const float* gg = (const float*)G;
         if (gp.wm == 1)
-            k_gram_bf3<1><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
+            k_gram_bf3<1><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
+                                              part, st);
         else if (gp.wm == 2)
-            k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part, st);
+            k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
+                                              part, st);
         else
-            k_gram_bf3_lds<<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, gp.chunk, part,
-                                               st);
+            k_gram_bf3_lds<<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
+                                               part, st);
     } else if (dtype == STF_F64) {
-        gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles);
+        gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles,
+                              wup);
     } else {
-        gram_dispatch<float>(g2, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles);
+        gram_dispatch<float>(g2, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles,
+                             wup);
     }
     if (after_main) (void)hipEventRecord(after_main, s);
     const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
     k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
-                                                                 gp.nb, nst, p, S, W, st);
+                                                                 gp.nb, nst, wup, p, S, W, st);
 }
 
 void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
@@ -2440,15 +2472,15 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
         if (rp.tile == 256) {
             // M_L slice resident in LDS (plans of this shape only exist for pk <= 384)
             if (pk <= 128)
-                k_residual_bf6_lds<128><<<nwg, 256, 0, s>>>(
+                k_residual_bf6_lds<128, kMixRW><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
                     (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
                     rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
             else if (pk <= 256)
-                k_residual_bf6_lds<256><<<nwg, 256, 0, s>>>(
+                k_residual_bf6_lds<256, kMixRW><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
                     (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
                     rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
             else
-                k_residual_bf6_lds<384><<<nwg, 256, 0, s>>>(
+                k_residual_bf6_lds<384, kMixRW><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
                     (const float*)X, (float*)G, (const float*)Gprev, MS, prow, pk, nu, n, p,
                     rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm, st);
             return;
@@ -2615,11 +2647,11 @@ void launch_batched(int stage, int dtype, int precision, int variant_key, const 
         case BS_RESID:
             if (mixed) {
                 if (variant_key <= 128)
-                    kb_residual_bf6_lds<128><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                    kb_residual_bf6_lds<128><<<g, 64 * (256 / kMixRW), 0, s>>>(d, L, O, c, parity);
                 else if (variant_key <= 256)
-                    kb_residual_bf6_lds<256><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                    kb_residual_bf6_lds<256><<<g, 64 * (256 / kMixRW), 0, s>>>(d, L, O, c, parity);
                 else
-                    kb_residual_bf6_lds<384><<<g, 256, 0, s>>>(d, L, O, c, parity);
+                    kb_residual_bf6_lds<384><<<g, 64 * (256 / kMixRW), 0, s>>>(d, L, O, c, parity);
             } else if (f64) {
                 kb_residual<double><<<g, 512, 0, s>>>(d, L, O, c, parity);
             } else {
