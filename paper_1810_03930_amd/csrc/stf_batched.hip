@@ -6,7 +6,10 @@
 // workgroups find their problem through a prefix table, and each problem keeps
 // its own device state, so a converged problem's workgroups return at once.
 // A chunk of iterations is captured once as a HIP graph and replayed; the host
-// reads every problem's state once per chunk and stops when all are done.
+// reads every problem's state once per chunk and stops when all are done.  In
+// the float32 forms a problem that reaches its switch_tol stops; once all are
+// done, those continue together in float64 (kernels and groups of the float64
+// form, each from its float64 master iterate), as a single solve does.
 // Tile shapes per problem: the Gram bucket (MFMA tiles per wave) follows p;
 // the number of split-K chunks and residual row blocks follows the problem's
 // share of the batch's n p^2 work, from a batch-wide workgroup budget that
@@ -44,6 +47,9 @@ struct BatchPlan {
     std::vector<ResPlan> res;
     std::vector<int32_t> nblk_rows;
     std::vector<Group> groups[BS_ROWSQ + 1];
+    // float32 forms: the float64 continuation after a hand-over (switch_tol)
+    std::vector<ResPlan> res64;
+    std::vector<Group> groups64[BS_ROWSQ + 1];
     size_t desc = 0;                // BDesc[nprob]
     size_t states = 0;              // DevState[nprob]: gathered device states
     size_t tables = 0, table_bytes = 0;
@@ -66,7 +72,6 @@ int batch_check(int32_t nprob, const stf_problem* probs, const stf_options* opts
             const stf_options& o = opts[b];
             // one storage dtype and kernel set for the whole batch
             if (o.precision != prec) return STF_E_INVALID;
-            if (o.switch_tol > 0.0) return STF_E_UNSUPPORTED;
             if (o.variant != STF_PLAM && o.variant != STF_PCAL) return STF_E_INVALID;
             if (o.mult_rule != STF_MULT_PSI && o.mult_rule != STF_MULT_PSI_PHI)
                 return STF_E_INVALID;
@@ -106,6 +111,7 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
     P.L.resize(nprob);
     P.gram.resize(nprob);
     P.res.resize(nprob);
+    P.res64.resize(nprob);
     P.nblk_rows.resize(nprob);
     P.pbase.resize(nprob);
     for (int b = 0; b < nprob; ++b) {
@@ -117,6 +123,11 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         const GramPlan g0 = make_gram_plan(pr.n, pr.p, 1024, true);
         const int64_t tg = std::max<int64_t>(g0.n_tiles, (int64_t)llround(bg * share));
         P.gram[b] = make_gram_plan(pr.n, pr.p, std::min<int64_t>(tg, 1024), true);
+        {
+            const ResPlan r0 = make_res_plan(pr.n, pr.p, 128);
+            const int64_t tr = std::max<int64_t>(r0.ncb, (int64_t)llround(kResBudget * share));
+            P.res64[b] = make_res_plan(pr.n, pr.p, 128, std::min<int64_t>(tr, 1024));
+        }
         if (mixed) {
             const ResPlan r0 = make_res_plan(pr.n, pr.p, 256);
             const int64_t tr = std::max<int64_t>(r0.ncb, (int64_t)llround(br * share));
@@ -130,7 +141,9 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         const int64_t want = std::max<int64_t>(1, ((int64_t)pr.n * pr.p + 8191) / 8192);
         P.nblk_rows[b] = (int32_t)std::min<int64_t>(std::min<int64_t>(rows4, want), 65536);
     }
-    // grouped-launch tables
+    // grouped-launch tables, for the batch's form and (float32 forms) for the
+    // float64 continuation
+    std::vector<Group>* G = nullptr;
     auto add = [&](int stage, int key, const std::vector<int>& members,
                    const std::vector<int32_t>& wgs) {
         Group g;
@@ -141,7 +154,7 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
             g.list.push_back(members[i]);
             g.off.push_back(g.off.back() + wgs[i]);
         }
-        if (!g.list.empty()) P.groups[stage].push_back(g);
+        if (!g.list.empty()) G[stage].push_back(g);
     };
     std::vector<int> all(nprob), hart;
     std::iota(all.begin(), all.end(), 0);
@@ -152,54 +165,63 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         for (int b : m) w.push_back((int32_t)f(b));
         return w;
     };
-    add(BS_HARTREE, 0, hart, wg_of(hart, [&](int) { return 1; }));
-    add(BS_ROWSQ, 0, hart, wg_of(hart, [&](int b) { return P.nblk_rows[b]; }));
-    add(BS_GRAD, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
-    for (int wm : {1, 2, 4}) {
-        std::vector<int> m;
-        for (int b = 0; b < nprob; ++b)
-            if (P.gram[b].wm == wm) m.push_back(b);
-        add(BS_GRAM, wm, m, wg_of(m, [&](int b) { return P.gram[b].n_tiles * P.gram[b].nchunks; }));
-    }
-    add(BS_REDUCE, 0, all, wg_of(all, [&](int b) {
-            const GramPlan& g = P.gram[b];
-            return ((int64_t)g.n_tiles * g.bt * g.bt + 255) / 256;
-        }));
-    add(BS_STAGE1, 0, all, wg_of(all, [&](int b) { return probs[b].p; }));
-    add(BS_PPGEMM, 0, all, wg_of(all, [&](int b) {
-            const int t = (probs[b].p + 15) / 16;
-            return 2 * t * t;
-        }));
-    if (mixed) {
-        add(BS_SPLIT, 0, all, wg_of(all, [&](int b) {
-                const int64_t prow = (int64_t)P.res[b].ncb * 64, pk = (probs[b].p + 31) / 32 * 32;
-                return (prow * pk + 255) / 256;
-            }));
-        for (int pkmax : {128, 256, 384}) {
+    auto build = [&](bool mx, const std::vector<ResPlan>& RP) {
+        add(BS_HARTREE, 0, hart, wg_of(hart, [&](int) { return 1; }));
+        add(BS_ROWSQ, 0, hart, wg_of(hart, [&](int b) { return P.nblk_rows[b]; }));
+        add(BS_GRAD, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
+        for (int wm : {1, 2, 4}) {
             std::vector<int> m;
-            for (int b = 0; b < nprob; ++b) {
-                const int pk = (probs[b].p + 31) / 32 * 32;
-                const int key = pk <= 128 ? 128 : (pk <= 256 ? 256 : 384);
-                if (key == pkmax) m.push_back(b);
-            }
-            add(BS_RESID, pkmax, m, wg_of(m, [&](int b) { return P.res[b].nrb * P.res[b].ncb; }));
+            for (int b = 0; b < nprob; ++b)
+                if (P.gram[b].wm == wm) m.push_back(b);
+            add(BS_GRAM, wm, m, wg_of(m, [&](int b) { return P.gram[b].n_tiles * P.gram[b].nchunks; }));
         }
-    } else {
-        add(BS_RESID, 0, all, wg_of(all, [&](int b) { return P.res[b].nrb * P.res[b].ncb; }));
+        add(BS_REDUCE, 0, all, wg_of(all, [&](int b) {
+                const GramPlan& g = P.gram[b];
+                return ((int64_t)g.n_tiles * g.bt * g.bt + 255) / 256;
+            }));
+        add(BS_STAGE1, 0, all, wg_of(all, [&](int b) { return probs[b].p; }));
+        add(BS_PPGEMM, 0, all, wg_of(all, [&](int b) {
+                const int t = (probs[b].p + 15) / 16;
+                return 2 * t * t;
+            }));
+        if (mx) {
+            add(BS_SPLIT, 0, all, wg_of(all, [&](int b) {
+                    const int64_t prow = (int64_t)RP[b].ncb * 64, pk = (probs[b].p + 31) / 32 * 32;
+                    return (prow * pk + 255) / 256;
+                }));
+            for (int pkmax : {128, 256, 384}) {
+                std::vector<int> m;
+                for (int b = 0; b < nprob; ++b) {
+                    const int pk = (probs[b].p + 31) / 32 * 32;
+                    const int key = pk <= 128 ? 128 : (pk <= 256 ? 256 : 384);
+                    if (key == pkmax) m.push_back(b);
+                }
+                add(BS_RESID, pkmax, m, wg_of(m, [&](int b) { return RP[b].nrb * RP[b].ncb; }));
+            }
+        } else {
+            add(BS_RESID, 0, all, wg_of(all, [&](int b) { return RP[b].nrb * RP[b].ncb; }));
+        }
+        add(BS_COLRED, 0, all, wg_of(all, [&](int b) { return (2 * probs[b].p + 31) / 32; }));
+        add(BS_STAGE2, 0, all, wg_of(all, [&](int) { return 1; }));
+        add(BS_UPDATE, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
+    };
+    G = P.groups;
+    build(mixed, P.res);
+    if (P.dtype == STF_F32) {
+        G = P.groups64;
+        build(false, P.res64);
     }
-    add(BS_COLRED, 0, all, wg_of(all, [&](int b) { return (2 * probs[b].p + 31) / 32; }));
-    add(BS_STAGE2, 0, all, wg_of(all, [&](int) { return 1; }));
-    add(BS_UPDATE, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
     // table storage
     P.tables = off;
     size_t tb = 0;
-    for (auto& gs : P.groups)
-        for (auto& g : gs) {
-            g.dev_list = P.tables + tb;
-            tb += g.list.size() * 4;
-            g.dev_off = P.tables + tb;
-            tb += g.off.size() * 4;
-        }
+    for (auto* GS : {P.groups, P.groups64})
+        for (int st = 0; st <= BS_ROWSQ; ++st)
+            for (auto& g : GS[st]) {
+                g.dev_list = P.tables + tb;
+                tb += g.list.size() * 4;
+                g.dev_off = P.tables + tb;
+                tb += g.off.size() * 4;
+            }
     P.table_bytes = tb;
     off = align256(P.tables + tb);
     for (int b = 0; b < nprob; ++b) P.pbase[b] = take(P.L[b].total);
@@ -207,16 +229,19 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
     return P;
 }
 
-void enqueue_batched_iteration(const BatchPlan& P, char* ws, int parity, hipStream_t s) {
+// One iteration of every problem: the grouped launches of `groups` with the
+// kernels of (dtype, precision).
+void enqueue_batched_iteration(const BatchPlan& P, const std::vector<Group>* groups, int dtype,
+                               int precision, char* ws, int parity, hipStream_t s) {
     const BDesc* d = (const BDesc*)(ws + P.desc);
     auto run = [&](int stage) {
-        for (const Group& g : P.groups[stage]) {
+        for (const Group& g : groups[stage]) {
             BGroup bg;
             bg.list = (const int32_t*)(ws + g.dev_list);
             bg.off = (const int32_t*)(ws + g.dev_off);
             bg.cnt = (int32_t)g.list.size();
             bg.total = g.off.back();
-            launch_batched(stage, P.dtype, P.precision, g.key, d, bg, parity, s);
+            launch_batched(stage, dtype, precision, g.key, d, bg, parity, s);
         }
     };
     run(BS_HARTREE);
@@ -225,7 +250,7 @@ void enqueue_batched_iteration(const BatchPlan& P, char* ws, int parity, hipStre
     run(BS_REDUCE);
     run(BS_STAGE1);
     run(BS_PPGEMM);
-    if (P.precision == STF_PREC_MIXED) run(BS_SPLIT);
+    if (precision == STF_PREC_MIXED) run(BS_SPLIT);
     run(BS_RESID);
     run(BS_COLRED);
     run(BS_STAGE2);
@@ -282,11 +307,14 @@ int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
     HIPCHK(hipMemcpyAsync(ws + P.desc, hd.data(), sizeof(BDesc) * hd.size(),
                           hipMemcpyHostToDevice, s));
     htab.assign(P.table_bytes / 4, 0);
-    for (const auto& gs : P.groups)
-        for (const auto& g : gs) {
-            memcpy((char*)htab.data() + (g.dev_list - P.tables), g.list.data(), g.list.size() * 4);
-            memcpy((char*)htab.data() + (g.dev_off - P.tables), g.off.data(), g.off.size() * 4);
-        }
+    for (const auto* GS : {P.groups, P.groups64})
+        for (int st = 0; st <= BS_ROWSQ; ++st)
+            for (const auto& g : GS[st]) {
+                memcpy((char*)htab.data() + (g.dev_list - P.tables), g.list.data(),
+                       g.list.size() * 4);
+                memcpy((char*)htab.data() + (g.dev_off - P.tables), g.off.data(),
+                       g.off.size() * 4);
+            }
     if (P.table_bytes)
         HIPCHK(hipMemcpyAsync(ws + P.tables, htab.data(), P.table_bytes, hipMemcpyHostToDevice,
                               s));
@@ -307,7 +335,7 @@ int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
         q.max_iter = opt->max_iter;
         q.kkt_every = opt->kkt_every;
         q.kkt_identity = 1;
-        q.switch_tol = 0.0;
+        q.switch_tol = (P.dtype == STF_F32) ? std::max(0.0, opt->switch_tol) : 0.0;
         q.history = nullptr;
         HIPCHK(hipMemcpyAsync(hd[b].prm, &q, sizeof(q), hipMemcpyHostToDevice, s));
         launch_init_state(hd[b].st, s);
@@ -359,53 +387,100 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
     HIPCHK(hipEventRecord(e0, s));
     int chunk = std::max(1, opt->check_every);
     if (opt->use_graph && (chunk & 1)) chunk += 1;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    if (opt->use_graph && s != nullptr) {
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < chunk; ++i) enqueue_batched_iteration(P, w, i & 1, s);
-        if (hipStreamEndCapture(s, &graph) != hipSuccess) return STF_E_HIP;
-        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(graph);
-            return STF_E_HIP;
-        }
-    }
     std::vector<DevState> hs(nprob);
     int64_t limit = 1;
     for (int b = 0; b < nprob; ++b) limit = std::max<int64_t>(limit, (int64_t)opts[b].max_iter + 1);
-    int64_t enq = 0;
-    int err = 0;
     int64_t iters_run = 0;
-    while (true) {
-        if (gexec) {
-            if (hipGraphLaunch(gexec, s) != hipSuccess) { err = 1; break; }
-            enq += chunk;
-        } else {
-            const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
-            for (int i = 0; i < todo; ++i) enqueue_batched_iteration(P, w, (int)((enq + i) & 1), s);
-            enq += todo;
-            if (last_launch()) { err = 1; break; }
+
+    // Enqueue iterations of every problem with the given groups and kernels
+    // until every problem is done; returns nonzero on a HIP error.
+    auto run_phase = [&](const std::vector<Group>* groups, int dtype, int precision) -> int {
+        hipGraphExec_t gexec = nullptr;
+        hipGraph_t graph = nullptr;
+        if (opt->use_graph && s != nullptr) {
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
+            for (int i = 0; i < chunk; ++i)
+                enqueue_batched_iteration(P, groups, dtype, precision, w, i & 1, s);
+            if (hipStreamEndCapture(s, &graph) != hipSuccess) return 1;
+            if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphDestroy(graph);
+                return 1;
+            }
         }
-        bool all = true;
-        launch_gather_states((const BDesc*)(w + P.desc), nprob, (DevState*)(w + P.states), s);
-        if (hipMemcpyAsync(hs.data(), w + P.states, sizeof(DevState) * (size_t)nprob,
-                           hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            err = 1;
-            break;
+        int64_t enq = 0;
+        int err = 0;
+        while (true) {
+            if (gexec) {
+                if (hipGraphLaunch(gexec, s) != hipSuccess) { err = 1; break; }
+                enq += chunk;
+            } else {
+                const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
+                for (int i = 0; i < todo; ++i)
+                    enqueue_batched_iteration(P, groups, dtype, precision, w,
+                                              (int)((enq + i) & 1), s);
+                enq += todo;
+                if (last_launch()) { err = 1; break; }
+            }
+            bool all = true;
+            launch_gather_states((const BDesc*)(w + P.desc), nprob, (DevState*)(w + P.states),
+                                 s);
+            if (hipMemcpyAsync(hs.data(), w + P.states, sizeof(DevState) * (size_t)nprob,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                err = 1;
+                break;
+            }
+            int64_t mx = 0;
+            for (int b = 0; b < nprob; ++b) {
+                all = all && hs[b].done;
+                mx = std::max<int64_t>(mx, hs[b].done ? hs[b].final_iter : hs[b].iter);
+            }
+            iters_run = mx;
+            if (all) break;
+            if (enq > limit + 2 * chunk) { err = 1; break; }
         }
-        int64_t mx = 0;
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (graph) hipGraphDestroy(graph);
+        return err;
+    };
+
+    if (run_phase(P.groups, P.dtype, P.precision)) return STF_E_HIP;
+    std::vector<int> switched(nprob, -1);
+    bool any_switch = false;
+    for (int b = 0; b < nprob; ++b)
+        if (hs[b].done && hs[b].status == STF_SWITCH) {
+            switched[b] = hs[b].final_iter;
+            any_switch = true;
+        }
+    if (any_switch) {
+        // Float64 continuation (see stf_solve): every problem now iterates on its
+        // float64 master with float64 kernels; problems that did not hand over
+        // are done and their workgroups return at once.  The batch restarts at
+        // parity 0, so buffer 0 takes the redone iteration's G and buffer 1 the
+        // previous gradL (float32, exact in float64).
         for (int b = 0; b < nprob; ++b) {
-            all = all && hs[b].done;
-            mx = std::max<int64_t>(mx, hs[b].done ? hs[b].final_iter : hs[b].iter);
+            const Layout& L = P.L[b];
+            char* base = w + P.pbase[b];
+            BDesc& d = hd[b];
+            d.X = d.Xm;
+            d.Xm = nullptr;
+            d.g[0] = base + L.g64;
+            d.g[1] = base + L.g64b;
+            d.res = P.res64[b];
+            const int k = switched[b];
+            if (k < 0) continue;
+            if (k >= 1)
+                launch_convert(STF_F64, base + L.g[(k - 1) & 1], STF_F32, d.g[1],
+                               (size_t)d.n * d.p, s);
+            hpv[b].switch_tol = 0.0;
+            HIPCHK(hipMemcpyAsync(d.prm, &hpv[b], sizeof(DevParams), hipMemcpyHostToDevice, s));
+            launch_resume_state(d.st, s);
         }
-        iters_run = mx;
-        if (all) break;
-        if (enq > limit + 2 * chunk) { err = 1; break; }
+        HIPCHK(hipMemcpyAsync(w + P.desc, hd.data(), sizeof(BDesc) * hd.size(),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (run_phase(P.groups64, STF_F64, STF_PREC_FP64)) return STF_E_HIP;
     }
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
-    if (err) return STF_E_HIP;
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms_loop = 0.f;
@@ -421,7 +496,7 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
         r.kkt0 = hs[b].kkt0;
         r.eta_last = hs[b].eta;
         r.ms_loop = ms_loop;
-        r.switch_iter = -1;
+        r.switch_iter = switched[b];
         if (hs[b].status == STF_E_DIVERGED) {
             r.kkt_abs = r.kkt_rel = r.feas = r.fval = NAN;
             worst = STF_E_DIVERGED;
@@ -432,7 +507,8 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
         pw.L = P.L[b];
         const int64_t n = probs[b].n;
         const int p = probs[b].p;
-        double* Xd = (P.dtype == STF_F64) ? (double*)X[b] : hd[b].Xm;
+        double* Xd = (P.dtype == STF_F64) ? (double*)X[b]
+                                          : pw.at<double>(pw.L.x64);  // the float64 master
         double* tmp = (P.dtype == STF_F64) ? pw.at<double>(pw.L.g[1]) : pw.at<double>(pw.L.g64);
         DevState* st_eval = pw.at<DevState>(pw.L.state_eval);
         launch_init_state(st_eval, s);

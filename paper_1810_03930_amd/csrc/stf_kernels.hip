@@ -261,6 +261,80 @@ __global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
     out[e] = s;
 }
 
+// The same 3D solve in three passes with the planes staged in LDS (grids with
+// nx, ny, nz <= 64).  k_dst_xy applies S_x along x and S_y along y to one
+// z-plane per workgroup: out_plane = S_y in_plane S_x^T (S symmetric);
+// k_dst_z applies, for one y and all x, S_z along z, the division by
+// lx + ly + lz and S_z again (the forward and inverse z transforms fused).
+// 1024 threads per workgroup: one workgroup per plane or slab (64 of them on
+// 64^3) must hide its own LDS and global latencies.
+constexpr int kDstMax = 64;
+__global__ __launch_bounds__(1024) void k_dst_xy(const double* __restrict__ in,
+                                                double* __restrict__ out,
+                                                const double* __restrict__ Sx,
+                                                const double* __restrict__ Sy, int nx, int ny,
+                                                const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double A[kDstMax * kDstMax], T[kDstMax * kDstMax];
+    __shared__ double Mx[kDstMax * kDstMax], My[kDstMax * kDstMax];
+    const int nxy = nx * ny;
+    const double* src = in + (size_t)blockIdx.x * nxy;
+    double* dst = out + (size_t)blockIdx.x * nxy;
+    for (int e = threadIdx.x; e < nxy; e += blockDim.x) A[e] = src[e];
+    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) Mx[e] = Sx[e];
+    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) My[e] = Sy[e];
+    __syncthreads();
+    // T[y][k] = sum_x A[y][x] Sx[k][x]; S is symmetric, so Sx[x][k] is read
+    // (consecutive lanes, consecutive k: no bank conflicts)
+    for (int e = threadIdx.x; e < nxy; e += blockDim.x) {
+        const int y = e / nx, k = e % nx;
+        double acc = 0.0;
+        for (int x = 0; x < nx; ++x) acc += A[y * nx + x] * Mx[x * nx + k];
+        T[e] = acc;
+    }
+    __syncthreads();
+    // out[k][x] = sum_y Sy[k][y] T[y][x]
+    for (int e = threadIdx.x; e < nxy; e += blockDim.x) {
+        const int k = e / nx, x = e % nx;
+        double acc = 0.0;
+        for (int y = 0; y < ny; ++y) acc += My[k * ny + y] * T[y * nx + x];
+        dst[e] = acc;
+    }
+}
+__global__ __launch_bounds__(1024) void k_dst_z(const double* in, double* out,
+                                               const double* __restrict__ Sz,
+                                               const double* __restrict__ lx,
+                                               const double* __restrict__ ly,
+                                               const double* __restrict__ lz, int nx, int ny,
+                                               int nz, const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double A[kDstMax * kDstMax], U[kDstMax * kDstMax], Mz[kDstMax * kDstMax];
+    const int y = blockIdx.x;
+    const size_t sxy = (size_t)nx * ny;
+    const int nzx = nz * nx;
+    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
+        const int z = e / nx, x = e % nx;
+        A[e] = in[(size_t)z * sxy + (size_t)y * nx + x];
+    }
+    for (int e = threadIdx.x; e < nz * nz; e += blockDim.x) Mz[e] = Sz[e];
+    __syncthreads();
+    // U[k][x] = (sum_z Sz[k][z] A[z][x]) / (lx[x] + ly[y] + lz[k])
+    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
+        const int k = e / nx, x = e % nx;
+        double acc = 0.0;
+        for (int z = 0; z < nz; ++z) acc += Mz[k * nz + z] * A[z * nx + x];
+        U[e] = acc / ((lx[x] + ly[y]) + lz[k]);
+    }
+    __syncthreads();
+    // out[z][x] = sum_k Sz[z][k] U[k][x]
+    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
+        const int z = e / nx, x = e % nx;
+        double acc = 0.0;
+        for (int k = 0; k < nz; ++k) acc += Mz[z * nz + k] * U[k * nx + x];
+        out[(size_t)z * sxy + (size_t)y * nx + x] = acc;
+    }
+}
+
 // ------------------------------------------------------------ gradient ----
 // G = (L + Diag v + alpha Diag phi) X for the 1D (ND = 2 neighbours) and 3D
 // (ND = 6) Dirichlet stencils, computed in the arithmetic of the input X and
@@ -1471,7 +1545,7 @@ __device__ __forceinline__ void body_residual(
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_) {
     if (st && st->done) return;
-    constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
+    constexpr int KC = 32;  // rows of M_L (columns of X) per LDS stage
     constexpr int XS = KC + 1;
     constexpr int MST = 128 + 4;
     constexpr int NT = 128 * WC;       // threads: 2 x WC waves
@@ -2312,6 +2386,14 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi, dou
     const double* lx = Sz + (size_t)nz * nz;
     const double* ly = lx + nx;
     const double* lz = ly + ny;
+    if (nx <= kDstMax && ny <= kDstMax && nz <= kDstMax) {
+        // planes in LDS: xy forward, z forward + divide + z inverse (in place:
+        // a workgroup reads its whole slab before writing it), xy inverse
+        k_dst_xy<<<nz, 1024, 0, s>>>(rho, scr, Sx, Sy, nx, ny, st);
+        k_dst_z<<<ny, 1024, 0, s>>>(scr, scr, Sz, lx, ly, lz, nx, ny, nz, st);
+        k_dst_xy<<<nz, 1024, 0, s>>>(scr, phi, Sx, Sy, nx, ny, st);
+        return;
+    }
     const unsigned g = (unsigned)((n + 255) / 256);
     const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
     // forward transform along x, y, z; divide by the eigenvalues; transform back

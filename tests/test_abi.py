@@ -140,9 +140,9 @@ def test_batched_host_checks():
     ptrs = (ctypes.c_void_p * 2)(1, 1)
     assert lib.stf_solve_batched(0, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
                                  vp(res), None) == L.E_INVALID
-    sw = (L.StfOptions * 2)(_valid_options(), _valid_options())
-    sw[1].switch_tol = 1e-3
-    assert lib.stf_solve_batched(2, vp(probs), vp(ptrs), vp(sw), ctypes.c_void_p(1), 1,
+    p3b = (L.StfProblem * 2)(_problem(n=1000, p=10),
+                             _problem(kind=L.KIND_STENCIL3D, n=1000, grid=(10, 10, 10)))
+    assert lib.stf_solve_batched(2, vp(p3b), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
                                  vp(res), None) == L.E_UNSUPPORTED
     assert lib.stf_solve_batched(2, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
                                  vp(res), None) == L.E_WORKSPACE

@@ -134,3 +134,25 @@ def test_batched_tuner_and_budgets():
     _, _, Xb, _ = _run(probs, x0s, gl, budgets=(bg, br))
     for a, b in zip(Xa, Xb):
         assert rel(a, b) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_batched_handover_reaches_fp64_tolerance(precision):
+    """Float32 batches hand each problem over to float64 at switch_tol and
+    finish together in float64, at the oracle's minimum to 1e-8."""
+    probs, x0s = _batch()
+    ol, gl = _opts(probs, precision=precision, max_iter=5000, tol=1e-8, orth=True,
+                   check_every=50)
+    for g in gl:
+        g.switch_tol = 1e-3
+    res, rc, Xs, _ = _run(probs, x0s, gl)
+    print(f"{precision}: switched at", [r["switch_iter"] for r in res],
+          "converged at", [r["iters"] for r in res])
+    assert rc == 0
+    assert all(r["switch_iter"] > 0 for r in res)
+    for prob, x0, o, r in zip(probs, x0s, ol, res):
+        o.max_iter = 5000
+        ref = O.solve(OracleProblem(prob), x0, o)
+        assert ref.status == 0 and r["status"] == 0
+        assert r["kkt_rel"] <= 1.01e-8
+        assert abs(r["fval"] - ref.f) <= 1e-8 * abs(ref.f)

@@ -169,6 +169,14 @@ def batched_ks1d(nprob: int = 256, config: int = 4, n_range=(1000, 20000),
     return probs, x0s
 
 
+def alternate_start(config: int, n: int, p: int, start: int) -> np.ndarray:
+    """Another seeded X0 for the same operator (start >= 1; start 0 is the
+    workload's own X0): the iteration count of the Barzilai-Borwein method
+    varies with the start, so timings to a tolerance are also taken over a few."""
+    rng = np.random.default_rng([SEED_BASE + config, 1000 + start])
+    return orthonormal_start(rng, n, p)
+
+
 def random_matrix(config: int, shape, salt: int = 0) -> np.ndarray:
     """A seeded N(0,1) matrix for unit tests of individual steps."""
     rng = np.random.default_rng([SEED_BASE + config, salt])
