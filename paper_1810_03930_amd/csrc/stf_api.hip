@@ -282,7 +282,7 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
                   w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
     launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
-                        w.at<double>(w.L.T1), w.at<double>(w.L.T2), p, c.st, s);
+                        w.at<double>(w.L.W), w.at<double>(w.L.T1), p, c.st, s);
     const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.mixed_plan() : w.L.res;
     launch_residual(c.dtype, c.precision, rp, c.X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,

@@ -182,7 +182,7 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         add(BS_STAGE1, 0, all, wg_of(all, [&](int b) { return probs[b].p; }));
         add(BS_PPGEMM, 0, all, wg_of(all, [&](int b) {
                 const int t = (probs[b].p + 15) / 16;
-                return 2 * t * t;
+                return t * t;
             }));
         if (mx) {
             add(BS_SPLIT, 0, all, wg_of(all, [&](int b) {

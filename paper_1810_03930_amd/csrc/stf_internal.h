@@ -169,8 +169,9 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
                    DevState* st, hipStream_t s);
-void launch_kkt_products(const double* S, const double* ML, const double* Bm, double* T1,
-                         double* T2, int p, DevState* st, hipStream_t s);
+// per-tile partials of <B, S B - 2 (W - S M_L)> into part[((p+15)/16)^2]
+void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
+                         double* part, int p, DevState* st, hipStream_t s);
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      void* G, const void* Gprev, const double* ML, const double* Psi,
                      const double* nu, int64_t n, int p, double* part_col,

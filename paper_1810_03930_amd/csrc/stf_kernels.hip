@@ -1833,38 +1833,50 @@ __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ pa
 }
 
 
-// T1 = S M_L and T2 = S B for p x p float64 matrices (blockIdx.z selects),
-// the two products of the float64 KKT identity evaluated in stage 2.
+// The p x p part of the float64 KKT identity evaluated in stage 2: for one
+// 16 x 16 tile (bx, by), T1 = S M_L and T2 = S B on the tile, then the tile's
+// share of <B, T2 - 2 (W - T1)> summed in the workgroup and written to
+// part[by * tiles + bx] (T1 and T2 themselves are not stored).
 __device__ __forceinline__ void body_pp_gemm2(const double* __restrict__ S,
                                               const double* __restrict__ M1,
                                               const double* __restrict__ M2,
-                                              double* __restrict__ T1, double* __restrict__ T2,
-                                              int p, const DevState* __restrict__ st, int bx,
-                                              int by, int bz) {
+                                              const double* __restrict__ W,
+                                              double* __restrict__ part, int p,
+                                              const DevState* __restrict__ st, int bx, int by) {
     if (st->done) return;
-    __shared__ double As[16][17], Bs[16][17];
-    const double* B = bz ? M2 : M1;
-    double* C = bz ? T2 : T1;
+    __shared__ double As[16][17], B1[16][17], B2[16][17];
+    __shared__ double sh[4];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int row = by * 16 + ty, col = bx * 16 + tx;
-    double acc = 0.0;
+    double t1 = 0.0, t2 = 0.0;
     for (int k0 = 0; k0 < p; k0 += 16) {
         As[ty][tx] = (row < p && k0 + tx < p) ? S[(size_t)row * p + k0 + tx] : 0.0;
-        Bs[ty][tx] = (k0 + ty < p && col < p) ? B[(size_t)(k0 + ty) * p + col] : 0.0;
+        const bool ok = (k0 + ty < p) && (col < p);
+        B1[ty][tx] = ok ? M1[(size_t)(k0 + ty) * p + col] : 0.0;
+        B2[ty][tx] = ok ? M2[(size_t)(k0 + ty) * p + col] : 0.0;
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc += As[ty][k] * Bs[k][tx];
+        for (int k = 0; k < 16; ++k) {
+            t1 += As[ty][k] * B1[k][tx];
+            t2 += As[ty][k] * B2[k][tx];
+        }
         __syncthreads();
     }
-    if (row < p && col < p) C[(size_t)row * p + col] = acc;
+    double c = 0.0;
+    if (row < p && col < p) {
+        const size_t e = (size_t)row * p + col;
+        c = M2[e] * (t2 - 2.0 * (W[e] - t1));
+    }
+    c = block_sum256(c, sh);
+    if (threadIdx.x == 0) part[by * ((p + 15) / 16) + bx] = c;
 }
 __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
                                                   const double* __restrict__ M1,
                                                   const double* __restrict__ M2,
-                                                  double* __restrict__ T1,
-                                                  double* __restrict__ T2, int p,
+                                                  const double* __restrict__ W,
+                                                  double* __restrict__ part, int p,
                                                   const DevState* __restrict__ st) {
-    body_pp_gemm2(S, M1, M2, T1, T2, p, st, blockIdx.x, blockIdx.y, blockIdx.z);
+    body_pp_gemm2(S, M1, M2, W, part, p, st, blockIdx.x, blockIdx.y);
 }
 
 // -------------------------------------------------------- p x p stage 2 ----
@@ -1898,9 +1910,9 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
     for (int i = t; i < p; i += blockDim.x) v[4] += feas_part[i];
     if (ident) {
         for (int i = t; i < p; i += blockDim.x) v[5] += colgg[i];
-        const size_t p2 = (size_t)p * p;
-        for (size_t e = t; e < p2; e += blockDim.x)
-            v[6] += Bm[e] * (T2[e] - 2.0 * (W[e] - T1[e]));
+        // tile partials of <B, S B - 2 (W - S M_L)> from the p x p product pass
+        const int nt = (p + 15) / 16;
+        for (int e = t; e < nt * nt; e += blockDim.x) v[6] += T1[e];
     }
 #pragma unroll
     for (int q = 0; q < 7; ++q) sr[q][t] = v[q];
@@ -2282,8 +2294,7 @@ __global__ __launch_bounds__(256) void kb_stage1(STF_BATCH_ARGS) {
 __global__ __launch_bounds__(256) void kb_pp_gemm2(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const int t = (d.p + 15) / 16;
-    body_pp_gemm2(d.S, d.ML, d.Bm, d.T1, d.T2, d.p, d.st, lid_ % t, (lid_ / t) % t,
-                  lid_ / (t * t));
+    body_pp_gemm2(d.S, d.ML, d.Bm, d.W, d.T1, d.p, d.st, lid_ % t, lid_ / t);
 }
 
 __global__ __launch_bounds__(256) void kb_split3(STF_BATCH_ARGS) {
@@ -2530,10 +2541,10 @@ void launch_stage1(const DevParams* prm, const double* S, const double* W, doubl
     k_stage1<<<p, 256, 0, s>>>(prm, S, W, Psi, ML, Bm, feas_part, p, st);
 }
 
-void launch_kkt_products(const double* S, const double* ML, const double* Bm, double* T1,
-                         double* T2, int p, DevState* st, hipStream_t s) {
-    dim3 grid((p + 15) / 16, (p + 15) / 16, 2);
-    k_pp_gemm2<<<grid, 256, 0, s>>>(S, ML, Bm, T1, T2, p, st);
+void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
+                         double* part, int p, DevState* st, hipStream_t s) {
+    dim3 grid((p + 15) / 16, (p + 15) / 16);
+    k_pp_gemm2<<<grid, 256, 0, s>>>(S, ML, Bm, W, part, p, st);
 }
 
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X, void* G,
