@@ -38,8 +38,9 @@ BETA = 4.0          # PCAL penalty for the 3D KS workload (above its p-th eigenv
 TOL = 1e-6
 SWITCH_TOL = 2e-5   # relative KKT at which the fast form continues in float64
 BATCH_SWITCH_TOL = 1e-3
-MAX_ITER = 3000
+MAX_ITER = 6000
 HBM_PEAK_GBS = 8000.0
+FORM_DTYPE = {"fp32": "f32", "mixed": "bf16x3/bf16x6 MFMA, f32 storage, f64 master"}
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed_bf16": 2500.0}
 
 
@@ -137,6 +138,9 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
             more.append(r)
     runs = [conv] + more
     ttk_all = [(r["ms_loop"] + r["ms_orth"]) / 1000.0 for r in runs]
+    reached = [r["rc"] == 0 and r["kkt_rel"] <= TOL for r in runs]
+    # a start that did not reach the tolerance counts as infinitely slow
+    med = float(np.median([t if ok else np.inf for t, ok in zip(ttk_all, reached)]))
     out = {
         "iters_per_s": 1000.0 / ms_step,
         "ms_per_step": ms_step,
@@ -155,14 +159,14 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "ms_orth": conv["ms_orth"],
         "time_to_kkt_s_per_start": ttk_all,
         "iters_to_kkt_per_start": [r["iters"] for r in runs],
-        "reached_per_start": [r["rc"] == 0 and r["kkt_rel"] <= TOL for r in runs],
-        "time_to_kkt_s_median": float(np.median(ttk_all)),
+        "reached_per_start": reached,
+        "time_to_kkt_s_median": med if np.isfinite(med) else None,
     }
     return out, x64
 
 
 KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_residual",
-                "update": "k_update", "hartree": "k_dst_axis"}
+                "update": "k_update", "hartree": "k_dst_xy + k_dst_z"}
 # the device function that does the work of each timed kernel, per form
 KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gram_lds",
                ("fp64", "grad"): "body_grad_stencil", ("fp64", "update"): "body_update",
@@ -334,7 +338,7 @@ def batched_main(args, torch, S, W):
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": fast["ms_per_batch_iter"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.fast_form == "fp32" else "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
+        "dtype": FORM_DTYPE[args.fast_form],
         "data": "synthetic",
         "config": {"workload": "256 x 1D Kohn-Sham-shaped PCAL, n~U[1000,20000], "
                                "p~U[8,128], alpha~U[0.5,2], beta = alpha p n / 8 + 10",
@@ -351,7 +355,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--fast-form", default="mixed", choices=["fp32", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--starts", type=int, default=3,
+    ap.add_argument("--starts", type=int, default=5,
                     help="seeded starting points of the time-to-KKT solves (the median is reported)")
     ap.add_argument("--skip-ttk", action="store_true",
                     help="skip the time-to-KKT solves (short runs under hardware counters)")
@@ -413,7 +417,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.fast_form == "fp32" else "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
+        "dtype": FORM_DTYPE[args.fast_form],
         "data": "synthetic",
         "config": {"workload": "3D Kohn-Sham-shaped PCAL, 7-point Dirichlet Laplacian on a "
                                "64^3 grid + Diag(V), V~U(0,1), alpha=1, beta=4, ABB steps",
@@ -426,7 +430,8 @@ def main():
          "starts": args.starts},
         "speedup_time_to_kkt": None if args.skip_ttk else
         base["time_to_kkt_s"] / fast["time_to_kkt_s"],
-        "speedup_time_to_kkt_median": None if args.skip_ttk else
+        "speedup_time_to_kkt_median": None if (args.skip_ttk or not fast["time_to_kkt_s_median"]
+                                               or not base["time_to_kkt_s_median"]) else
         base["time_to_kkt_s_median"] / fast["time_to_kkt_s_median"],
         "forms": forms,
         "roofline": roof,

@@ -74,13 +74,15 @@ extern "C" {
 
 /* arithmetic of the iteration:
  *   FP64  - X, G in float64, float64 MFMA / VALU everywhere;
- *   FP32  - X, G in float32, float32 MFMA products, float64 accumulation of
- *           every reduction over n, float64 p x p stage;
- *   MIXED - as FP32, but the Gram products use split-bf16 (three bf16 MFMA
- *           products, float32 tile accumulation) and the row-block products
- *           use split-fp16 with a power-of-two scale.
- * The p x p multiplier stage, the KKT test and CholeskyQR2 are float64 in
- * every mode. */
+ *   FP32  - X, G in float32 with a float64 master iterate, float32 MFMA
+ *           products, float64 accumulation of every reduction over n,
+ *           float64 p x p stage;
+ *   MIXED - as FP32, but the Gram products use the two-way bf16 split (three
+ *           bf16 MFMA products, float32 tile accumulation) and the row-block
+ *           product X M_L the exact three-way bf16 split (six products).
+ * Both float32 forms stall near relative KKT 5e-6 (see switch_tol).  The
+ * p x p multiplier stage, the KKT test and CholeskyQR2 are float64 in every
+ * mode. */
 #define STF_PREC_FP64  0
 #define STF_PREC_FP32  1
 #define STF_PREC_MIXED 2
@@ -137,7 +139,8 @@ typedef struct stf_problem {
  *               in float64 from the float64 master iterate, with the eta,
  *               column norms and previous gradL carried over, and the solve
  *               continues in float64 (stf_result.switch_iter = k).  The float32
- *               forms stall where rounding noise in G and X M dominates the
+ *               forms stall where the rounding noise of their products (the
+ *               row-block product X M_L and the Grams) dominates the
  *               Barzilai-Borwein quotients; this finishes the descent exactly.
  * history     : device, (max_iter + 1) x 4 float64, or NULL: row k receives
  *               { ||G - X Psi||_F (NaN when the stop test was not due),

@@ -128,6 +128,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         raise RuntimeError(
             f"{path} is missing: build it with `python -m paper_1810_03930_amd.build` "
             "(the HIP library is required; there is no fallback)")
+    try:
+        # bind to the HIP runtime torch has loaded (one runtime per process, so
+        # torch's streams and device pointers are valid in the library)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

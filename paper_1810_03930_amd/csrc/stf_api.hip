@@ -55,7 +55,8 @@ ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg) {
         r.nrb = (int)std::max<int64_t>(nrb, 1);
         return r;
     }
-    r.ncb = (p + tile - 1) / tile;
+    // tile 128: 128-row tiles of 64 columns (float64 / float32 kernels); 64: square
+    r.ncb = (p + 63) / 64;
     r.nrt = (n + tile - 1) / tile;
     const int64_t target = target_wg > 0 ? target_wg : ((tile == 128) ? 1024 : 2048);
     int64_t nrb = (target + r.ncb - 1) / r.ncb;
@@ -109,10 +110,9 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.T2 = take(pp);
     L.fpart = take((size_t)p * 8);
     L.nu = take((size_t)p * 8);
-    L.colxg = take((size_t)p * 8);
-    L.colgg = take((size_t)p * 8);
+    L.colpart = take((size_t)32 * 2 * p * 8);
     // iterations: W symmetric (upper blocks); evaluation / CholeskyQR2 / step API: full
-    L.gram = make_gram_plan(n, p, 1024, true);
+    L.gram = make_gram_plan(n, p, 512, true);   // one round at two workgroups per CU
     L.gram64 = make_gram_plan(n, p);
     {
         // room for any tile set (S upper + all of W) at either plan's chunk count
@@ -292,7 +292,7 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
                   w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Bm),
                   w.at<double>(w.L.T1), w.at<double>(w.L.T2), w.at<double>(w.L.fpart),
-                  w.at<double>(w.L.colxg), w.at<double>(w.L.colgg), w.at<double>(w.L.nu), p, c.st,
+                  w.at<double>(w.L.colpart), w.at<double>(w.L.nu), p, c.st,
                   s);
     mark(6);
     launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s, c.Xm);

@@ -177,7 +177,7 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         }
         add(BS_REDUCE, 0, all, wg_of(all, [&](int b) {
                 const GramPlan& g = P.gram[b];
-                return ((int64_t)g.n_tiles * g.bt * g.bt + 255) / 256;
+                return ((int64_t)g.n_tiles * g.bt * g.bt + 63) / 64;
             }));
         add(BS_STAGE1, 0, all, wg_of(all, [&](int b) { return probs[b].p; }));
         add(BS_PPGEMM, 0, all, wg_of(all, [&](int b) {
@@ -201,7 +201,9 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
         } else {
             add(BS_RESID, 0, all, wg_of(all, [&](int b) { return RP[b].nrb * RP[b].ncb; }));
         }
-        add(BS_COLRED, 0, all, wg_of(all, [&](int b) { return (2 * probs[b].p + 31) / 32; }));
+        add(BS_COLRED, 0, all, wg_of(all, [&](int b) {
+                return (2 * probs[b].p + 63) / 64 * col_groups(RP[b].nrb);
+            }));
         add(BS_STAGE2, 0, all, wg_of(all, [&](int) { return 1; }));
         add(BS_UPDATE, 0, all, wg_of(all, [&](int b) { return P.nblk_rows[b]; }));
     };
@@ -292,8 +294,7 @@ int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
         d.T2 = at(L.T2);
         d.fpart = at(L.fpart);
         d.nu = at(L.nu);
-        d.colxg = at(L.colxg);
-        d.colgg = at(L.colgg);
+        d.colpart = at(L.colpart);
         d.gram_part = at(L.gram_part);
         d.res_col = at(L.res_col);
         d.res_scal = at(L.res_scal);

@@ -61,9 +61,16 @@ struct GramPlan {
 struct ResPlan {
     int tile;        // 128 (float64 / float32), 64 or 256 (split-bf16 kernels)
     int nrb;         // row-block workgroups (each strides over row tiles)
-    int ncb;         // ceil(p / tile) column blocks
+    int ncb;         // ceil(p / 64) column blocks of 64 columns
     int64_t nrt;     // ceil(n / tile) row tiles
 };
+
+// Row-block groups of the column-dot reduction after the residual pass (the
+// last step sums the groups): one group per 64 row blocks, at most 32.
+__host__ __device__ inline int col_groups(int nrb) {
+    const int g = nrb / 64;
+    return g < 1 ? 1 : (g > 32 ? 32 : g);
+}
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
@@ -73,7 +80,7 @@ struct Layout {
     size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
     size_t rho, phi, hscr;
     size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, T2, fpart;
-    size_t nu, colxg, colgg;
+    size_t nu, colpart;   // colpart: col_groups(res.nrb) x 2p column-dot partials
     size_t gram_part;
     size_t res_col, res_scal, dots;
     size_t dst;           // sine tables and 1D eigenvalues (3D Hartree solve)
@@ -98,7 +105,7 @@ struct BDesc {
     double* Xm;        // float64 master iterate (float32 forms), else null
     void* g[2];        // G / gradL double buffer
     double *rho, *phi, *S, *W, *Psi, *ML, *Bm, *T1, *T2, *fpart;
-    double *nu, *colxg, *colgg, *gram_part, *res_col, *res_scal;
+    double *nu, *colpart, *gram_part, *res_col, *res_scal;
     __bf16* mix;
     DevState* st;
     DevParams* prm;
@@ -127,7 +134,7 @@ void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t 
 
 int elem_size(int dtype);
 // target_wg: workgroups the plan aims at (the single-problem defaults when omitted)
-GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 1024, bool wup = false);
+GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 512, bool wup = false);
 ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
 Layout make_layout(const stf_problem* prob, int precision);
 size_t align256(size_t x);
@@ -180,7 +187,7 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* W,
                    const double* Bm, const double* T1, const double* T2,
-                   const double* feas_part, double* colxg, double* colgg, double* nu,
+                   const double* feas_part, double* colpart, double* nu,
                    int p, DevState* st, hipStream_t s);
 // Xm (float32 X only): float64 master iterate, read and written; X gets its rounding
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,

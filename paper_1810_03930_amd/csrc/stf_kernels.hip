@@ -698,7 +698,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
             }
 }
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_lds(const T* __restrict__ X,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gram_lds(const T* __restrict__ X,
                                                   const T* __restrict__ G, int64_t n, int p,
                                                   int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
@@ -1405,25 +1405,42 @@ __device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part
                                                      double* __restrict__ W,
                                                      const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
-    const int64_t e = (int64_t)bid_ * blockDim.x + threadIdx.x;
+    // 64 consecutive tile elements per workgroup; wave w sums the chunks
+    // q = w (mod 4), two loads in flight, and wave 0 adds the four slices
+    __shared__ double sred[4][64];
+    const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
     const int64_t per = (int64_t)bt * bt;
-    if (e >= per * n_tiles) return;
-    const int tile = (int)(e / per);
-    const int ii = (int)((e % per) / bt), jj = (int)(e % bt);
-    int bi, bj;
-    bool isS;
-    gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
-    const int r = bi * bt + ii, c = bj * bt + jj;
-    if (r >= p || c >= p) return;
-    const bool mirrored = isS || wup;
-    if (mirrored && r > c) return;
-    if (!isS && !W) return;
-    double s = 0.0;
-    const size_t stride = (size_t)n_tiles * per;
-    for (int q = 0; q < nchunks; ++q) s += part[(size_t)q * stride + e];
+    const int64_t e = (int64_t)bid_ * 64 + lane;
+    bool live = e < per * n_tiles;
+    int r = 0, c = 0;
+    bool isS = false, mirrored = false;
+    if (live) {
+        const int tile = (int)(e / per);
+        const int ii = (int)((e % per) / bt), jj = (int)(e % bt);
+        int bi, bj;
+        gram_tile(tile, nb, n_s_tiles, wup, bi, bj, isS);
+        r = bi * bt + ii;
+        c = bj * bt + jj;
+        mirrored = isS || wup;
+        live = r < p && c < p && !(mirrored && r > c) && (isS || W);
+    }
+    double s0 = 0.0, s1 = 0.0;
+    if (live) {
+        const size_t stride = (size_t)n_tiles * per;
+        int q = slice;
+        for (; q + 4 < nchunks; q += 8) {
+            s0 += part[(size_t)q * stride + e];
+            s1 += part[(size_t)(q + 4) * stride + e];
+        }
+        if (q < nchunks) s0 += part[(size_t)q * stride + e];
+    }
+    sred[slice][lane] = s0 + s1;
+    __syncthreads();
+    if (slice != 0 || !live) return;
+    const double sum = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
     double* M = isS ? S : W;
-    M[(size_t)r * p + c] = s;
-    if (mirrored) M[(size_t)c * p + r] = s;
+    M[(size_t)r * p + c] = sum;
+    if (mirrored) M[(size_t)c * p + r] = sum;
 }
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
@@ -1530,38 +1547,43 @@ __global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ pr
 
 
 // ------------------------------------------------------ residual pass ------
-// For a 128 x 128 tile of rows x columns (four waves of 64 x 64; X and M_L
-// staged through LDS in K-chunks):  gradL = G - X M_L  (written over G), and,
+// Columns per workgroup of the float64 / float32 residual kernels: 128 x 64
+// tiles keep a wave's accumulators at 64 x 32, so two independent 4-wave
+// workgroups share each CU and one's epilogue overlaps the other's MFMAs.
+constexpr int kResBC = 64;
+// For a tile of 128 rows x kResBC columns (2 x WC waves; X and M_L staged
+// through LDS in K-chunks):  gradL = G - X M_L  (written over G), and,
 // when KKT and the stop test is due, R = G - X Psi with ||R||_F^2 accumulated.
 // The Barzilai-Borwein pair uses the stored gradL^{k-1} (in Gprev) and the
 // identity X^{k-1} = nu^{k-1} X^k + gradL^{k-1} / eta^{k-1} (the PCAL scaling
 // undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
-template <typename T, bool APPLY, bool KKT, int WC>
+template <typename T, typename TG, bool APPLY, bool KKT, int WC>
 __device__ __forceinline__ void body_residual(
-    const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
+    const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_) {
     if (st && st->done) return;
-    constexpr int KC = 32;  // rows of M_L (columns of X) per LDS stage
+    constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // rows of M_L (columns of X) per LDS stage
     constexpr int XS = KC + 1;
-    constexpr int MST = 128 + 4;
+    constexpr int BC = kResBC;         // columns per workgroup
+    constexpr int MST = BC + 4;
     constexpr int NT = 128 * WC;       // threads: 2 x WC waves
-    constexpr int WTC = 128 / WC;      // columns per wave
+    constexpr int WTC = BC / WC;       // columns per wave
     constexpr int JT = WTC / 16;       // 16-column MFMA tiles per wave
     __shared__ T Xs[128 * XS];
     __shared__ T Ms[KC * MST];
     __shared__ double sh[2 * WC];
-    __shared__ double scol[2][2][128];
+    __shared__ double scol[2][2][BC];
     const int nwg = nblk_;
     const int lid = xcd_remap(bid_, nwg);
     const int rb = lid / ncb, cb = lid % ncb;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, wr = wave / WC, wc = wave % WC;
     const int lr = lane & 15, lk = lane >> 4;
-    const int cblk = cb * 128;
+    const int cblk = cb * BC;
     const int c0 = cblk + wc * WTC;
 
     // KKT instantiations run only the stop-test product R = G - X Psi
@@ -1588,11 +1610,11 @@ __device__ __forceinline__ void body_residual(
         cok[j] = c < p;
         onu[j] = (!APPLY && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
     }
-    // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x 128),
+    // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x BC),
     // 16-byte vectors when the row pitch allows it, prefetched one chunk ahead
     constexpr int VX = 16 / (int)sizeof(T);          // elements of X per 16-byte load
     constexpr int NXV = 128 * KC / VX / NT;          // X vectors per thread
-    constexpr int NMV = KC * 128 / 2 / NT;           // float64 pairs of M per thread
+    constexpr int NMV = KC * BC / 2 / NT;            // float64 pairs of M per thread
     const bool vec = ((p % VX) == 0);
     T xr[NXV][VX];
     T mr[NMV][2];
@@ -1618,7 +1640,7 @@ __device__ __forceinline__ void body_residual(
 #pragma unroll
         for (int s2 = 0; s2 < NMV; ++s2) {
             const int e = tid + NT * s2;
-            const int kk = e >> 6, cc = (e & 63) * 2;
+            const int kk = e / (BC / 2), cc = (e % (BC / 2)) * 2;
             const int k = kc + kk, c = cblk + cc;
             if ((p & 1) == 0 && k < p && c + 2 <= p) {
                 typedef double dv2 __attribute__((ext_vector_type(2)));
@@ -1647,7 +1669,7 @@ __device__ __forceinline__ void body_residual(
 #pragma unroll
         for (int s2 = 0; s2 < NMV; ++s2) {
             const int e = tid + NT * s2;
-            const int kk = e >> 6, cc = (e & 63) * 2;
+            const int kk = e / (BC / 2), cc = (e % (BC / 2)) * 2;
 #pragma unroll
             for (int v = 0; v < 2; ++v) Ms[kk * MST + cc + v] = mr[s2][v];
         }
@@ -1686,11 +1708,10 @@ __device__ __forceinline__ void body_residual(
                     for (int j = 0; j < JT; ++j) a1[i][j] = Mma<T>::run(a[i], b[j], a1[i][j]);
             }
         }
-        // epilogue, one 16-row sub-tile at a time
+        if (APPLY) {
+            // mode 0: Out = X M; mode 1: Out -= X M
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (APPLY) {
-                // mode 0: Out = X M; mode 1: Out -= X M
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < JT; ++j)
 #pragma unroll
@@ -1699,51 +1720,58 @@ __device__ __forceinline__ void body_residual(
                         if (r < n && cok[j]) {
                             const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
                             if (mode == 1)
-                                G[idx] = (T)((double)G[idx] - (double)a1[i][j][q]);
+                                G[idx] = (TG)((double)G[idx] - (double)a1[i][j][q]);
                             else
-                                G[idx] = (T)a1[i][j][q];
+                                G[idx] = (TG)a1[i][j][q];
                         }
                     }
-                continue;
+            continue;
+        }
+        // G, X and gradL^{k-1} of one 16 x 16 sub-tile per round; the next
+        // round's loads are issued before this round's arithmetic
+        constexpr int NR = 4 * JT;
+        TG eg[2][4], ep[2][4];
+        T ex[2][4];
+        auto eload = [&](int rr, int sb) {
+            const int i = rr / JT, j = rr % JT;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
+                const bool ok = (r < n) && cok[j];
+                const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
+                eg[sb][q] = ok ? G[idx] : (TG)0;
+                ex[sb][q] = (ok && iterate) ? X[idx] : (T)0;
+                ep[sb][q] = (ok && have_prev) ? Gprev[idx] : (TG)0;
             }
-            // loads of one 16-column group issued together (enough to keep
-            // the register count at two waves per SIMD)
+        };
+        eload(0, 0);
 #pragma unroll
-            for (int j = 0; j < JT; ++j) {
-                T gv[4], xv[4], gpv[4];
+        for (int rr = 0; rr < NR; ++rr) {
+            if (rr + 1 < NR) eload(rr + 1, (rr + 1) & 1);
+            const int i = rr / JT, j = rr % JT, sb = rr & 1;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
-                    const bool ok = (r < n) && cok[j];
-                    const size_t idx = (size_t)r * p + c0 + j * 16 + lr;
-                    gv[q] = ok ? G[idx] : (T)0;
-                    xv[q] = (ok && iterate) ? X[idx] : (T)0;
-                    gpv[q] = (ok && have_prev) ? Gprev[idx] : (T)0;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
+                if (r >= n || !cok[j]) continue;
+                const double g = (double)eg[sb][q];
+                if (KKT) {
+                    const double rk = g - (double)a1[i][j][q];
+                    skk += rk * rk;
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
-                    if (r >= n || !cok[j]) continue;
-                    const double g = (double)gv[q];
-                    if (KKT) {
-                        const double rk = g - (double)a1[i][j][q];
-                        skk += rk * rk;
-                    }
-                    if (!iterate) continue;
-                    const T glt = (T)(g - (double)a1[i][j][q]);
-                    G[(size_t)r * p + c0 + j * 16 + lr] = glt;
-                    const double gl = (double)glt;
-                    const double x = (double)xv[q];
-                    cxg[j] += x * gl;
-                    cgg[j] += gl * gl;
-                    if (have_prev) {
-                        const double glp = (double)gpv[q];
-                        const double sd = onu[j] * x - glp * rinv_eta;
-                        const double yd = gl - glp;
-                        sss += sd * sd;
-                        ssy += sd * yd;
-                        syy += yd * yd;
-                    }
+                if (!iterate) continue;
+                const TG glt = (TG)(g - (double)a1[i][j][q]);
+                G[(size_t)r * p + c0 + j * 16 + lr] = glt;
+                const double gl = (double)glt;
+                const double x = (double)ex[sb][q];
+                cxg[j] += x * gl;
+                cgg[j] += gl * gl;
+                if (have_prev) {
+                    const double glp = (double)ep[sb][q];
+                    const double sd = onu[j] * x - glp * rinv_eta;
+                    const double yd = gl - glp;
+                    sss += sd * sd;
+                    ssy += sd * yd;
+                    syy += yd * yd;
                 }
             }
         }
@@ -1766,7 +1794,7 @@ __device__ __forceinline__ void body_residual(
             }
         }
         __syncthreads();
-        if (tid < 128) {
+        if (tid < BC) {
             const int c = cblk + tid;
             if (c < p) {
                 double* pc = part_col + ((size_t)rb * p + c) * 2;
@@ -1787,49 +1815,52 @@ __device__ __forceinline__ void body_residual(
         ps[3] = t3;
     }
 }
-template <typename T, bool APPLY, bool KKT, int WC>
-__global__ __launch_bounds__(128 * WC) void k_residual(
-    const T* __restrict__ X, T* __restrict__ G, const T* __restrict__ Gprev,
+template <typename T, typename TG, bool APPLY, bool KKT, int WC>
+__global__ __launch_bounds__(128 * WC, 2) void k_residual(
+    const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
-    body_residual<T, APPLY, KKT, WC>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col,
+    body_residual<T, TG, APPLY, KKT, WC>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col,
                                      part_scal, prm, st, mode, blockIdx.x, gridDim.x);
 }
 
 
-// Column partial sums over the row blocks in a fixed order: 32 (column, dot)
-// pairs per workgroup, each summed by 8 threads over interleaved row blocks.
+// Column dots of the residual pass summed over row blocks in a fixed order,
+// in col_groups(nrb) groups of row blocks (the last step adds the groups).
 __device__ __forceinline__ void body_colreduce(const double* __restrict__ part_col, int nrb,
-                                                   int p, double* __restrict__ colxg,
-                                                   double* __restrict__ colgg,
-                                                   const DevState* __restrict__ st, int bid_, int nblk_) {
+                                                   int p, double* __restrict__ colpart,
+                                                   const DevState* __restrict__ st, int bx, int g) {
     if (st->done) return;
-    __shared__ double sred[8][32];
-    const int e = bid_ * 32 + (threadIdx.x & 31);
-    const int part = threadIdx.x >> 5;
-    double s = 0.0;
-    if (e < 2 * p)
-        for (int b = part; b < nrb; b += 8) s += part_col[(size_t)b * 2 * p + e];
-    sred[part][threadIdx.x & 31] = s;
-    __syncthreads();
-    if (threadIdx.x < 32 && e < 2 * p) {
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) t += sred[q][threadIdx.x];
-        const int c = e >> 1;
-        if (e & 1)
-            colgg[c] = t;
-        else
-            colxg[c] = t;
+    // workgroup (bx, g): 64 consecutive values e of the 2p interleaved column
+    // dots, summed over the row blocks of group g; wave w takes the rows
+    // b = w (mod 4), two loads in flight
+    __shared__ double sred[4][64];
+    const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int ng = col_groups(nrb);
+    const int rg = (nrb + ng - 1) / ng;
+    const int e = bx * 64 + lane;
+    const int b0 = g * rg, b1 = min(nrb, b0 + rg);
+    const size_t w2 = (size_t)2 * p;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < 2 * p) {
+        int b = b0 + slice;
+        for (; b + 4 < b1; b += 8) {
+            s0 += part_col[(size_t)b * w2 + e];
+            s1 += part_col[(size_t)(b + 4) * w2 + e];
+        }
+        if (b < b1) s0 += part_col[(size_t)b * w2 + e];
     }
+    sred[slice][lane] = s0 + s1;
+    __syncthreads();
+    if (slice == 0 && e < 2 * p)
+        colpart[(size_t)g * w2 + e] = (sred[0][lane] + sred[1][lane]) + (sred[2][lane] + sred[3][lane]);
 }
 __global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part_col, int nrb,
-                                                   int p, double* __restrict__ colxg,
-                                                   double* __restrict__ colgg,
+                                                   int p, double* __restrict__ colpart,
                                                    const DevState* __restrict__ st) {
-    body_colreduce(part_col, nrb, p, colxg, colgg, st, blockIdx.x, gridDim.x);
+    body_colreduce(part_col, nrb, p, colpart, st, blockIdx.x, blockIdx.y);
 }
 
 
@@ -1844,19 +1875,35 @@ __device__ __forceinline__ void body_pp_gemm2(const double* __restrict__ S,
                                               double* __restrict__ part, int p,
                                               const DevState* __restrict__ st, int bx, int by) {
     if (st->done) return;
-    __shared__ double As[16][17], B1[16][17], B2[16][17];
+    constexpr int KB = 64;  // K chunk; the next chunk is loaded while this one is used
+    __shared__ double As[16][KB + 1], B1[KB][17], B2[KB][17];
     __shared__ double sh[4];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int row = by * 16 + ty, col = bx * 16 + tx;
-    double t1 = 0.0, t2 = 0.0;
-    for (int k0 = 0; k0 < p; k0 += 16) {
-        As[ty][tx] = (row < p && k0 + tx < p) ? S[(size_t)row * p + k0 + tx] : 0.0;
-        const bool ok = (k0 + ty < p) && (col < p);
-        B1[ty][tx] = ok ? M1[(size_t)(k0 + ty) * p + col] : 0.0;
-        B2[ty][tx] = ok ? M2[(size_t)(k0 + ty) * p + col] : 0.0;
-        __syncthreads();
+    double a[4], b1[4], b2[4];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int q = 0; q < 4; ++q) {
+            const int ka = k0 + tx + 16 * q, kb = k0 + ty + 16 * q;
+            a[q] = (row < p && ka < p) ? S[(size_t)row * p + ka] : 0.0;
+            const bool ok = kb < p && col < p;
+            b1[q] = ok ? M1[(size_t)kb * p + col] : 0.0;
+            b2[q] = ok ? M2[(size_t)kb * p + col] : 0.0;
+        }
+    };
+    double t1 = 0.0, t2 = 0.0;
+    load(0);
+    for (int k0 = 0; k0 < p; k0 += KB) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[ty][tx + 16 * q] = a[q];
+            B1[ty + 16 * q][tx] = b1[q];
+            B2[ty + 16 * q][tx] = b2[q];
+        }
+        __syncthreads();
+        if (k0 + KB < p) load(k0 + KB);
+#pragma unroll 16
+        for (int k = 0; k < KB; ++k) {
             t1 += As[ty][k] * B1[k][tx];
             t2 += As[ty][k] * B2[k][tx];
         }
@@ -1893,8 +1940,7 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ T1,
                                                  const double* __restrict__ T2,
                                                  const double* __restrict__ feas_part,
-                                                 const double* __restrict__ colxg,
-                                                 const double* __restrict__ colgg,
+                                                 double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
                                                  DevState* __restrict__ st, int bid_, int nblk_) {
     if (st->done) return;
@@ -1903,13 +1949,21 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
     __shared__ int s_stop;
     const int t = threadIdx.x;
     const bool ident = prm->kkt_identity != 0;
+    // column dots: the ncolg group partials summed into group 0 (x.gradL at
+    // 2c, gradL.gradL at 2c + 1), each value by the one thread that reads it
+    for (int e = t; e < 2 * p; e += blockDim.x) {
+        double a = 0.0;
+        for (int g = 0; g < ncolg; ++g) a += colpart[(size_t)g * 2 * p + e];
+        colpart[e] = a;
+    }
+    __syncthreads();
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = t; b < nparts; b += blockDim.x)
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] += part_scal[(size_t)b * 4 + q];
     for (int i = t; i < p; i += blockDim.x) v[4] += feas_part[i];
     if (ident) {
-        for (int i = t; i < p; i += blockDim.x) v[5] += colgg[i];
+        for (int i = t; i < p; i += blockDim.x) v[5] += colpart[2 * i + 1];
         // tile partials of <B, S B - 2 (W - S M_L)> from the p x p product pass
         const int nt = (p + 15) / 16;
         for (int e = t; e < nt * nt; e += blockDim.x) v[6] += T1[e];
@@ -2012,7 +2066,8 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
         double nv = 1.0;
         if (pcal) {
             // ||X_c - gradL_c / eta||_2^2 expanded with float64 column dots
-            const double y2 = S[(size_t)c * p + c] - 2.0 * colxg[c] / eta + colgg[c] / (eta * eta);
+            const double y2 = S[(size_t)c * p + c] - 2.0 * colpart[2 * c] / eta +
+                              colpart[2 * c + 1] / (eta * eta);
             nv = sqrt(y2);
         }
         nu[c] = nv;
@@ -2028,11 +2083,11 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
                                                  const double* __restrict__ T1,
                                                  const double* __restrict__ T2,
                                                  const double* __restrict__ feas_part,
-                                                 const double* __restrict__ colxg,
-                                                 const double* __restrict__ colgg,
+                                                 double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
                                                  DevState* __restrict__ st) {
-    body_stage2(prm, part_scal, nparts, S, W, Bm, T1, T2, feas_part, colxg, colgg, nu, p, st, blockIdx.x, gridDim.x);
+    body_stage2(prm, part_scal, nparts, S, W, Bm, T1, T2, feas_part, colpart, ncolg, nu, p, st,
+                blockIdx.x, gridDim.x);
 }
 
 
@@ -2256,7 +2311,7 @@ __global__ __launch_bounds__(256) void kb_gram(STF_BATCH_ARGS) {
                      g.n_tiles, g.wup, g.chunk, d.gram_part, d.st, lid_, nb_);
 }
 
-__global__ __launch_bounds__(256) void kb_gram_lds64(STF_BATCH_ARGS) {
+__global__ __launch_bounds__(256, 2) void kb_gram_lds64(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const GramPlan& g = d.gram;
     body_gram_lds<double>((const double*)d.X, (const double*)d.g[parity], d.n, d.p, g.nb,
@@ -2304,10 +2359,10 @@ __global__ __launch_bounds__(256) void kb_split3(STF_BATCH_ARGS) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void kb_residual(STF_BATCH_ARGS) {
+__global__ __launch_bounds__(256, 2) void kb_residual(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const ResPlan& r = d.res;
-    body_residual<T, false, false, 4>((const T*)d.X, (T*)d.g[parity], (const T*)d.g[parity ^ 1],
+    body_residual<T, T, false, false, 2>((const T*)d.X, (T*)d.g[parity], (const T*)d.g[parity ^ 1],
                                    d.ML, d.Psi, d.nu, d.n, d.p, r.nrb, r.ncb, r.nrt, d.res_col,
                                    d.res_scal, d.prm, d.st, RES_ITERATE, lid_, nb_);
 }
@@ -2325,13 +2380,14 @@ __global__ __launch_bounds__(64 * (256 / kMixRW)) void kb_residual_bf6_lds(STF_B
 
 __global__ __launch_bounds__(256) void kb_colreduce(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
-    body_colreduce(d.res_col, d.res.nrb, d.p, d.colxg, d.colgg, d.st, lid_, nb_);
+    const int nch = (2 * d.p + 63) / 64;
+    body_colreduce(d.res_col, d.res.nrb, d.p, d.colpart, d.st, lid_ % nch, lid_ / nch);
 }
 
 __global__ __launch_bounds__(1024) void kb_stage2(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.W, d.Bm, d.T1, d.T2, d.fpart,
-                d.colxg, d.colgg, d.nu, d.p, d.st, 0, 1);
+                d.colpart, col_groups(d.res.nrb), d.nu, d.p, d.st, 0, 1);
 }
 
 template <typename T>
@@ -2531,7 +2587,7 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
     }
     if (after_main) (void)hipEventRecord(after_main, s);
     const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
-    k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
+    k_gram_reduce<<<(unsigned)((tot + 63) / 64), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
                                                                  gp.nb, nst, wup, p, S, W, st);
 }
 
@@ -2589,19 +2645,19 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     mark();
     if (dtype == STF_F64) {
         if (kkt_prod)
-            k_residual<double, false, true, 2><<<nwg, 256, 0, s>>>(
+            k_residual<double, double, false, true, 2><<<nwg, 256, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
                 rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
         else
-            k_residual<double, false, false, 4><<<nwg, 512, 0, s>>>(
+            k_residual<double, double, false, false, 2><<<nwg, 256, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
                 rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode);
     } else if (kkt_prod) {
-        k_residual<float, false, true, 2><<<nwg, 256, 0, s>>>(
+        k_residual<float, float, false, true, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
     } else {
-        k_residual<float, false, false, 4><<<nwg, 512, 0, s>>>(
+        k_residual<float, float, false, false, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)G, (const float*)Gprev, ML, Psi, nu, n, p, rp.nrb, rp.ncb,
             rp.nrt, part_col, part_scal, prm, st, mode);
     }
@@ -2609,11 +2665,12 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
 
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* W, const double* Bm,
-                   const double* T1, const double* T2, const double* feas_part, double* colxg,
-                   double* colgg, double* nu, int p, DevState* st, hipStream_t s) {
-    k_colreduce<<<(2 * p + 31) / 32, 256, 0, s>>>(part_col, rp.nrb, p, colxg, colgg, st);
+                   const double* T1, const double* T2, const double* feas_part, double* colpart,
+                   double* nu, int p, DevState* st, hipStream_t s) {
+    const int ng = col_groups(rp.nrb);
+    k_colreduce<<<dim3((2 * p + 63) / 64, ng), 256, 0, s>>>(part_col, rp.nrb, p, colpart, st);
     k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, W, Bm, T1, T2, feas_part,
-                                colxg, colgg, nu, p, st);
+                                colpart, ng, nu, p, st);
 }
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
@@ -2630,11 +2687,11 @@ void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const 
                   int64_t n, int p, hipStream_t s, int subtract) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     if (dtype == STF_F64)
-        k_residual<double, true, false, 2><<<nwg, 256, 0, s>>>(
+        k_residual<double, double, true, false, 2><<<nwg, 256, 0, s>>>(
             (const double*)X, (double*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
             rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
     else
-        k_residual<float, true, false, 2><<<nwg, 256, 0, s>>>(
+        k_residual<float, float, true, false, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
             rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
 }
@@ -2746,9 +2803,9 @@ void launch_batched(int stage, int dtype, int precision, int variant_key, const 
                 else
                     kb_residual_bf6_lds<384><<<g, 64 * (256 / kMixRW), 0, s>>>(d, L, O, c, parity);
             } else if (f64) {
-                kb_residual<double><<<g, 512, 0, s>>>(d, L, O, c, parity);
+                kb_residual<double><<<g, 256, 0, s>>>(d, L, O, c, parity);
             } else {
-                kb_residual<float><<<g, 512, 0, s>>>(d, L, O, c, parity);
+                kb_residual<float><<<g, 256, 0, s>>>(d, L, O, c, parity);
             }
             break;
         case BS_COLRED:
