@@ -353,6 +353,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     hp.kkt_every = opt->kkt_every;
     hp.kkt_identity = 1;
     hp.switch_tol = (opt->precision == STF_PREC_FP64) ? 0.0 : std::max(0.0, opt->switch_tol);
+    hp.switch_stall = kSwitchStall;
     hp.history = opt->history;
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);

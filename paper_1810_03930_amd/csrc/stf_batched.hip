@@ -337,6 +337,7 @@ int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
         q.kkt_every = opt->kkt_every;
         q.kkt_identity = 1;
         q.switch_tol = (P.dtype == STF_F32) ? std::max(0.0, opt->switch_tol) : 0.0;
+        q.switch_stall = kSwitchStall;
         q.history = nullptr;
         HIPCHK(hipMemcpyAsync(hd[b].prm, &q, sizeof(q), hipMemcpyHostToDevice, s));
         launch_init_state(hd[b].st, s);

@@ -26,7 +26,9 @@ struct DevState {
     int32_t status;       // STF_OK / STF_MAX_ITER / STF_E_DIVERGED
     int32_t final_iter;   // index of the returned iterate
     int32_t info;         // Cholesky failure pivot + 1, or 0
-    int32_t pad[3];
+    int32_t k_best;       // iteration of the smallest stop-test value so far
+    int32_t pad[2];
+    double kkt_best;      // that value
 };
 
 // Parameters the device kernels read (copied once per solve into the workspace).
@@ -36,13 +38,17 @@ struct DevParams {
     int32_t n_scal_parts;   // number of scalar partial slots written by the residual pass
     int32_t n_col_parts;    // number of row-block column partials
     int32_t kkt_identity;   // 1: stop test from the float64 p x p identity (no second product)
-    int32_t pad;
+    int32_t switch_stall;   // hand over also after this many iterations without a new
+                            // smallest stop-test value (with switch_tol > 0; 0 = never)
     double switch_tol;      // relative KKT at which a reduced-precision solve hands over
     double* history;        // optional per-iteration record, (max_iter + 1) x 4
 };
 
 // Internal status of a reduced-precision phase that reached switch_tol.
 #define STF_SWITCH 2
+// Iterations without a new smallest stop-test value after which a
+// reduced-precision phase hands over even above switch_tol.
+constexpr int kSwitchStall = 400;
 
 // Tiling of the split-K Gram pass.
 struct GramPlan {

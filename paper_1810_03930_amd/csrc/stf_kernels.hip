@@ -357,8 +357,9 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
     typedef T tv __attribute__((ext_vector_type(V)));
     const int lane = threadIdx.x & 63;
     const bool vec = (p % V) == 0;
-    for (int64_t r = (int64_t)bid_ * 4 + (threadIdx.x >> 6); r < n;
-         r += (int64_t)nblk_ * 4) {
+    const int rpb = blockDim.x >> 6;  // rows per workgroup: one per wave
+    for (int64_t r = (int64_t)bid_ * rpb + (threadIdx.x >> 6); r < n;
+         r += (int64_t)nblk_ * rpb) {
         double dg = (ND == 6) ? 6.0 : 2.0;
         if (v) dg += v[r];
         if (phi) dg += alpha * phi[r];
@@ -1209,8 +1210,10 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const bool vec = (p % 4) == 0;
     for (int64_t rt = rb; rt < nrt; rt += nrb) {
         const int64_t r0 = rt * 256 + wave * RW;
-        float xa[IT][8];
-        auto load_x = [&](int kc) {
+        // X fragments (16 rows x 8 consecutive columns per MFMA tile) of two
+        // K-chunks in flight: chunk kc is split while kc + 64 is loaded
+        float xa[2][IT][8];
+        auto load_x = [&](int kc, float (&dst)[IT][8]) {
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 const int64_t r = r0 + i * 16 + lr;
@@ -1221,12 +1224,12 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                     const f4 v = *(const f4*)(src + 4);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        xa[i][e] = u[e];
-                        xa[i][4 + e] = v[e];
+                        dst[i][e] = u[e];
+                        dst[i][4 + e] = v[e];
                     }
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) xa[i][e] = (r < n && c + e < p) ? src[e] : 0.f;
+                    for (int e = 0; e < 8; ++e) dst[i][e] = (r < n && c + e < p) ? src[e] : 0.f;
                 }
             }
         };
@@ -1237,48 +1240,40 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
-        load_x(0);
-        for (int kc = 0; kc < pk; kc += 32) {
+        auto step = [&](int kc, float (&buf)[IT][8]) {
             bf8 xh[IT], xm[IT], xl[IT];
 #pragma unroll
-            for (int i = 0; i < IT; ++i) split3(xa[i], xh[i], xm[i], xl[i]);
-            if (kc + 32 < pk) load_x(kc + 32);
-            bf8 mh[4], mm[4], ml[4];
+            for (int i = 0; i < IT; ++i) split3(buf[i], xh[i], xm[i], xl[i]);
+            if (kc + 64 < pk) load_x(kc + 64, buf);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int o = (j * 16 + lr) * LP + kc + 8 * g;
-                mh[j] = *(const bf8*)&Ms[o];
-                mm[j] = *(const bf8*)&Ms[64 * LP + o];
-                ml[j] = *(const bf8*)&Ms[2 * 64 * LP + o];
+                const bf8 mh = *(const bf8*)&Ms[o];
+                const bf8 mm = *(const bf8*)&Ms[64 * LP + o];
+                const bf8 ml = *(const bf8*)&Ms[2 * 64 * LP + o];
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mh, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mm, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mh, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], ml, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xl[i], mh, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mm, acc[i][j]);
             }
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mh[j], acc[i][j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mm[j], acc[i][j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mh[j], acc[i][j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], ml[j], acc[i][j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xl[i], mh[j], acc[i][j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mm[j], acc[i][j]);
+        };
+        load_x(0, xa[0]);
+        if (32 < pk) load_x(32, xa[1]);
+        for (int kc = 0; kc < pk; kc += 64) {
+            step(kc, xa[0]);
+            if (kc + 32 < pk) step(kc + 32, xa[1]);
         }
-        // gradL = G - X M_L over G (G, X and gradL^{k-1} of the block are read
-        // here; the second wave of the SIMD covers their latency);
-        // the BB and column dots of the block are summed in float32 per lane
+        // gradL = G - X M_L over G, one 16 x 16 sub-tile per round; the next
+        // round's G, X and gradL^{k-1} are loaded before this round's arithmetic.
+        // The BB and column dots of the block are summed in float32 per lane
         // (at most 4 IT terms per column, 16 IT per BB dot) and added in float64
         const size_t tb = (size_t)r0 * p + cblk;
         float* Gt = G + tb;
@@ -1287,37 +1282,40 @@ __device__ __forceinline__ void body_residual_bf6_lds(
         const float rinv_f = (float)rinv_eta;
         float tss = 0.f, tsy = 0.f, tyy = 0.f;
         float txg[4] = {0.f, 0.f, 0.f, 0.f}, tgg[4] = {0.f, 0.f, 0.f, 0.f};
+        constexpr int NR = IT * 4;
+        float eg[2][4], ex[2][4], ep[2][4];
+        auto eload = [&](int rr, int sb) {
+            const int i = rr / 4, j = rr % 4;
 #pragma unroll
-        for (int i = 0; i < IT; ++i) {
+            for (int q = 0; q < 4; ++q) {
+                const int rw = i * 16 + Mma<float>::row(g, q);
+                const bool ok = (r0 + rw < n) && cok[j];
+                const int off = rw * p + j * 16 + lr;
+                eg[sb][q] = ok ? Gt[off] : 0.f;
+                ex[sb][q] = ok ? Xt[off] : 0.f;
+                ep[sb][q] = (ok && have_prev) ? Pt[off] : 0.f;
+            }
+        };
+        eload(0, 0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float onu_f = (float)onu[j];
-                float gv[4], xv[4], gpv[4];
-                int off[4];
-                bool ok[4];
+        for (int rr = 0; rr < NR; ++rr) {
+            if (rr + 1 < NR) eload(rr + 1, (rr + 1) & 1);
+            const int i = rr / 4, j = rr % 4, sb = rr & 1;
+            const float onu_f = (float)onu[j];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int rr = i * 16 + Mma<float>::row(g, q);
-                    ok[q] = (r0 + rr < n) && cok[j];
-                    off[q] = rr * p + j * 16 + lr;
-                    gv[q] = ok[q] ? Gt[off[q]] : 0.f;
-                    xv[q] = ok[q] ? Xt[off[q]] : 0.f;
-                    gpv[q] = (ok[q] && have_prev) ? Pt[off[q]] : 0.f;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!ok[q]) continue;
-                    const float gl = gv[q] - acc[i][j][q];
-                    Gt[off[q]] = gl;
-                    txg[j] += xv[q] * gl;
-                    tgg[j] += gl * gl;
-                    if (have_prev) {
-                        const float sd = onu_f * xv[q] - gpv[q] * rinv_f;
-                        const float yd = gl - gpv[q];
-                        tss += sd * sd;
-                        tsy += sd * yd;
-                        tyy += yd * yd;
-                    }
+            for (int q = 0; q < 4; ++q) {
+                const int rw = i * 16 + Mma<float>::row(g, q);
+                if (r0 + rw >= n || !cok[j]) continue;
+                const float gl = eg[sb][q] - acc[i][j][q];
+                Gt[rw * p + j * 16 + lr] = gl;
+                txg[j] += ex[sb][q] * gl;
+                tgg[j] += gl * gl;
+                if (have_prev) {
+                    const float sd = onu_f * ex[sb][q] - ep[sb][q] * rinv_f;
+                    const float yd = gl - ep[sb][q];
+                    tss += sd * sd;
+                    tsy += sd * yd;
+                    tyy += yd * yd;
                 }
             }
         }
@@ -1992,14 +1990,23 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
             const double kkt = sqrt(k2);
             if (k == 0) st->kkt0 = kkt;
             st->kkt = kkt;
+            const bool best = (k == 0) || kkt < st->kkt_best;
+            if (best) {
+                st->kkt_best = kkt;
+                st->k_best = k;
+            }
             if (!isfinite(kkt)) {
                 st->status = STF_E_DIVERGED;
                 stop = 1;
             } else if (st->kkt0 == 0.0 || kkt <= prm->tol * st->kkt0) {
                 st->status = STF_OK;
                 stop = 1;
-            } else if (prm->switch_tol > 0.0 && kkt <= prm->switch_tol * st->kkt0) {
-                // hand over to float64: the state is left as it was before this stage
+            } else if (prm->switch_tol > 0.0 &&
+                       (kkt <= prm->switch_tol * st->kkt0 ||
+                        (prm->switch_stall > 0 && k - st->k_best >= prm->switch_stall))) {
+                // hand over to float64 (at switch_tol, or when the reduced-precision
+                // descent has stopped improving): the state is left as it was
+                // before this stage
                 st->status = STF_SWITCH;
                 stop = 1;
             }

@@ -245,6 +245,27 @@ def test_switch_reaches_fp64_tolerance(precision):
     _check_returned_point(op, res, X64, lam)
 
 
+def test_switch_on_stall():
+    """With a switch_tol it cannot reach, a MIXED solve hands over once its
+    stop-test value has not improved for 400 iterations (its split-bf16 Grams
+    put a floor far above 1e-10 under its own stop test), and the float64
+    phase then reaches 1e-10.  (FP32 on this small grid drives its own stop
+    test below 1e-10 -- it measures the float32-rounded G -- so it is not
+    a stall case.)"""
+    precision = "mixed"
+    prob, x0 = _problem("ks3d")
+    op = OracleProblem(prob)
+    o, g = _pair(prob, beta=4.0, max_iter=6000, tol=1e-10, orth=True, precision=precision)
+    g.switch_tol = 1e-30
+    res, _, X64, lam = _gpu_solve(prob, x0, g)
+    print(f"{precision}: hand-over on stall at k={res['switch_iter']}, converged at "
+          f"{res['iters']}, kkt_rel {res['kkt_rel']:.2e}")
+    assert res["rc"] == 0
+    assert 400 <= res["switch_iter"] < res["iters"]
+    assert res["kkt_rel"] <= 1.01e-10
+    _check_returned_point(op, res, X64, lam)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
 @pytest.mark.parametrize("grid,p", [((20, 18, 16), 100), ((16, 16, 12), 300)])
 def test_reduced_precision_iterates_wide(precision, grid, p):
