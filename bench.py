@@ -36,7 +36,7 @@ P = 256
 ALPHA = 1.0
 BETA = 4.0          # PCAL penalty for the 3D KS workload (above its p-th eigenvalue)
 TOL = 1e-6
-SWITCH_TOL = 2e-5   # relative KKT at which the fast form continues in float64
+SWITCH_TOL = 1e-5   # relative KKT at which the fast form continues in float64
 BATCH_SWITCH_TOL = 1e-3
 MAX_ITER = 6000
 HBM_PEAK_GBS = 8000.0
