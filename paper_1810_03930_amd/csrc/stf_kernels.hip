@@ -266,39 +266,66 @@ __global__ __launch_bounds__(256) void k_dst_axis(const double* __restrict__ in,
 // z-plane per workgroup: out_plane = S_y in_plane S_x^T (S symmetric);
 // k_dst_z applies, for one y and all x, S_z along z, the division by
 // lx + ly + lz and S_z again (the forward and inverse z transforms fused).
-// 1024 threads per workgroup: one workgroup per plane or slab (64 of them on
-// 64^3) must hide its own LDS and global latencies.
+// Each 64 x 64 product is sixteen 16 x 16 tiles of float64 MFMA, one per wave
+// of the 1024-thread workgroup; the operands sit in LDS zero-padded to 64 x 64
+// with a 65-double row pitch (the 16 rows an MFMA operand reads then fall in
+// different banks).
 constexpr int kDstMax = 64;
+constexpr int kDP = kDstMax + 1;
+
+// 16 x 16 tile (ti, tj) of L R over the padded 64-long inner dimension; the
+// lane holds rows 16 ti + Mma<double>::row(lk, q), column 16 tj + lr.
+__device__ __forceinline__ d4 dst_tile(const double* L, const double* R, int ti, int tj,
+                                       int lr, int lk) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < kDstMax; k += 4) {
+        const double a = L[(16 * ti + lr) * kDP + k + lk];
+        const double b = R[(k + lk) * kDP + 16 * tj + lr];
+        acc = Mma<double>::run(a, b, acc);
+    }
+    return acc;
+}
+
+// m x m matrix (row-major, global) into a zero-padded 64 x kDP LDS array
+__device__ __forceinline__ void dst_stage(double* D, const double* M, int rows, int cols,
+                                          int ld) {
+    for (int e = threadIdx.x; e < kDstMax * kDstMax; e += blockDim.x) {
+        const int r = e / kDstMax, c = e % kDstMax;
+        D[r * kDP + c] = (r < rows && c < cols) ? M[(size_t)r * ld + c] : 0.0;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_dst_xy(const double* __restrict__ in,
                                                 double* __restrict__ out,
                                                 const double* __restrict__ Sx,
                                                 const double* __restrict__ Sy, int nx, int ny,
                                                 const DevState* __restrict__ st) {
     if (st && st->done) return;
-    __shared__ double A[kDstMax * kDstMax], T[kDstMax * kDstMax];
-    __shared__ double Mx[kDstMax * kDstMax], My[kDstMax * kDstMax];
+    __shared__ double A[kDstMax * kDP], T[kDstMax * kDP];
+    __shared__ double Mx[kDstMax * kDP], My[kDstMax * kDP];
     const int nxy = nx * ny;
     const double* src = in + (size_t)blockIdx.x * nxy;
     double* dst = out + (size_t)blockIdx.x * nxy;
-    for (int e = threadIdx.x; e < nxy; e += blockDim.x) A[e] = src[e];
-    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) Mx[e] = Sx[e];
-    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) My[e] = Sy[e];
+    dst_stage(A, src, ny, nx, nx);
+    dst_stage(Mx, Sx, nx, nx, nx);
+    dst_stage(My, Sy, ny, ny, ny);
     __syncthreads();
-    // T[y][k] = sum_x A[y][x] Sx[k][x]; S is symmetric, so Sx[x][k] is read
-    // (consecutive lanes, consecutive k: no bank conflicts)
-    for (int e = threadIdx.x; e < nxy; e += blockDim.x) {
-        const int y = e / nx, k = e % nx;
-        double acc = 0.0;
-        for (int x = 0; x < nx; ++x) acc += A[y * nx + x] * Mx[x * nx + k];
-        T[e] = acc;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
+    // T[y][k] = sum_x A[y][x] Sx[x][k]  (S symmetric)
+    {
+        const d4 t = dst_tile(A, Mx, ti, tj, lr, lk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[(16 * ti + Mma<double>::row(lk, q)) * kDP + 16 * tj + lr] = t[q];
     }
     __syncthreads();
     // out[k][x] = sum_y Sy[k][y] T[y][x]
-    for (int e = threadIdx.x; e < nxy; e += blockDim.x) {
-        const int k = e / nx, x = e % nx;
-        double acc = 0.0;
-        for (int y = 0; y < ny; ++y) acc += My[k * ny + y] * T[y * nx + x];
-        dst[e] = acc;
+    const d4 o = dst_tile(My, T, ti, tj, lr, lk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = 16 * ti + Mma<double>::row(lk, q), x = 16 * tj + lr;
+        if (k < ny && x < nx) dst[k * nx + x] = o[q];
     }
 }
 __global__ __launch_bounds__(1024) void k_dst_z(const double* in, double* out,
@@ -308,30 +335,34 @@ __global__ __launch_bounds__(1024) void k_dst_z(const double* in, double* out,
                                                const double* __restrict__ lz, int nx, int ny,
                                                int nz, const DevState* __restrict__ st) {
     if (st && st->done) return;
-    __shared__ double A[kDstMax * kDstMax], U[kDstMax * kDstMax], Mz[kDstMax * kDstMax];
+    __shared__ double A[kDstMax * kDP], U[kDstMax * kDP], Mz[kDstMax * kDP];
     const int y = blockIdx.x;
     const size_t sxy = (size_t)nx * ny;
-    const int nzx = nz * nx;
-    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
-        const int z = e / nx, x = e % nx;
-        A[e] = in[(size_t)z * sxy + (size_t)y * nx + x];
+    for (int e = threadIdx.x; e < kDstMax * kDstMax; e += blockDim.x) {
+        const int z = e / kDstMax, x = e % kDstMax;
+        A[z * kDP + x] = (z < nz && x < nx) ? in[(size_t)z * sxy + (size_t)y * nx + x] : 0.0;
     }
-    for (int e = threadIdx.x; e < nz * nz; e += blockDim.x) Mz[e] = Sz[e];
+    dst_stage(Mz, Sz, nz, nz, nz);
     __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
     // U[k][x] = (sum_z Sz[k][z] A[z][x]) / (lx[x] + ly[y] + lz[k])
-    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
-        const int k = e / nx, x = e % nx;
-        double acc = 0.0;
-        for (int z = 0; z < nz; ++z) acc += Mz[k * nz + z] * A[z * nx + x];
-        U[e] = acc / ((lx[x] + ly[y]) + lz[k]);
+    {
+        const d4 u = dst_tile(Mz, A, ti, tj, lr, lk);
+        const int x = 16 * tj + lr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 16 * ti + Mma<double>::row(lk, q);
+            U[k * kDP + x] = (k < nz && x < nx) ? u[q] / ((lx[x] + ly[y]) + lz[k]) : 0.0;
+        }
     }
     __syncthreads();
-    // out[z][x] = sum_k Sz[z][k] U[k][x]
-    for (int e = threadIdx.x; e < nzx; e += blockDim.x) {
-        const int z = e / nx, x = e % nx;
-        double acc = 0.0;
-        for (int k = 0; k < nz; ++k) acc += Mz[z * nz + k] * U[k * nx + x];
-        out[(size_t)z * sxy + (size_t)y * nx + x] = acc;
+    // out[z][x] = sum_k Sz[z][k] U[k][x]  (every read of this slab is done)
+    const d4 o = dst_tile(Mz, U, ti, tj, lr, lk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int z = 16 * ti + Mma<double>::row(lk, q), x = 16 * tj + lr;
+        if (z < nz && x < nx) out[(size_t)z * sxy + (size_t)y * nx + x] = o[q];
     }
 }
 
