@@ -238,7 +238,8 @@ def roofline_for(form, precision, n, p):
 
 def cpu_baseline(prob, x0):
     """The float64 oracle, unchanged, on this host: per-iteration cost from a
-    1-iteration and a 4-iteration run (the difference is 3 full iterations)."""
+    1-iteration and a 9-iteration run (the difference is 8 full iterations;
+    about 10-15 s of host work in all)."""
     from threadpoolctl import threadpool_info
     from oracle.problems import OracleProblem
     from oracle import solver as O
@@ -249,12 +250,12 @@ def cpu_baseline(prob, x0):
     t0 = time.perf_counter()
     O.solve(op, x0, O.Options(max_iter=1, **opt))
     t1 = time.perf_counter()
-    O.solve(op, x0, O.Options(max_iter=4, **opt))
+    O.solve(op, x0, O.Options(max_iter=9, **opt))
     t2 = time.perf_counter()
-    per_iter = ((t2 - t1) - (t1 - t0)) / 3.0
+    per_iter = ((t2 - t1) - (t1 - t0)) / 8.0
     return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": int(min(cores, threads)),
-            "kind": "oracle", "sample": "3 PCAL iterations of the 64^3 p=256 workload "
-            f"(difference of a 4- and a 1-iteration float64 run; {t2 - t0:.1f} s total)",
+            "kind": "oracle", "sample": "8 PCAL iterations of the 64^3 p=256 workload "
+            f"(difference of a 9- and a 1-iteration float64 run; {t2 - t0:.1f} s total)",
             "s_per_iter": per_iter, "host_cores_visible": cores, "blas_threads": threads}
 
 

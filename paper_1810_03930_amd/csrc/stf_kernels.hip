@@ -428,7 +428,7 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                 ov o;
 #pragma unroll
                 for (int e = 0; e < V; ++e) o[e] = (TO)acc[e];
-                *(ov*)(gr + c) = o;
+                __builtin_nontemporal_store(o, (ov*)(gr + c));  // streamed: keep L2 for X
             }
         } else {
             for (int c = lane; c < p; c += 64) {
@@ -2150,8 +2150,9 @@ __device__ __forceinline__ void body_update(T* __restrict__ X, double* __restric
             const double x = xm ? xm[c] : (double)xr[c];
             const double y = (x - (double)gr[c] / eta) / nu[c];
             const T yt = (T)y;
-            xr[c] = yt;
-            if (xm) xm[c] = y;
+            // streamed, not re-read by this pass: non-temporal stores
+            __builtin_nontemporal_store(yt, &xr[c]);
+            if (xm) __builtin_nontemporal_store(y, &xm[c]);
             s += xm ? y * y : (double)yt * (double)yt;
         }
         if (rho) {
