@@ -311,9 +311,10 @@ int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* L
  *            tol, step rule, variant, max_iter may differ); precision must
  *            be the same for all, use_graph and check_every are taken from
  *            opts[0]; history is ignored; MIXED needs p <= 384.  switch_tol
- *            acts as in stf_solve: in the float32 forms a problem that reaches
- *            it stops, and once every problem is done those continue in
- *            float64 together (stf_result.switch_iter per problem)
+ *            acts as in stf_solve, per problem: in the float32 forms a problem
+ *            that reaches it (or stalls) continues in float64 at once while
+ *            the others go on in float32 in the same iterations
+ *            (stf_result.switch_iter per problem)
  *   ws     : device workspace of ws_bytes >= stf_batched_workspace_size()
  *   res    : host array of nprob results (ms_loop / ms_orth: the whole batch)
  * Returns the lowest per-problem status: STF_OK when every problem converged,

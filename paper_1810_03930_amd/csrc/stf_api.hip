@@ -84,6 +84,8 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.state_eval = take(sizeof(DevState));
     L.params = take(sizeof(DevParams));
     L.params_eval = take(sizeof(DevParams));
+    L.state64 = take(sizeof(DevState));
+    L.params64 = take(sizeof(DevParams));
     L.g[0] = take(np * elem_size(dt));
     L.g[1] = take(np * elem_size(dt));
     if (dt == STF_F64) {

@@ -7,9 +7,11 @@
 // its own device state, so a converged problem's workgroups return at once.
 // A chunk of iterations is captured once as a HIP graph and replayed; the host
 // reads every problem's state once per chunk and stops when all are done.  In
-// the float32 forms a problem that reaches its switch_tol stops; once all are
-// done, those continue together in float64 (kernels and groups of the float64
-// form, each from its float64 master iterate), as a single solve does.
+// the float32 forms with a switch_tol, every iteration runs the float32 groups,
+// a per-problem hand-over and the float64 groups (second descriptors: the
+// float64 master, float64 gradient buffers, own state and parameters): a
+// problem that reaches its switch_tol continues in float64 in the same
+// iteration, as a single solve does, while the others go on in float32.
 // Tile shapes per problem: the Gram bucket (MFMA tiles per wave) follows p;
 // the number of split-K chunks and residual row blocks follows the problem's
 // share of the batch's n p^2 work, from a batch-wide workgroup budget that
@@ -52,6 +54,8 @@ struct BatchPlan {
     std::vector<Group> groups64[BS_ROWSQ + 1];
     size_t desc = 0;                // BDesc[nprob]
     size_t states = 0;              // DevState[nprob]: gathered device states
+    size_t desc64 = 0;              // float32 forms: BDesc[nprob] of the float64 continuation
+    size_t states64 = 0;            //   and its gathered states
     size_t tables = 0, table_bytes = 0;
     size_t total = 0;
 };
@@ -108,6 +112,10 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
     };
     P.desc = take(sizeof(BDesc) * (size_t)nprob);
     P.states = take(sizeof(DevState) * (size_t)nprob);
+    if (P.dtype == STF_F32) {
+        P.desc64 = take(sizeof(BDesc) * (size_t)nprob);
+        P.states64 = take(sizeof(DevState) * (size_t)nprob);
+    }
     P.L.resize(nprob);
     P.gram.resize(nprob);
     P.res.resize(nprob);
@@ -232,10 +240,10 @@ BatchPlan make_batch_plan(int32_t nprob, const stf_problem* probs, int precision
 }
 
 // One iteration of every problem: the grouped launches of `groups` with the
-// kernels of (dtype, precision).
+// kernels of (dtype, precision) on the descriptors d.
 void enqueue_batched_iteration(const BatchPlan& P, const std::vector<Group>* groups, int dtype,
-                               int precision, char* ws, int parity, hipStream_t s) {
-    const BDesc* d = (const BDesc*)(ws + P.desc);
+                               int precision, const BDesc* d, char* ws, int parity,
+                               hipStream_t s) {
     auto run = [&](int stage) {
         for (const Group& g : groups[stage]) {
             BGroup bg;
@@ -394,15 +402,62 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
     for (int b = 0; b < nprob; ++b) limit = std::max<int64_t>(limit, (int64_t)opts[b].max_iter + 1);
     int64_t iters_run = 0;
 
-    // Enqueue iterations of every problem with the given groups and kernels
-    // until every problem is done; returns nonzero on a HIP error.
-    auto run_phase = [&](const std::vector<Group>* groups, int dtype, int precision) -> int {
+    // float32 forms with a hand-over: every problem that reaches its switch_tol
+    // (or stalls) continues in float64 at once, on its own, while the others go
+    // on in float32: each iteration runs the float32 kernels on the float32
+    // descriptors, the per-problem hand-over, then the float64 kernels on the
+    // continuation descriptors (their states start done, so those workgroups
+    // return at once until a problem hands over).
+    bool any_sw = false;
+    for (int b = 0; b < nprob; ++b) any_sw = any_sw || (hpv[b].switch_tol > 0.0);
+    const bool two = (P.dtype == STF_F32) && any_sw;
+    const BDesc* d32 = (const BDesc*)(w + P.desc);
+    const BDesc* d64 = two ? (const BDesc*)(w + P.desc64) : nullptr;
+    std::vector<DevState> hs64(nprob);
+    if (two) {
+        std::vector<BDesc> hd64 = hd;
+        for (int b = 0; b < nprob; ++b) {
+            const Layout& L = P.L[b];
+            char* base = w + P.pbase[b];
+            BDesc& d = hd64[b];
+            d.X = d.Xm;  // the float64 master
+            d.Xm = nullptr;
+            d.g[0] = base + L.g64;
+            d.g[1] = base + L.g64b;
+            d.res = P.res64[b];
+            d.st = (DevState*)(base + L.state64);
+            d.prm = (DevParams*)(base + L.params64);
+            DevParams q = hpv[b];
+            q.switch_tol = 0.0;
+            HIPCHK(hipMemcpyAsync(d.prm, &q, sizeof(q), hipMemcpyHostToDevice, s));
+            DevState z;
+            memset(&z, 0, sizeof(z));
+            z.done = 1;
+            HIPCHK(hipMemcpyAsync(d.st, &z, sizeof(z), hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipMemcpyAsync(w + P.desc64, hd64.data(), sizeof(BDesc) * hd64.size(),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));  // the host arrays above are read by the copies
+    }
+    auto enqueue = [&](int parity) {
+        enqueue_batched_iteration(P, P.groups, P.dtype, P.precision, d32, w, parity, s);
+        if (two) {
+            launch_batched_switch(d32, d64, nprob, parity, s);
+            enqueue_batched_iteration(P, P.groups64, STF_F64, STF_PREC_FP64, d64, w, parity, s);
+        }
+    };
+    // the state that describes problem b now
+    auto cur = [&](int b) -> const DevState& {
+        return (two && hs[b].status == STF_SWITCHED) ? hs64[b] : hs[b];
+    };
+
+    // Enqueue iterations until every problem is done; nonzero on a HIP error.
+    auto run_phase = [&]() -> int {
         hipGraphExec_t gexec = nullptr;
         hipGraph_t graph = nullptr;
         if (opt->use_graph && s != nullptr) {
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return 1;
-            for (int i = 0; i < chunk; ++i)
-                enqueue_batched_iteration(P, groups, dtype, precision, w, i & 1, s);
+            for (int i = 0; i < chunk; ++i) enqueue(i & 1);
             if (hipStreamEndCapture(s, &graph) != hipSuccess) return 1;
             if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
                 hipGraphDestroy(graph);
@@ -417,25 +472,27 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
                 enq += chunk;
             } else {
                 const int todo = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, limit - enq));
-                for (int i = 0; i < todo; ++i)
-                    enqueue_batched_iteration(P, groups, dtype, precision, w,
-                                              (int)((enq + i) & 1), s);
+                for (int i = 0; i < todo; ++i) enqueue((int)((enq + i) & 1));
                 enq += todo;
                 if (last_launch()) { err = 1; break; }
             }
-            bool all = true;
-            launch_gather_states((const BDesc*)(w + P.desc), nprob, (DevState*)(w + P.states),
-                                 s);
+            launch_gather_states(d32, nprob, (DevState*)(w + P.states), s);
+            if (two) launch_gather_states(d64, nprob, (DevState*)(w + P.states64), s);
             if (hipMemcpyAsync(hs.data(), w + P.states, sizeof(DevState) * (size_t)nprob,
                                hipMemcpyDeviceToHost, s) != hipSuccess ||
+                (two && hipMemcpyAsync(hs64.data(), w + P.states64,
+                                       sizeof(DevState) * (size_t)nprob,
+                                       hipMemcpyDeviceToHost, s) != hipSuccess) ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 err = 1;
                 break;
             }
+            bool all = true;
             int64_t mx = 0;
             for (int b = 0; b < nprob; ++b) {
-                all = all && hs[b].done;
-                mx = std::max<int64_t>(mx, hs[b].done ? hs[b].final_iter : hs[b].iter);
+                const DevState& c = cur(b);
+                all = all && c.done;
+                mx = std::max<int64_t>(mx, c.done ? c.final_iter : c.iter);
             }
             iters_run = mx;
             if (all) break;
@@ -446,43 +503,10 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
         return err;
     };
 
-    if (run_phase(P.groups, P.dtype, P.precision)) return STF_E_HIP;
+    if (run_phase()) return STF_E_HIP;
     std::vector<int> switched(nprob, -1);
-    bool any_switch = false;
     for (int b = 0; b < nprob; ++b)
-        if (hs[b].done && hs[b].status == STF_SWITCH) {
-            switched[b] = hs[b].final_iter;
-            any_switch = true;
-        }
-    if (any_switch) {
-        // Float64 continuation (see stf_solve): every problem now iterates on its
-        // float64 master with float64 kernels; problems that did not hand over
-        // are done and their workgroups return at once.  The batch restarts at
-        // parity 0, so buffer 0 takes the redone iteration's G and buffer 1 the
-        // previous gradL (float32, exact in float64).
-        for (int b = 0; b < nprob; ++b) {
-            const Layout& L = P.L[b];
-            char* base = w + P.pbase[b];
-            BDesc& d = hd[b];
-            d.X = d.Xm;
-            d.Xm = nullptr;
-            d.g[0] = base + L.g64;
-            d.g[1] = base + L.g64b;
-            d.res = P.res64[b];
-            const int k = switched[b];
-            if (k < 0) continue;
-            if (k >= 1)
-                launch_convert(STF_F64, base + L.g[(k - 1) & 1], STF_F32, d.g[1],
-                               (size_t)d.n * d.p, s);
-            hpv[b].switch_tol = 0.0;
-            HIPCHK(hipMemcpyAsync(d.prm, &hpv[b], sizeof(DevParams), hipMemcpyHostToDevice, s));
-            launch_resume_state(d.st, s);
-        }
-        HIPCHK(hipMemcpyAsync(w + P.desc, hd.data(), sizeof(BDesc) * hd.size(),
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (run_phase(P.groups64, STF_F64, STF_PREC_FP64)) return STF_E_HIP;
-    }
+        if (two && hs[b].status == STF_SWITCHED) switched[b] = hs[b].final_iter;
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms_loop = 0.f;
@@ -493,13 +517,14 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
     int worst = STF_OK;
     for (int b = 0; b < nprob; ++b) {
         stf_result& r = res[b];
-        r.status = hs[b].status;
-        r.iters = hs[b].final_iter;
-        r.kkt0 = hs[b].kkt0;
-        r.eta_last = hs[b].eta;
+        const DevState& hb = cur(b);
+        r.status = hb.status;
+        r.iters = hb.final_iter;
+        r.kkt0 = hb.kkt0;
+        r.eta_last = hb.eta;
         r.ms_loop = ms_loop;
         r.switch_iter = switched[b];
-        if (hs[b].status == STF_E_DIVERGED) {
+        if (hb.status == STF_E_DIVERGED) {
             r.kkt_abs = r.kkt_rel = r.feas = r.fval = NAN;
             worst = STF_E_DIVERGED;
             continue;
@@ -532,7 +557,7 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
         r.fval = he.red[0];
         r.kkt_abs = he.red[1];
         r.feas = he.red[2];
-        r.kkt_rel = (hs[b].kkt0 > 0.0) ? he.red[1] / hs[b].kkt0 : 0.0;
+        r.kkt_rel = (cur(b).kkt0 > 0.0) ? he.red[1] / cur(b).kkt0 : 0.0;
         if (r.status == STF_MAX_ITER && worst == STF_OK) worst = STF_MAX_ITER;
     }
     HIPCHK(hipEventRecord(e2, s));

@@ -44,8 +44,10 @@ struct DevParams {
     double* history;        // optional per-iteration record, (max_iter + 1) x 4
 };
 
-// Internal status of a reduced-precision phase that reached switch_tol.
+// Internal status of a reduced-precision phase that reached switch_tol, and
+// (batched solves) of one whose float64 continuation has taken over.
 #define STF_SWITCH 2
+#define STF_SWITCHED 3
 // Iterations without a new smallest stop-test value after which a
 // reduced-precision phase hands over even above switch_tol.
 constexpr int kSwitchStall = 400;
@@ -81,6 +83,7 @@ __host__ __device__ inline int col_groups(int nrb) {
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
     size_t state, state_eval, params, params_eval;
+    size_t state64, params64;  // batched float32 forms: the float64 continuation's
     size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
     size_t x64, g64;      // float64 n*p buffers: master iterate (float32 forms) and scratch
     size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
@@ -137,6 +140,12 @@ enum BStage {
 void launch_batched(int stage, int dtype, int precision, int variant_key, const BDesc* d,
                     const BGroup& grp, int parity, hipStream_t s);
 void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t s);
+// Batched per-problem hand-over: every problem whose reduced-precision state d32
+// reports STF_SWITCH gets its previous gradL (float32 buffer parity ^ 1)
+// converted into its float64 continuation's buffer parity ^ 1 and its state
+// copied to d64's (resumed) while d32's is marked STF_SWITCHED.
+void launch_batched_switch(const BDesc* d32, const BDesc* d64, int nprob, int parity,
+                           hipStream_t s);
 
 int elem_size(int dtype);
 // target_wg: workgroups the plan aims at (the single-problem defaults when omitted)

@@ -2446,6 +2446,37 @@ __global__ void kb_gather_states(const BDesc* __restrict__ D, int nprob,
     if (b < nprob) out[b] = *D[b].st;
 }
 
+// Per-problem hand-over of a batched float32 solve (see launch_batched_switch):
+// kSwitchWg workgroups per problem convert, then one thread per problem moves
+// the state (a separate launch, so that no workgroup reads the status after
+// it has changed).
+constexpr int kSwitchWg = 8;
+__global__ __launch_bounds__(256) void kb_switch_convert(const BDesc* __restrict__ D32,
+                                                         const BDesc* __restrict__ D64,
+                                                         int nprob, int parity) {
+    const int b = blockIdx.x / kSwitchWg, part = blockIdx.x % kSwitchWg;
+    if (b >= nprob) return;
+    const DevState* st = D32[b].st;
+    if (!(st->done && st->status == STF_SWITCH)) return;
+    const float* src = (const float*)D32[b].g[parity ^ 1];
+    double* dst = (double*)D64[b].g[parity ^ 1];
+    const int64_t np = D32[b].n * (int64_t)D32[b].p;
+    for (int64_t e = (int64_t)part * 256 + threadIdx.x; e < np; e += (int64_t)kSwitchWg * 256)
+        dst[e] = (double)src[e];
+}
+__global__ void kb_switch_state(const BDesc* __restrict__ D32, const BDesc* __restrict__ D64,
+                                int nprob) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nprob) return;
+    DevState* st = D32[b].st;
+    if (!(st->done && st->status == STF_SWITCH)) return;
+    DevState t = *st;
+    t.done = 0;
+    t.status = 0;
+    *D64[b].st = t;
+    st->status = STF_SWITCHED;
+}
+
 // =================================================================== host ===
 
 static inline unsigned grid_rows(int64_t n) {
@@ -2769,6 +2800,12 @@ void launch_eval_finish(const stf_problem* prob, const double* X, const double* 
 
 void launch_gather_states(const BDesc* d, int nprob, DevState* out, hipStream_t s) {
     kb_gather_states<<<(nprob + 63) / 64, 64, 0, s>>>(d, nprob, out);
+}
+
+void launch_batched_switch(const BDesc* d32, const BDesc* d64, int nprob, int parity,
+                           hipStream_t s) {
+    kb_switch_convert<<<(unsigned)nprob * kSwitchWg, 256, 0, s>>>(d32, d64, nprob, parity);
+    kb_switch_state<<<(nprob + 63) / 64, 64, 0, s>>>(d32, d64, nprob);
 }
 
 // One grouped launch of a batched stage; variant_key selects the template of

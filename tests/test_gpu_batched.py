@@ -138,8 +138,9 @@ def test_batched_tuner_and_budgets():
 
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
 def test_batched_handover_reaches_fp64_tolerance(precision):
-    """Float32 batches hand each problem over to float64 at switch_tol and
-    finish together in float64, at the oracle's minimum to 1e-8."""
+    """Float32 batches hand each problem over to float64 at switch_tol, each
+    as soon as it gets there (the others go on in float32 in the same
+    iterations), and every problem reaches the oracle's minimum to 1e-8."""
     probs, x0s = _batch()
     ol, gl = _opts(probs, precision=precision, max_iter=5000, tol=1e-8, orth=True,
                    check_every=50)
@@ -156,3 +157,25 @@ def test_batched_handover_reaches_fp64_tolerance(precision):
         assert ref.status == 0 and r["status"] == 0
         assert r["kkt_rel"] <= 1.01e-8
         assert abs(r["fval"] - ref.f) <= 1e-8 * abs(ref.f)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_batched_switch_at_start_is_the_fp64_form(precision):
+    """switch_tol >= 1: every problem hands over at k = 0 and then iterates in
+    float64 from its float32-rounded X0, so after 20 steps each iterate is the
+    float64 oracle's from that start up to the float32 rounding of the
+    returned X (1e-6; the float32 forms themselves are off by ~1e-4 here)."""
+    probs, x0s = _batch()
+    x0r = [x.astype(np.float32).astype(np.float64) for x in x0s]
+    k = 20
+    ol, gl = _opts(probs, precision=precision, max_iter=k)
+    for g in gl:
+        g.switch_tol = 2.0
+    res, rc, Xs, _ = _run(probs, x0r, gl)
+    for prob, x0, o, r, X in zip(probs, x0r, ol, res, Xs):
+        assert r["switch_iter"] == 0 and r["iters"] == k
+        o.record_iterates = [k]
+        ref = O.solve(OracleProblem(prob), x0, o)
+        err = rel(X, ref.iterates[k])
+        print(f"{precision} n={prob.n} p={prob.p}: float64 after the hand-over, error {err:.2e}")
+        assert err <= 1e-6
