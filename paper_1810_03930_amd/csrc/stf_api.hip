@@ -109,7 +109,6 @@ Layout make_layout(const stf_problem* prob, int precision) {
     L.Lam = take(pp);
     L.Bm = take(pp);
     L.T1 = take(pp);
-    L.T2 = take(pp);
     L.fpart = take((size_t)p * 8);
     L.nu = take((size_t)p * 8);
     L.colpart = take((size_t)32 * 2 * p * 8);
@@ -292,10 +291,8 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
                     RES_ITERATE, w.base + w.L.mix, s, ev ? ev[4] : nullptr);
     mark(5);
     launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
-                  w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Bm),
-                  w.at<double>(w.L.T1), w.at<double>(w.L.T2), w.at<double>(w.L.fpart),
-                  w.at<double>(w.L.colpart), w.at<double>(w.L.nu), p, c.st,
-                  s);
+                  w.at<double>(w.L.S), w.at<double>(w.L.T1), w.at<double>(w.L.fpart),
+                  w.at<double>(w.L.colpart), w.at<double>(w.L.nu), p, c.st, s);
     mark(6);
     launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s, c.Xm);
     mark(7);

@@ -299,7 +299,6 @@ int setup_batch(const BatchPlan& P, const stf_problem* probs, void* const* X,
         d.ML = at(L.ML);
         d.Bm = at(L.Bm);
         d.T1 = at(L.T1);
-        d.T2 = at(L.T2);
         d.fpart = at(L.fpart);
         d.nu = at(L.nu);
         d.colpart = at(L.colpart);

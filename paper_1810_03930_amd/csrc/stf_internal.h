@@ -88,7 +88,7 @@ struct Layout {
     size_t x64, g64;      // float64 n*p buffers: master iterate (float32 forms) and scratch
     size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
     size_t rho, phi, hscr;
-    size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, T2, fpart;
+    size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, fpart;  // T1: p x p product-pass partials
     size_t nu, colpart;   // colpart: col_groups(res.nrb) x 2p column-dot partials
     size_t gram_part;
     size_t res_col, res_scal, dots;
@@ -113,7 +113,7 @@ struct BDesc {
     void* X;           // iterate in the storage dtype (caller's buffer)
     double* Xm;        // float64 master iterate (float32 forms), else null
     void* g[2];        // G / gradL double buffer
-    double *rho, *phi, *S, *W, *Psi, *ML, *Bm, *T1, *T2, *fpart;
+    double *rho, *phi, *S, *W, *Psi, *ML, *Bm, *T1, *fpart;
     double *nu, *colpart, *gram_part, *res_col, *res_scal;
     __bf16* mix;
     DevState* st;
@@ -199,11 +199,11 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      const double* nu, int64_t n, int p, double* part_col,
                      double* part_scal, const DevParams* prm, DevState* st,
                      int mode, void* mix, hipStream_t s, hipEvent_t before_main = nullptr);
+// pp_part: the ((p+15)/16)^2 tile partials of the KKT identity's p x p term
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
-                   const double* part_scal, const double* S, const double* W,
-                   const double* Bm, const double* T1, const double* T2,
-                   const double* feas_part, double* colpart, double* nu,
-                   int p, DevState* st, hipStream_t s);
+                   const double* part_scal, const double* S, const double* pp_part,
+                   const double* feas_part, double* colpart, double* nu, int p, DevState* st,
+                   hipStream_t s);
 // Xm (float32 X only): float64 master iterate, read and written; X gets its rounding
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
                    const double* nu, double* rho, const DevState* st, hipStream_t s,

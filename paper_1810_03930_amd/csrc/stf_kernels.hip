@@ -1964,10 +1964,7 @@ __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
 __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
-                                                 const double* __restrict__ W,
-                                                 const double* __restrict__ Bm,
-                                                 const double* __restrict__ T1,
-                                                 const double* __restrict__ T2,
+                                                 const double* __restrict__ pp_part,
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
@@ -1995,7 +1992,7 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
         for (int i = t; i < p; i += blockDim.x) v[5] += colpart[2 * i + 1];
         // tile partials of <B, S B - 2 (W - S M_L)> from the p x p product pass
         const int nt = (p + 15) / 16;
-        for (int e = t; e < nt * nt; e += blockDim.x) v[6] += T1[e];
+        for (int e = t; e < nt * nt; e += blockDim.x) v[6] += pp_part[e];
     }
 #pragma unroll
     for (int q = 0; q < 7; ++q) sr[q][t] = v[q];
@@ -2116,15 +2113,12 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
 __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
-                                                 const double* __restrict__ W,
-                                                 const double* __restrict__ Bm,
-                                                 const double* __restrict__ T1,
-                                                 const double* __restrict__ T2,
+                                                 const double* __restrict__ pp_part,
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
                                                  DevState* __restrict__ st) {
-    body_stage2(prm, part_scal, nparts, S, W, Bm, T1, T2, feas_part, colpart, ncolg, nu, p, st,
+    body_stage2(prm, part_scal, nparts, S, pp_part, feas_part, colpart, ncolg, nu, p, st,
                 blockIdx.x, gridDim.x);
 }
 
@@ -2425,7 +2419,7 @@ __global__ __launch_bounds__(256) void kb_colreduce(STF_BATCH_ARGS) {
 
 __global__ __launch_bounds__(1024) void kb_stage2(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
-    body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.W, d.Bm, d.T1, d.T2, d.fpart,
+    body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.T1, d.fpart,
                 d.colpart, col_groups(d.res.nrb), d.nu, d.p, d.st, 0, 1);
 }
 
@@ -2734,12 +2728,12 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
 }
 
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
-                   const double* part_scal, const double* S, const double* W, const double* Bm,
-                   const double* T1, const double* T2, const double* feas_part, double* colpart,
-                   double* nu, int p, DevState* st, hipStream_t s) {
+                   const double* part_scal, const double* S, const double* pp_part,
+                   const double* feas_part, double* colpart, double* nu, int p, DevState* st,
+                   hipStream_t s) {
     const int ng = col_groups(rp.nrb);
     k_colreduce<<<dim3((2 * p + 63) / 64, ng), 256, 0, s>>>(part_col, rp.nrb, p, colpart, st);
-    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, W, Bm, T1, T2, feas_part,
+    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, pp_part, feas_part,
                                 colpart, ng, nu, p, st);
 }
 
