@@ -281,3 +281,21 @@ def test_reduced_precision_iterates_wide(precision, grid, p):
     print(f"{precision} form {grid} p={p}: relative iterate error after {k} steps = {err:.3e}")
     assert res["iters"] == k
     assert err <= 1e-5 * k
+
+
+@pytest.mark.parametrize("grid,p", [((20, 18, 16), 100), ((16, 16, 12), 300), ((9, 8, 7), 37)])
+@pytest.mark.parametrize("k", [1, 10])
+def test_fp64_iterates_ragged_tiles(grid, p, k):
+    """FP64 form with p off the tile grids: 64-column residual blocks (100:
+    the second half empty; 300: five blocks, the last 44 wide; 37: one partly
+    filled block), 128 x 128 Gram tiles with ragged edges, 16-deep K chunks
+    with a short last chunk; iterates to 1e-10 of the oracle."""
+    prob, x0, _ = W.ks3d(grid=grid, p=p)
+    o, g = _pair(prob, beta=4.0, max_iter=k)
+    o.record_iterates = [k]
+    ref = O.solve(OracleProblem(prob), x0, o)
+    res, X, _, _ = _gpu_solve(prob, x0, g)
+    err = rel(X, ref.iterates[k])
+    print(f"fp64 {grid} p={p}: relative iterate error after {k} steps = {err:.2e}")
+    assert res["iters"] == k
+    assert err <= 1e-10
