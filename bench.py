@@ -171,8 +171,11 @@ KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_resid
 KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gram_lds",
                ("fp64", "grad"): "body_grad_stencil", ("fp64", "update"): "body_update",
                ("mixed", "residual"): "body_residual_bf6_lds",
-               ("mixed", "gram"): "body_gram_bf3_lds", ("mixed", "grad"): "body_grad_stencil",
+               ("mixed", "gram"): "body_gram_bf3_lds", ("mixed", "grad"): "body_grad_line",
                ("mixed", "update"): "body_update"}
+# kernels that differ from KERNEL_NAMES in one form (the 3D gradient with a
+# float32 G walks runs of rows)
+KERNEL_NAMES_FORM = {("mixed", "grad"): "k_grad_line", ("fp32", "grad"): "k_grad_line"}
 
 
 def body_digest(name):
@@ -224,7 +227,8 @@ def roofline_for(form, precision, n, p):
         peak_f = PEAK_TFLOPS["mixed_bf16"] / mults.get(name, 1.0)
     t_mem = by / (HBM_PEAK_GBS * 1e9)
     traffic = traffic_for(name, precision)
-    common = {"kernel": KERNEL_NAMES[name], "group": name, "avg_launch_ms": ms,
+    common = {"kernel": KERNEL_NAMES_FORM.get((precision, name), KERNEL_NAMES[name]),
+              "group": name, "avg_launch_ms": ms,
               "algorithmic_bytes": by, "algorithmic_flops": fl,
               "traffic": traffic}
     if t_mma > t_mem and name in mults:

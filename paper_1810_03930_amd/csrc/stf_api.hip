@@ -33,6 +33,9 @@ GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg, bool wup) {
     nch = std::max<int64_t>(nch, 1);
     int64_t chunk = (n + nch - 1) / nch;
     chunk = (chunk + 3) / 4 * 4;
+    // the Gram kernels address a chunk's rows with 32-bit byte offsets
+    const int64_t max_chunk = std::max<int64_t>(4, ((int64_t(1) << 31) - 1) / (8 * (int64_t)p) / 4 * 4);
+    chunk = std::min(chunk, max_chunk);
     g.chunk = chunk;
     g.nchunks = (int)((n + chunk - 1) / chunk);
     return g;

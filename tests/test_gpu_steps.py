@@ -27,6 +27,7 @@ CASES_3D = [
     ((6, 7, 5), 9, 1.0),
     ((16, 16, 16), 70, 1.0),
     ((20, 18, 17), 130, 0.5),
+    ((9, 7, 5), 64, 1.0),
 ]
 
 
