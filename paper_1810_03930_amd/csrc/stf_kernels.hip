@@ -22,6 +22,7 @@
 #include "stf_internal.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace stf {
 
@@ -2744,41 +2745,45 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
     const double* ph = (prob->alpha != 0.0) ? phi : nullptr;
     const int nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
     const unsigned g = grid_rows(n);
-    // 3D with a float32 G: runs of kRun rows per wave when the rows split into
-    // 16-byte vectors (measured on 64^3 x 256: 0.27 against 0.32 ms for the
-    // one-wave-per-row form; no gain with a float64 G, and the 1D problems are
-    // too short for runs to fill the chip)
-    constexpr int kRun = 64;
-    int64_t gl = ((n + kRun - 1) / kRun + 3) / 4;
-    const unsigned glr = (unsigned)(gl > 65536 ? 65536 : (gl < 1 ? 1 : gl));
-#define STF_GRAD(TI, TO, ND, XP)                                                              \
-    do {                                                                                      \
-        if (ND == 6 && sizeof(TO) == 4 && p % (16 / (int)sizeof(TI)) == 0)                    \
-            k_grad_line<TI, TO, ND, kRun><<<glr, 256, 0, s>>>((const TI*)(XP), (TO*)G, n, p,  \
-                                                              nx, ny, nz, prob->v, ph,        \
-                                                              prob->alpha, st);               \
-        else                                                                                  \
-            k_grad_stencil<TI, TO, ND><<<g, 256, 0, s>>>((const TI*)(XP), (TO*)G, n, p, nx,   \
-                                                         ny, nz, prob->v, ph, prob->alpha,    \
-                                                         st);                                 \
-    } while (0)
+    auto run = [&](auto ti, auto to, auto nd, const void* XP) {
+        typedef decltype(ti) TI;
+        typedef decltype(to) TO;
+        constexpr int ND = decltype(nd)::value;
+        // 3D with a float32 G: runs of kRun rows per wave when the rows split into
+        // 16-byte vectors (measured on 64^3 x 256: 0.27 against 0.32 ms for the
+        // one-wave-per-row form; no gain with a float64 G, and the 1D problems are
+        // too short for runs to fill the chip)
+        if constexpr (ND == 6 && sizeof(TO) == 4) {
+            constexpr int kRun = 64;
+            if (p % (16 / (int)sizeof(TI)) == 0) {
+                const int64_t gl = ((n + kRun - 1) / kRun + 3) / 4;
+                const unsigned glr = (unsigned)(gl > 65536 ? 65536 : (gl < 1 ? 1 : gl));
+                k_grad_line<TI, TO, ND, kRun><<<glr, 256, 0, s>>>(
+                    (const TI*)XP, (TO*)G, n, p, nx, ny, nz, prob->v, ph, prob->alpha, st);
+                return;
+            }
+        }
+        k_grad_stencil<TI, TO, ND><<<g, 256, 0, s>>>((const TI*)XP, (TO*)G, n, p, nx, ny, nz,
+                                                     prob->v, ph, prob->alpha, st);
+    };
+    typedef std::integral_constant<int, 6> D3;
+    typedef std::integral_constant<int, 2> D1;
     if (prob->kind == STF_KIND_STENCIL3D) {
         if (dtype == STF_F64)
-            STF_GRAD(double, double, 6, X);
+            run(0.0, 0.0, D3(), X);
         else if (Xm)
             // float32 G of the float64 master iterate, stencil evaluated in float64
-            STF_GRAD(double, float, 6, Xm);
+            run(0.0, 0.0f, D3(), Xm);
         else
-            STF_GRAD(float, float, 6, X);
+            run(0.0f, 0.0f, D3(), X);
     } else {
         if (dtype == STF_F64)
-            STF_GRAD(double, double, 2, X);
+            run(0.0, 0.0, D1(), X);
         else if (Xm)
-            STF_GRAD(double, float, 2, Xm);
+            run(0.0, 0.0f, D1(), Xm);
         else
-            STF_GRAD(float, float, 2, X);
+            run(0.0f, 0.0f, D1(), X);
     }
-#undef STF_GRAD
 }
 
 template <typename T>

@@ -57,6 +57,18 @@ def test_gradient_3d(grid, p, alpha, dt):
     assert rel(to_np(g), g_ref) <= tol
 
 
+def test_gradient_3d_grid_stride():
+    """More 64-row runs than one launch of the line-walking gradient holds
+    (65536 workgroups x 4 waves): its grid-stride loop, float32 G, alpha = 0."""
+    prob, x0, _ = W.ks3d(grid=(256, 256, 260), p=4, alpha=0.0)
+    op = OracleProblem(prob)
+    x = to_dev(x0, torch.float32)
+    g_ref = op.grad(to_np(x))
+    dp = S.DeviceProblem.from_host(prob)
+    g = S.gradient(dp, x)
+    assert rel(to_np(g), g_ref) <= 2e-6
+
+
 @pytest.mark.parametrize("n,p", [(300, 37), (520, 130), (257, 64)])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_gradient_dense(n, p, dt):
