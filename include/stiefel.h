@@ -142,7 +142,7 @@ typedef struct stf_problem {
  *               forms stall where the rounding noise of their products (the
  *               row-block product X M_L and the Grams) dominates the
  *               Barzilai-Borwein quotients; this finishes the descent exactly.
- *               The hand-over also happens, above switch_tol, once 400
+ *               The hand-over also happens, above switch_tol, once 100
  *               iterations have passed without a new smallest stop-test value
  *               (a float32 descent that wanders instead of converging).
  * history     : device, (max_iter + 1) x 4 float64, or NULL: row k receives

@@ -50,7 +50,7 @@ struct DevParams {
 #define STF_SWITCHED 3
 // Iterations without a new smallest stop-test value after which a
 // reduced-precision phase hands over even above switch_tol.
-constexpr int kSwitchStall = 400;
+constexpr int kSwitchStall = 100;
 
 // Tiling of the split-K Gram pass.
 struct GramPlan {

@@ -247,7 +247,7 @@ def test_switch_reaches_fp64_tolerance(precision):
 
 def test_switch_on_stall():
     """With a switch_tol it cannot reach, a MIXED solve hands over once its
-    stop-test value has not improved for 400 iterations (its split-bf16 Grams
+    stop-test value has not improved for 100 iterations (its split-bf16 Grams
     put a floor far above 1e-10 under its own stop test), and the float64
     phase then reaches 1e-10.  (FP32 on this small grid drives its own stop
     test below 1e-10 -- it measures the float32-rounded G -- so it is not
@@ -261,7 +261,7 @@ def test_switch_on_stall():
     print(f"{precision}: hand-over on stall at k={res['switch_iter']}, converged at "
           f"{res['iters']}, kkt_rel {res['kkt_rel']:.2e}")
     assert res["rc"] == 0
-    assert 400 <= res["switch_iter"] < res["iters"]
+    assert 100 <= res["switch_iter"] < res["iters"]
     assert res["kkt_rel"] <= 1.01e-10
     _check_returned_point(op, res, X64, lam)
 
