@@ -23,7 +23,9 @@ Table 2); here it is CholeskyQR2 in float64.
 Readings where the paper is silent or ambiguous (each is a switch here):
   * BB pair: ``bb_index="standard"`` uses S = X^k - X^{k-1},
     Y = gradL^k - gradL^{k-1} for eta^k (the usual Barzilai-Borwein pair);
-    ``"lagged"`` uses S^{k-1}, Y^{k-1} exactly as printed in Section 5.1.
+    ``"lagged"`` uses S^{k-1}, Y^{k-1} exactly as printed in Section 5.1 for
+    the BB quotients.  The differential rule eta_D is printed with the newest
+    pair, so it uses (X^k - X^{k-1}, gradL^k - gradL^{k-1}) under both.
   * eta^0 is an input; k counts from 0, so ABB takes BB1 at odd k.
   * A rule whose quotient is not finite or not positive keeps eta^{k-1}.
   * PCAL updates all columns from X^k (one Jacobi sweep per iteration).
@@ -84,6 +86,10 @@ class Result:
     Lam: Optional[np.ndarray] = None
     history: Dict[str, List[float]] = field(default_factory=dict)
     iterates: Dict[int, np.ndarray] = field(default_factory=dict)
+    # for k in record_iterates (k < iters): the gradL^k the update of iteration k
+    # stepped with, and the multiplier Lambda^k it was formed with
+    grads: Dict[int, np.ndarray] = field(default_factory=dict)
+    mults: Dict[int, np.ndarray] = field(default_factory=dict)
 
 
 def kkt_residual(op, X: np.ndarray, G: Optional[np.ndarray] = None) -> float:
@@ -138,6 +144,8 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
     I = np.eye(p)
     hist: Dict[str, List[float]] = {"kkt_rel": [], "feas": [], "eta": [], "f": []}
     iterates: Dict[int, np.ndarray] = {}
+    grads: Dict[int, np.ndarray] = {}
+    mults: Dict[int, np.ndarray] = {}
     rec = set(int(k) for k in opt.record_iterates)
 
     X_prev = None          # X^{k-1}
@@ -193,7 +201,9 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
         elif k == 0:
             eta_k = float(opt.eta0)
         else:
-            if opt.bb_index == "standard":
+            # eta_D is defined with the newest pair under both readings; only the
+            # BB quotients are printed with the lagged pair
+            if opt.bb_index == "standard" or opt.eta_rule == "diff":
                 Sd = X - X_prev
                 Yd = gL - gL_prev
             else:
@@ -211,6 +221,9 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
         eta = eta_k
         if opt.record_history:
             hist["eta"].append(eta)
+        if k in rec:
+            grads[k] = gL.copy()
+            mults[k] = Lam.copy()
         # step 4: the proximal linearized update
         Y = X - gL / eta
         if opt.variant == "pcal":
@@ -225,17 +238,19 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
     if status == STATUS_DIVERGED:
         return Result(status=status, iters=k, X=X, Q=None, kkt0=kkt0 or np.nan,
                       kkt_abs=np.nan, kkt_rel=np.nan, feas=np.nan, f=np.nan,
-                      eta_last=eta, history=hist, iterates=iterates)
+                      eta_last=eta, history=hist, iterates=iterates,
+                      grads=grads, mults=mults)
     Q = cholqr2(X) if opt.orth_final else None
     if Q is not None:
         Gq = op.grad(Q)
         kkt_q = float(np.linalg.norm(Gq - Q @ Psi(Gq.T @ Q)))
         return Result(status=status, iters=k, X=X, Q=Q, kkt0=kkt0, kkt_abs=kkt_q,
                       kkt_rel=kkt_q / kkt0, feas=feasibility(Q), f=op.f(Q),
-                      eta_last=eta, Lam=Psi(Gq.T @ Q), history=hist, iterates=iterates)
+                      eta_last=eta, Lam=Psi(Gq.T @ Q), history=hist, iterates=iterates,
+                      grads=grads, mults=mults)
     return Result(status=status, iters=k, X=X, Q=None, kkt0=kkt0, kkt_abs=kkt,
                   kkt_rel=kkt / kkt0, feas=feas, f=op.f(X), eta_last=eta,
-                  Lam=Lam_psi, history=hist, iterates=iterates)
+                  Lam=Lam_psi, history=hist, iterates=iterates, grads=grads, mults=mults)
 
 
 def merit(op, X: np.ndarray, beta: float) -> float:

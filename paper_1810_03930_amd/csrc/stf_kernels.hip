@@ -2132,7 +2132,7 @@ __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
 
 // -------------------------------------------------------- p x p stage 2 ----
 // Divergence check, stop test (Section 5.1), eta^k (Section 5.1 rules), PCAL
-// column norms.  With prm->kkt_identity (float64 form) the stop test uses
+// column norms.  With prm->kkt_identity the stop test uses
 //   ||G - X Psi||^2 = ||gradL||^2 - 2 <W - S M_L, Bm> + <Bm, S Bm>
 // (G - X Psi = gradL - X Bm and X^T gradL = W - S M_L), whose terms are the
 // float64 column dots of the residual pass and p x p products.
@@ -2229,7 +2229,9 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
             } else {
                 double pss = ss, psy = sy, pyy = yy;
                 bool have = true;
-                if (prm->bb_index == STF_BB_LAGGED) {
+                // eta_D is defined with the newest pair; only the BB quotients
+                // are printed with the lagged one (Section 5.1)
+                if (prm->bb_index == STF_BB_LAGGED && rule != STF_ETA_DIFF) {
                     pss = st->ss_l;
                     psy = st->sy_l;
                     pyy = st->yy_l;

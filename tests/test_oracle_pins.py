@@ -147,23 +147,76 @@ def test_cholqr2_equals_householder_qr_up_to_signs():
     assert np.allclose(Q @ R, X, atol=1e-12)
 
 
+def test_cholqr2_second_pass_on_ill_conditioned_input():
+    """CholeskyQR loses orthogonality as kappa(X)^2 u; the second pass restores
+    it to the unit roundoff (Fukaya et al.; the post-process of Section 5.3).
+    At kappa = 3e6 one pass leaves ||Q^T Q - I|| ~ 1e-4, two leave ~1e-15."""
+    n, p = 400, 20
+    U, _ = np.linalg.qr(W.random_matrix(12, (n, p)))
+    V, _ = np.linalg.qr(W.random_matrix(13, (p, p)))
+    sig = np.logspace(0.0, -6.5, p)
+    X = (U * sig[None, :]) @ V.T
+    Q = O.cholqr2(X)
+    assert np.linalg.norm(Q.T @ Q - np.eye(p)) <= 1e-14 * p
+    # Q spans range(X) and X = Q R with R upper triangular
+    R = Q.T @ X
+    assert np.linalg.norm(np.tril(R, -1)) <= 1e-12 * np.linalg.norm(R)
+    assert np.linalg.norm(Q @ R - X) <= 1e-13 * np.linalg.norm(X)
+    # the test discriminates: a single CholeskyQR pass misses the bound by far
+    c = np.linalg.cholesky(X.T @ X)
+    Q1 = np.linalg.solve(c, X.T).T
+    assert np.linalg.norm(Q1.T @ Q1 - np.eye(p)) >= 1e-8
+
+
 # ------------------------------------------------------------- iteration --
-def test_pcal_columns_unit_norm_and_tangent_step():
-    """PCAL iterates have unit columns (closed form of Section 3.2) and, with
-    the Phi-corrected multiplier, diag(X^T gradL) = 0 at unit columns."""
-    prob, x0 = W.quad_tridiag(n=200, p=6)
+def _aug_lagrangian(op, X, Lam, beta):
+    """L_beta(X, Lam) = f(X) - 1/2 <Lam, X^T X - I> + beta/4 ||X^T X - I||_F^2, eq. (Lag)."""
+    C = X.T @ X - np.eye(X.shape[1])
+    return op.f(X) - 0.5 * float(np.sum(Lam * C)) + 0.25 * beta * float(np.sum(C * C))
+
+
+@pytest.mark.parametrize("mult", ["psi_phi", "psi"])
+def test_pcal_step_is_gradient_of_lagrangian_and_tangent(mult):
+    """The step PCAL takes (Alg. 3, closed form after (PLLagSph)):
+
+    * gradL^k is the Euclidean gradient of L_beta(., Lam^k) at X^k, eq. (Lag),
+      checked by central differences of L_beta itself (pins the sign of X Lam,
+      the factor of the beta term);
+    * with the Phi-corrected multiplier eq. (lambda2) and unit columns,
+      X_i^T gradL_i = 0 for every column i (the correction removes exactly the
+      radial part; a dropped, sign-flipped or wrongly built correction leaves
+      it nonzero), while eq. (Lambda1) leaves it nonzero;
+    * X^{k+1}_i = (X^k_i - gradL^k_i/eta^k) / ||.||, so under eq. (lambda2)
+      the normalizer is sqrt(1 + ||gradL_i||^2 / eta^2);
+    * the iterates keep unit columns.
+    """
+    prob, x0 = W.ks1d(n=160, p=6, alpha=1.0, config=2, with_potential=True)
     op = OracleProblem(prob)
-    opt = O.Options(variant="pcal", beta=1.0, eta0=6.0, tol=0.0, max_iter=7,
-                    record_iterates=[7])
+    beta = 30.0
+    ks = [0, 1, 4, 9]
+    opt = O.Options(variant="pcal", mult=mult, beta=beta, eta0=beta + prob.s_bound, tol=0.0,
+                    max_iter=10, record_history=True, record_iterates=ks + [k + 1 for k in ks])
     res = O.solve(op, x0, opt)
-    X = res.iterates[7]
-    assert np.allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-14)
-    G = op.grad(X)
-    Psi = O.Psi(G.T @ X)
-    R = O.grad_lagrangian(X, G, Psi, opt.beta)
-    D = O.Phi(X.T @ R)
-    gL = R - X @ D
-    assert np.max(np.abs(np.diag(X.T @ gL))) <= 1e-13 * np.linalg.norm(gL)
+    for k in ks:
+        X, gL, Lam, eta = res.iterates[k], res.grads[k], res.mults[k], res.history["eta"][k]
+        assert np.allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-14)
+        xi = W.random_matrix(11, X.shape, salt=k)
+
+        def cd(h):
+            return (_aug_lagrangian(op, X + h * xi, Lam, beta)
+                    - _aug_lagrangian(op, X - h * xi, Lam, beta)) / (2 * h)
+        fd = (4.0 * cd(5e-5) - cd(1e-4)) / 3.0      # Richardson: O(h^4) error
+        assert abs(float(np.sum(gL * xi)) - fd) <= 1e-9 * abs(fd), (k, mult)
+        radial = np.abs(np.einsum("ij,ij->j", X, gL))
+        if mult == "psi_phi":
+            assert radial.max() <= 1e-13 * np.linalg.norm(gL), k
+            nrm = np.sqrt(1.0 + np.sum(gL * gL, axis=0) / eta ** 2)
+        else:
+            # at the orthonormal X^0 both multipliers coincide (W symmetric, S = I)
+            assert k == 0 or radial.max() >= 1e-6 * np.linalg.norm(gL), k
+            nrm = np.linalg.norm(X - gL / eta, axis=0)
+        Xn = (X - gL / eta) / nrm[None, :]
+        assert np.max(np.abs(Xn - res.iterates[k + 1])) <= 1e-13, k
 
 
 def test_ky_fan_quadratic_small():
@@ -269,7 +322,8 @@ def test_bb_indexing_standard_and_lagged():
             assert Ke >= 4
             gL = {k: eta[k] * (Xs[k] - Xs[k + 1]) for k in range(Ke)}
             for k in range(2, Ke):
-                if bb == "standard":
+                if bb == "standard" or rule == "diff":
+                    # eta_D is printed with the newest pair (Section 5.1)
                     Sd, Yd = Xs[k] - Xs[k - 1], gL[k] - gL[k - 1]
                 else:
                     Sd, Yd = Xs[k - 1] - Xs[k - 2], gL[k - 1] - gL[k - 2]
