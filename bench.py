@@ -443,7 +443,9 @@ def main():
         "time_to_kkt_s_median": None if args.skip_ttk else
         {"fp64": base["time_to_kkt_s_median"], args.fast_form: fast["time_to_kkt_s_median"],
          "starts": args.starts},
-        "speedup_time_to_kkt": None if args.skip_ttk else
+        # seed 0 alone: only when both forms reached the tolerance from it
+        "speedup_time_to_kkt": None if (args.skip_ttk or not base["reached_per_start"][0]
+                                        or not fast["reached_per_start"][0]) else
         base["time_to_kkt_s"] / fast["time_to_kkt_s"],
         "speedup_time_to_kkt_median": None if (args.skip_ttk or not fast["time_to_kkt_s_median"]
                                                or not base["time_to_kkt_s_median"]) else

@@ -29,9 +29,9 @@
  *     are independent.
  *   - All device work is enqueued on `stream`; the solve entry points return
  *     after the final status has been read back (host-synchronous).
- *   - Return codes: STF_OK (0), STF_MAX_ITER (1, a result is still filled),
- *     or a negative STF_E_* code; stf_strerror() names them.  No C++
- *     exception crosses this boundary.
+ *   - Return codes: STF_OK (0), STF_MAX_ITER (1) or STF_TOL_UNMET (2) (a
+ *     result is still filled), or a negative STF_E_* code; stf_strerror()
+ *     names them.  No C++ exception crosses this boundary.
  */
 #ifndef STIEFEL_H
 #define STIEFEL_H
@@ -68,7 +68,9 @@ extern "C" {
 #define STF_ETA_ABB   4
 
 /* BB pair: STANDARD uses S = X^k - X^{k-1}, Y = gradL^k - gradL^{k-1} for
- * eta^k; LAGGED uses S^{k-1}, Y^{k-1} as printed in Section 5.1. */
+ * eta^k; LAGGED uses S^{k-1}, Y^{k-1} in the BB quotients as printed in
+ * Section 5.1.  The differential rule is printed with the newest pair and
+ * uses it under both settings. */
 #define STF_BB_STANDARD 0
 #define STF_BB_LAGGED   1
 
@@ -88,8 +90,10 @@ extern "C" {
 #define STF_PREC_MIXED 2
 
 /* ---- return codes -------------------------------------------------------- */
-#define STF_OK               0
+#define STF_OK               0   /* the float64 check of the returned point meets tol */
 #define STF_MAX_ITER         1
+#define STF_TOL_UNMET        2   /* the in-loop stop test was met, but the float64
+                                    KKT of the returned point is above tol */
 #define STF_E_INVALID       -1   /* bad argument: p <= 0, n < 2p, NULL, dtype, sizes */
 #define STF_E_DIVERGED      -2   /* non-finite values or ||X^T X - I||_F above feas_blowup */
 #define STF_E_HIP           -3   /* a HIP runtime call failed */
@@ -172,7 +176,7 @@ typedef struct stf_options {
 } stf_options;
 
 /* ---- result (host struct) -------------------------------------------------
- * status  : STF_OK / STF_MAX_ITER / STF_E_DIVERGED
+ * status  : STF_OK / STF_MAX_ITER / STF_TOL_UNMET / STF_E_DIVERGED
  * iters   : index k of the returned iterate X^k (number of updates made)
  * kkt0    : ||G - X Psi(G^T X)||_F at X^0 (iteration precision)
  * kkt_abs : the same at the returned point, float64 (after CholeskyQR2 if
@@ -243,31 +247,46 @@ int pcal_solve(const stf_problem* prob, void* X, const stf_options* opt,
 
 /* ---- step-level entry points (each is one step of the iteration) --------- */
 
-/* G = grad f(X) = (L + Diag v) X + alpha Diag(L^{-1} rho) X, or A X (dense).
+/* G = grad f(X) = (L + Diag v) X + alpha Diag(L^{-1} rho) X, or A X (dense):
+ * the gradients of Problem 1 (the simplified Kohn-Sham energy, with the
+ * operators of the workloads) and Problem 3 (Rayleigh-Ritz) of Section 5.2,
+ * "Func" in Table 1.
  * X, G: device n x p of dtype (STF_F64 / STF_F32); the dense kind requires
- * dtype == A_dtype.  Computes rho and the Hartree solve internally. */
+ * dtype == A_dtype.  Computes rho and the Hartree solve internally (in the
+ * workspace).  Errors: STF_E_INVALID (NULL, bad dtype), STF_E_UNSUPPORTED
+ * (dense dtype mismatch), STF_E_WORKSPACE, STF_E_HIP.  Host-synchronous. */
 int stf_gradient(const stf_problem* prob, const void* X, void* G, int32_t dtype,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* phi = L^{-1} rho for the stencil kinds (the L^dagger of eq. (KS-energy));
+/* phi = L^{-1} rho for the stencil kinds (the L^dagger of eq. (KS-energy) and
+ * of Problem 1, Section 5.2);
  * rho, phi: device float64 length n.  1D: closed-form Green's function by
  * two scans; 3D: sine transforms along each axis. */
 int stf_hartree(const stf_problem* prob, const double* rho, double* phi,
                 void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* S = X^T X and W = X^T G (both p x p float64, full), the Gram products of
- * Table 1.  precision selects the product arithmetic (STF_PREC_*; FP64
- * needs dtype F64, the others F32). */
+/* S = X^T X and W = X^T G (both p x p float64, full, row-major), the Gram
+ * products of Table 1 ("feasibility" and "KKT" rows) that feed the
+ * multiplier of eq. (Lambda1).  X, G: device n x p of dtype.  precision
+ * selects the product arithmetic (STF_PREC_*; FP64 needs dtype F64, the
+ * others F32).  Host-synchronous. */
 int stf_gram(const stf_problem* prob, const void* X, const void* G, int32_t dtype,
              int32_t precision, double* S, double* W, void* ws, size_t ws_bytes,
              hipStream_t stream);
 
-/* In-place CholeskyQR2 of a float64 n x p X (full column rank). */
+/* In-place CholeskyQR2 of a float64 n x p X (full column rank): the
+ * orthonormalization post-process of Section 5.3 (Table 2), Cholesky-based as
+ * in the parallel experiments of Section 5.5, applied twice.  Returns
+ * STF_E_CHOLESKY (X unchanged in its first pass, or partly transformed) when a
+ * pivot is not positive (X rank-deficient to working precision). */
 int stf_cholqr2(const stf_problem* prob, double* X, void* ws, size_t ws_bytes,
                 hipStream_t stream);
 
 /* out3 (host, 3 doubles) = { f(X), ||G - X Psi(G^T X)||_F, ||X^T X - I||_F }
- * in float64 for a float64 X. */
+ * in float64 for a float64 X: the objective, the KKT violation of the stop
+ * test of Section 5.1 (with X Psi in place of X G^T X, as Section 3.3 notes)
+ * and the feasibility violation, the three columns of Table 2.  The dense
+ * kind needs A_dtype == STF_F64.  Host-synchronous. */
 int stf_eval(const stf_problem* prob, const double* X, double* out3,
              void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -317,8 +336,9 @@ int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* L
  *            (stf_result.switch_iter per problem)
  *   ws     : device workspace of ws_bytes >= stf_batched_workspace_size()
  *   res    : host array of nprob results (ms_loop / ms_orth: the whole batch)
- * Returns the lowest per-problem status: STF_OK when every problem converged,
- * STF_MAX_ITER when some reached max_iter, else the first STF_E_* met. */
+ * Returns the first STF_E_* met, else STF_MAX_ITER when some problem reached
+ * max_iter, else STF_TOL_UNMET when some problem's float64 check is above its
+ * tol, else STF_OK (every problem converged). */
 size_t stf_batched_workspace_size(int32_t nprob, const stf_problem* probs,
                                   const stf_options* opts);
 int stf_solve_batched(int32_t nprob, const stf_problem* probs, void* const* X,

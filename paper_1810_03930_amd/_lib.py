@@ -19,7 +19,7 @@ MULT_PSI, MULT_PSI_PHI = 0, 1
 ETA_CONST, ETA_DIFF, ETA_BB1, ETA_BB2, ETA_ABB = 0, 1, 2, 3, 4
 BB_STANDARD, BB_LAGGED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
-OK, MAX_ITER = 0, 1
+OK, MAX_ITER, TOL_UNMET = 0, 1, 2
 E_INVALID, E_DIVERGED, E_HIP, E_UNSUPPORTED, E_WORKSPACE, E_CHOLESKY = -1, -2, -3, -4, -5, -6
 
 

@@ -11,8 +11,9 @@
 // the adjoint zeta solves Hess[zeta] = P(g) for the loss gradient g = dl/dX*,
 // and dl/dV_j = -rowdot(zeta, X)_j  (d grad f / dV along dV is Diag(dV) X).
 // Hess is symmetric on the horizontal space; conjugate gradients runs on it in
-// float64, every vector operation on the device, one 16-byte read-back of the
-// two CG inner products per step.
+// float64, every vector operation and both step scalars on the device, with one
+// 16-byte read-back per step (<d, Hd> for the positivity check and the new
+// <r, r> for the stop test).
 #include <math.h>
 #include <string.h>
 
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ a,
 }
 
 __global__ __launch_bounds__(256) void k_dot_finish(const double* __restrict__ part, int nb,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int nout) {
     __shared__ double sh[2][256];
     double s0 = 0.0, s1 = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) {
@@ -102,15 +103,17 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double* __restrict__ p
     }
     if (threadIdx.x == 0) {
         out[0] = sh[0][0];
-        out[1] = sh[1][0];
+        if (nout > 1) out[1] = sh[1][0];
     }
 }
 
-// z += a d;  r -= a Hd
+// CG scalars on the device: sc[0] = <r, r>, sc[1] = <d, Hd>, sc[2] = the new <r, r>.
+// z += a d;  r -= a Hd  with a = sc[0] / sc[1]
 __global__ __launch_bounds__(256) void k_cg_step(double* __restrict__ z, double* __restrict__ r,
                                                  const double* __restrict__ d,
-                                                 const double* __restrict__ Hd, double a,
-                                                 size_t m) {
+                                                 const double* __restrict__ Hd,
+                                                 const double* __restrict__ sc, size_t m) {
+    const double a = sc[0] / sc[1];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (size_t)gridDim.x * blockDim.x) {
         z[e] += a * d[e];
@@ -118,14 +121,18 @@ __global__ __launch_bounds__(256) void k_cg_step(double* __restrict__ z, double*
     }
 }
 
-// d = r + b d
+// d = r + b d  with b = sc[2] / sc[0]
 __global__ __launch_bounds__(256) void k_cg_dir(double* __restrict__ d,
-                                                const double* __restrict__ r, double b,
-                                                size_t m) {
+                                                const double* __restrict__ r,
+                                                const double* __restrict__ sc, size_t m) {
+    const double b = sc[2] / sc[0];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (size_t)gridDim.x * blockDim.x)
         d[e] = r[e] + b * d[e];
 }
+
+// sc[0] = sc[2] (after every thread of k_cg_dir has read both)
+__global__ void k_cg_shift(double* __restrict__ sc) { sc[0] = sc[2]; }
 
 struct AdjLayout {
     size_t z, r, d, hd, t;             // n x p float64
@@ -170,7 +177,7 @@ static AdjLayout make_adj_layout(const stf_problem* prob) {
         L.dst = take(8);
     }
     L.dots = take(1024 * 2 * 8);
-    L.dot2 = take(2 * 8);
+    L.dot2 = take(4 * 8);
     L.total = off;
     return L;
 }
@@ -222,14 +229,18 @@ static void hess_apply(const AdjCtx& c, const double* d, double* Hd, hipStream_t
     project_inplace(c, Hd, s);
 }
 
-// the two inner products <a,b>, <c,d> read back to the host
-static int dots(const AdjCtx& c, const double* a, const double* b, const double* cc,
-                const double* d, double out[2], hipStream_t s) {
+// <a, b> into the device scalar *out (no read-back)
+static void dot_dev(const AdjCtx& c, const double* a, const double* b, double* out,
+                    hipStream_t s) {
     const size_t m = (size_t)c.prob->n * c.prob->p;
     const int nb = 1024;
-    k_dot2<<<nb, 256, 0, s>>>(a, b, cc, d, m, c.at<double>(c.L.dots));
-    k_dot_finish<<<1, 256, 0, s>>>(c.at<double>(c.L.dots), nb, c.at<double>(c.L.dot2));
-    if (hipMemcpyAsync(out, c.at<double>(c.L.dot2), 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+    k_dot2<<<nb, 256, 0, s>>>(a, b, nullptr, nullptr, m, c.at<double>(c.L.dots));
+    k_dot_finish<<<1, 256, 0, s>>>(c.at<double>(c.L.dots), nb, out, 1);
+}
+
+// read `cnt` device scalars back to the host (the one synchronization of a CG step)
+static int read_scalars(const double* dev, double* host, int cnt, hipStream_t s) {
+    if (hipMemcpyAsync(host, dev, (size_t)cnt * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
         return STF_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return STF_E_HIP;
     return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP;
@@ -269,8 +280,10 @@ static int adjoint_impl(const stf_problem* prob, const double* X, const double* 
     project_inplace(c, r, s);
     if (hipMemcpyAsync(d, r, m * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return STF_E_HIP;
     if (hipMemsetAsync(z, 0, m * 8, s) != hipSuccess) return STF_E_HIP;
+    double* sc = c.at<double>(c.L.dot2);
     double dd[2];
-    int rc = dots(c, r, r, nullptr, nullptr, dd, s);
+    dot_dev(c, r, r, sc, s);
+    int rc = read_scalars(sc, dd, 1, s);
     if (rc) return rc;
     const double b2 = dd[0];
     double rr = b2;
@@ -278,18 +291,18 @@ static int adjoint_impl(const stf_problem* prob, const double* X, const double* 
     if (b2 > 0.0) {
         for (it = 1; it <= cg_maxit; ++it) {
             hess_apply(c, d, hd, s);
-            if ((rc = dots(c, d, hd, nullptr, nullptr, dd, s))) return rc;
-            const double dHd = dd[0];
+            dot_dev(c, d, hd, sc + 1, s);
+            k_cg_step<<<grid_elems(m), 256, 0, s>>>(z, r, d, hd, sc, m);
+            dot_dev(c, r, r, sc + 2, s);
+            if ((rc = read_scalars(sc + 1, dd, 2, s))) return rc;
+            const double dHd = dd[0], rr_new = dd[1];
             if (!(dHd > 0.0) || !isfinite(dHd)) return STF_E_DIVERGED;  // not positive definite
-            const double a = rr / dHd;
-            k_cg_step<<<grid_elems(m), 256, 0, s>>>(z, r, d, hd, a, m);
-            if ((rc = dots(c, r, r, nullptr, nullptr, dd, s))) return rc;
-            const double rr_new = dd[0];
             if (rr_new <= cg_tol * cg_tol * b2) {
                 rr = rr_new;
                 break;
             }
-            k_cg_dir<<<grid_elems(m), 256, 0, s>>>(d, r, rr_new / rr, m);
+            k_cg_dir<<<grid_elems(m), 256, 0, s>>>(d, r, sc, m);
+            k_cg_shift<<<1, 1, 0, s>>>(sc);
             rr = rr_new;
         }
     }

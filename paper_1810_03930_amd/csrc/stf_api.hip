@@ -537,10 +537,15 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     res->kkt_abs = he.red[1];
     res->feas = he.red[2];
     res->kkt_rel = (hs.kkt0 > 0.0) ? he.red[1] / hs.kkt0 : 0.0;
+    // the in-loop stop test ran in the iteration's arithmetic on the iterate;
+    // "converged" is reported only when the float64 check of the returned
+    // point agrees
+    if (res->status == STF_OK && hs.kkt0 > 0.0 && !(he.red[1] <= opt->tol * hs.kkt0))
+        res->status = STF_TOL_UNMET;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipEventDestroy(e2);
-    return hs.status;
+    return res->status;
 }
 
 }  // namespace stf
@@ -672,6 +677,8 @@ const char* stf_strerror(int code) {
     switch (code) {
         case STF_OK: return "converged";
         case STF_MAX_ITER: return "maximum number of iterations reached";
+        case STF_TOL_UNMET:
+            return "stop test met in the iteration, float64 check of the returned point above tol";
         case STF_E_INVALID: return "invalid argument";
         case STF_E_DIVERGED: return "iteration diverged (non-finite values or infeasibility blow-up)";
         case STF_E_HIP: return "HIP runtime error";

@@ -557,7 +557,11 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
         r.kkt_abs = he.red[1];
         r.feas = he.red[2];
         r.kkt_rel = (cur(b).kkt0 > 0.0) ? he.red[1] / cur(b).kkt0 : 0.0;
-        if (r.status == STF_MAX_ITER && worst == STF_OK) worst = STF_MAX_ITER;
+        if (r.status == STF_OK && cur(b).kkt0 > 0.0 && !(he.red[1] <= opts[b].tol * cur(b).kkt0))
+            r.status = STF_TOL_UNMET;
+        // aggregate: the first error, else MAX_ITER, else TOL_UNMET, else OK
+        if (worst >= 0 && r.status > 0)
+            worst = (worst == STF_MAX_ITER || r.status == STF_MAX_ITER) ? STF_MAX_ITER : r.status;
     }
     HIPCHK(hipEventRecord(e2, s));
     HIPCHK(hipEventSynchronize(e2));

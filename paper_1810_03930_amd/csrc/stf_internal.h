@@ -46,8 +46,8 @@ struct DevParams {
 
 // Internal status of a reduced-precision phase that reached switch_tol, and
 // (batched solves) of one whose float64 continuation has taken over.
-#define STF_SWITCH 2
-#define STF_SWITCHED 3
+#define STF_SWITCH 16
+#define STF_SWITCHED 17
 // Iterations without a new smallest stop-test value after which a
 // reduced-precision phase hands over even above switch_tol.
 constexpr int kSwitchStall = 100;

@@ -37,3 +37,12 @@ def green_1d_extended(rho):
     B = np.cumsum(t[::-1])[::-1] - t              # sum_{j > i} (n+1-j) rho_j
     phi = ((n + 1 - j) * A + j * B) / (n + 1)
     return phi.astype(np.float64)
+
+
+def assert_converged(rc, kkt_rel, tol, slack=1.01):
+    """The status contract of a converged solve: STF_OK (0) exactly when the
+    float64 check of the returned point meets tol; a point just above it after
+    the orthonormalization post-process is STF_TOL_UNMET (2)."""
+    assert rc in (0, 2), rc
+    assert (rc == 0) == (kkt_rel <= tol), (rc, kkt_rel, tol)
+    assert kkt_rel <= slack * tol, (kkt_rel, tol)
