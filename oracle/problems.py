@@ -31,6 +31,18 @@ The Hartree solve phi = L^{-1} rho:
   orthonormal DST-I along each axis, and phi = S D^{-1} S rho.  The DST-I is
   taken from scipy.fft (a library primitive).  A sparse LU of the 3D
   operator is not used because its fill makes it take many minutes.
+
+Further terms of the test problems of Section 5.2 (each absent when zero / None):
+
+* a block-diagonal L = Diag(L_1, ..., L_s) of tridiag(-1,2,-1) blocks of order
+  ``block`` (the last block may be shorter): the 1D operator of the parallel
+  experiments of Section 5.5; its inverse is block-diagonal, each block the
+  textbook Green's function of the block;
+* the exchange term of Problem 6, -3/4 gamma rho^T rho^{1/3}, whose gradient is
+  -2 gamma Diag(rho^{1/3}) X (d rho_j / d X_ji = 2 X_ji);
+* the linear term tr(Glin^T X) of Problem 2, gradient Glin;
+* the right factor B of Problem 4: f = 1/2 tr(A^T X B X^T) = 1/2 tr(X^T A X B)
+  for symmetric A and B, gradient A X B.
 """
 from __future__ import annotations
 
@@ -40,8 +52,13 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def laplacian_1d(n: int) -> sp.csr_matrix:
-    """tridiag(-1, 2, -1) of order n (unscaled 1D Dirichlet Laplacian)."""
+def laplacian_1d(n: int, block: int = 0) -> sp.csr_matrix:
+    """tridiag(-1, 2, -1) of order n (unscaled 1D Dirichlet Laplacian), or with
+    ``block`` > 0 the block-diagonal matrix of such blocks of order ``block``
+    (the last one shorter when block does not divide n)."""
+    if block and block < n:
+        sizes = [block] * (n // block) + ([n % block] if n % block else [])
+        return sp.block_diag([laplacian_1d(m) for m in sizes], format="csr")
     e = np.ones(n)
     return sp.diags([-e[:-1], 2.0 * e, -e[:-1]], [-1, 0, 1], format="csr")
 
@@ -86,13 +103,19 @@ class OracleProblem:
         self.alpha = float(prob.alpha)
         self.grid = tuple(prob.grid)
         self.s_bound = float(prob.s_bound)
+        self.block = int(getattr(prob, "block", 0) or 0)
+        self.gamma = float(getattr(prob, "gamma", 0.0) or 0.0)
+        gl = getattr(prob, "Glin", None)
+        self.Glin = None if gl is None else np.asarray(gl, dtype=np.float64)
+        b = getattr(prob, "B", None)
+        self.B = None if b is None else np.asarray(b, dtype=np.float64)
         if prob.kind == "dense":
             self.A = np.asarray(prob.A, dtype=np.float64)
             self.L = None
             self.H0 = None
         else:
             if prob.kind == "stencil1d":
-                self.L = laplacian_1d(self.n)
+                self.L = laplacian_1d(self.n, self.block)
             elif prob.kind == "stencil3d":
                 self.L = laplacian_3d(self.grid)
             else:
@@ -123,8 +146,15 @@ class OracleProblem:
             # residual rho - T phi in extended precision, then one correction solve
             pe = phi.astype(np.longdouble)
             t = 2 * pe
-            t[1:] -= pe[:-1]
-            t[:-1] -= pe[1:]
+            left = pe[:-1].copy()
+            right = pe[1:].copy()
+            if self.block and self.block < self.n:
+                # no coupling across block boundaries
+                cut = np.arange(self.block, self.n, self.block)
+                left[cut - 1] = 0
+                right[cut - 1] = 0
+            t[1:] -= left
+            t[:-1] -= right
             resid = (rho.astype(np.longdouble) - t).astype(np.float64)
             return phi + self._lu.solve(resid)
         nx, ny, nz = self.grid
@@ -140,19 +170,35 @@ class OracleProblem:
             return self.A @ X
         return self.H0 @ X
 
+    def _quad(self, X: np.ndarray) -> np.ndarray:
+        """The gradient of the quadratic part: H0 X, or H0 X B (Problem 4)."""
+        t = self.apply_h0(X)
+        return t if self.B is None else t @ self.B
+
     # -- f and grad f ------------------------------------------------------
     def f(self, X: np.ndarray) -> float:
-        val = 0.5 * float(np.sum(X * self.apply_h0(X)))
-        if self.alpha != 0.0:
+        val = 0.5 * float(np.sum(X * self._quad(X)))
+        if self.Glin is not None:
+            val += float(np.sum(self.Glin * X))
+        if self.alpha != 0.0 or self.gamma != 0.0:
             rho = self.density(X)
-            val += 0.25 * self.alpha * float(rho @ self.hartree(rho))
+            if self.alpha != 0.0:
+                val += 0.25 * self.alpha * float(rho @ self.hartree(rho))
+            if self.gamma != 0.0:
+                val -= 0.75 * self.gamma * float(rho @ np.cbrt(rho))
         return val
 
     def grad(self, X: np.ndarray) -> np.ndarray:
-        g = self.apply_h0(X)
-        if self.alpha != 0.0:
-            phi = self.hartree(self.density(X))
-            g = g + self.alpha * phi[:, None] * X
+        g = self._quad(X)
+        if self.Glin is not None:
+            g = g + self.Glin
+        if self.alpha != 0.0 or self.gamma != 0.0:
+            rho = self.density(X)
+            if self.alpha != 0.0:
+                phi = self.hartree(rho)
+                g = g + self.alpha * phi[:, None] * X
+            if self.gamma != 0.0:
+                g = g - 2.0 * self.gamma * np.cbrt(rho)[:, None] * X
         return g
 
     def hess_vec(self, X: np.ndarray, xi: np.ndarray) -> np.ndarray:
@@ -161,10 +207,16 @@ class OracleProblem:
         Differentiating grad f along xi: H0 xi + alpha Diag(phi) xi
         + alpha Diag(L^{-1} d rho) X with d rho = 2 rowdot(X, xi).
         """
-        out = self.apply_h0(xi)
+        out = self._quad(xi)
+        drho = 2.0 * np.einsum("ij,ij->i", X, xi)
         if self.alpha != 0.0:
             phi = self.hartree(self.density(X))
-            drho = 2.0 * np.einsum("ij,ij->i", X, xi)
             dphi = self.hartree(drho)
             out = out + self.alpha * (phi[:, None] * xi + dphi[:, None] * X)
+        if self.gamma != 0.0:
+            # d/dt of -2 gamma rho^{1/3} X: -2 gamma (rho^{1/3} xi + rho^{-2/3} drho / 3 X)
+            rho = self.density(X)
+            c = np.cbrt(rho)
+            out = out - 2.0 * self.gamma * (c[:, None] * xi
+                                            + (drho / (3.0 * c * c))[:, None] * X)
         return out

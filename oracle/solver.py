@@ -64,6 +64,7 @@ class Options:
     tol: float = 1e-8
     max_iter: int = 3000
     mult: str = "psi_phi"          # "psi" (eq. Lambda1) | "psi_phi" (eq. lambda2, PCAL only)
+                                   # | "dual" (dual ascent, eq. (Lambda-alm): PLAM-DA / PCAL-DA)
     bb_index: str = "standard"     # "standard" | "lagged"
     orth_final: bool = True
     feas_blowup: float = 1e3
@@ -139,6 +140,8 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
         raise ValueError(opt.variant)
     if opt.mult == "psi_phi" and opt.variant != "pcal":
         raise ValueError("the Phi-corrected multiplier belongs to PCAL")
+    if opt.mult not in ("psi", "psi_phi", "dual"):
+        raise ValueError(opt.mult)
     X = np.array(X0, dtype=np.float64, copy=True)
     n, p = X.shape
     I = np.eye(p)
@@ -157,6 +160,7 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
     status = STATUS_MAX_ITER
     k = 0
     Lam = None
+    Lam_da = None          # the dual-ascent multiplier Lambda^{k-1}
     while True:
         if not np.all(np.isfinite(X)):
             status = STATUS_DIVERGED
@@ -192,6 +196,14 @@ def solve(op, X0: np.ndarray, opt: Options) -> Result:
             D = Phi(X.T @ R)
             Lam = Lam_psi + D
             gL = R - X @ D
+        elif opt.mult == "dual":
+            # PLAM-DA / PCAL-DA (Section 5.3): Step 3 replaced by the dual
+            # ascent of the augmented Lagrangian method, eq. (Lambda-alm),
+            # Lambda^k = Lambda^{k-1} - beta (X^k^T X^k - I), started from the
+            # closed form Psi(G^T X) at X^0
+            Lam = Lam_psi if k == 0 else Lam_da - opt.beta * C
+            Lam_da = Lam
+            gL = G - X @ Lam + opt.beta * (X @ C)
         else:
             Lam = Lam_psi
             gL = R
@@ -260,3 +272,98 @@ def merit(op, X: np.ndarray, beta: float) -> float:
     G = op.grad(X)
     C = X.T @ X - np.eye(p)
     return op.f(X) - 0.5 * float(np.sum(Psi(G.T @ X) * C)) + 0.25 * beta * float(np.sum(C * C))
+
+
+def moptqr(op, X0: np.ndarray, opt: Options) -> Result:
+    """The retraction-based comparator MOptQR with the Cholesky-QR retraction
+    (Table 1; Section 5.5 computes its QR with a Cholesky factorization):
+
+        D = grad f(X) - X grad f(X)^T X,   V = X - D / eta,
+        V^T V = R^T R (R upper),            X <- V R^{-1}.
+
+    eta (the reciprocal step size) follows the rules of Section 5.1 with the
+    pair S = X^k - X^{k-1}, Y = D^k - D^{k-1} (``bb_index`` as for PLAM/PCAL);
+    the stop test is the one of Section 5.1.  ``opt.variant``, ``beta`` and
+    ``mult`` are not used.  X0 is expected orthonormal.
+    """
+    X = np.array(X0, dtype=np.float64, copy=True)
+    n, p = X.shape
+    hist: Dict[str, List[float]] = {"kkt_rel": [], "feas": [], "eta": [], "f": []}
+    iterates: Dict[int, np.ndarray] = {}
+    grads: Dict[int, np.ndarray] = {}
+    rec = set(int(k) for k in opt.record_iterates)
+    X_prev = X_prev2 = D_prev = D_prev2 = None
+    eta = float(opt.eta0)
+    kkt0 = None
+    status = STATUS_MAX_ITER
+    k = 0
+    while True:
+        if not np.all(np.isfinite(X)):
+            status = STATUS_DIVERGED
+            break
+        if k in rec:
+            iterates[k] = X.copy()
+        G = op.grad(X)
+        W = X.T @ G
+        kkt = float(np.linalg.norm(G - X @ Psi(W)))
+        if kkt0 is None:
+            kkt0 = kkt
+        feas = feasibility(X)
+        if opt.record_history:
+            hist["kkt_rel"].append(kkt / kkt0 if kkt0 > 0 else 0.0)
+            hist["feas"].append(feas)
+            hist["f"].append(op.f(X))
+        if not np.isfinite(kkt):
+            status = STATUS_DIVERGED
+            break
+        if kkt0 == 0.0 or kkt / kkt0 <= opt.tol:
+            status = STATUS_CONVERGED
+            break
+        if k >= opt.max_iter:
+            status = STATUS_MAX_ITER
+            break
+        D = G - X @ W.T                      # grad f - X grad f^T X
+        if opt.eta_rule == "const":
+            eta_k = float(opt.eta_const)
+        elif k == 0:
+            eta_k = float(opt.eta0)
+        else:
+            if opt.bb_index == "standard" or opt.eta_rule == "diff":
+                Sd, Yd = X - X_prev, D - D_prev
+            elif k == 1:
+                Sd = None
+            else:
+                Sd, Yd = X_prev - X_prev2, D_prev - D_prev2
+            if Sd is None:
+                eta_k = float(opt.eta0)
+            else:
+                q = _bb_quotient(opt.eta_rule, k, float(np.sum(Sd * Sd)),
+                                 float(np.sum(Sd * Yd)), float(np.sum(Yd * Yd)))
+                eta_k = q if (np.isfinite(q) and q > 0.0) else eta
+        eta = eta_k
+        if opt.record_history:
+            hist["eta"].append(eta)
+        if k in rec:
+            grads[k] = D.copy()
+        V = X - D / eta
+        try:
+            R = np.linalg.cholesky(V.T @ V).T
+        except np.linalg.LinAlgError:
+            status = STATUS_DIVERGED
+            break
+        Xn = sla.solve_triangular(R, V.T, trans="T", lower=False).T
+        X_prev2, X_prev = X_prev, X
+        D_prev2, D_prev = D_prev, D
+        X = Xn
+        k += 1
+    if status == STATUS_DIVERGED:
+        return Result(status=status, iters=k, X=X, Q=None, kkt0=kkt0 or np.nan,
+                      kkt_abs=np.nan, kkt_rel=np.nan, feas=np.nan, f=np.nan,
+                      eta_last=eta, history=hist, iterates=iterates, grads=grads)
+    Q = cholqr2(X) if opt.orth_final else X
+    Gq = op.grad(Q)
+    kkt_q = float(np.linalg.norm(Gq - Q @ Psi(Gq.T @ Q)))
+    return Result(status=status, iters=k, X=X, Q=Q if opt.orth_final else None, kkt0=kkt0,
+                  kkt_abs=kkt_q, kkt_rel=kkt_q / kkt0, feas=feasibility(Q), f=op.f(Q),
+                  eta_last=eta, Lam=Psi(Gq.T @ Q), history=hist, iterates=iterates,
+                  grads=grads)

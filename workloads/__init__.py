@@ -54,6 +54,10 @@ class Problem:
     A: Optional[np.ndarray] = None          # dense operator (row-major n x n)
     s_bound: float = 0.0                    # upper bound of ||Hess f(0)||_2 (Section 5.1)
     meta: dict = field(default_factory=dict)
+    block: int = 0                          # stencil1d: order of the tridiagonal blocks (0: one)
+    gamma: float = 0.0                      # exchange weight of Problem 6
+    Glin: Optional[np.ndarray] = None       # linear term of Problem 2, float64 n x p
+    B: Optional[np.ndarray] = None          # right factor of Problem 4, float64 p x p
 
     def __post_init__(self):
         if self.kind == KIND_STENCIL1D and self.grid[0] == 0:
@@ -169,6 +173,82 @@ def batched_ks1d(nprob: int = 256, config: int = 4, n_range=(1000, 20000),
     return probs, x0s
 
 
+def ks1d_block(n: int = 10000, p: int = 1000, block: int = 5, alpha: float = 1.0,
+               config: int = 6):
+    """Problem 1 as in the parallel experiments of Section 5.5: L block-diagonal
+    with tridiag(-1,2,-1) blocks of order 5, alpha = 1."""
+    rng = rng_for(config)
+    x0 = orthonormal_start(rng, n, p)
+    prob = Problem(name=f"ks1d_block{block}_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p,
+                   alpha=float(alpha), v=None, grid=(n, 1, 1), s_bound=4.0, block=int(block))
+    return prob, x0
+
+
+def ocqp_tridiag(n: int = 10000, p: int = 1000, config: int = 7):
+    """Problem 2 as in Section 5.5: A = tridiag(-1, 2, -1), G = Random(n, p)
+    (uniform on [-1, 1]), f = 1/2 tr(X^T A X) + tr(G^T X)."""
+    rng = rng_for(config)
+    g = rng.uniform(-1.0, 1.0, (n, p))
+    x0 = orthonormal_start(rng, n, p)
+    prob = Problem(name=f"ocqp_tridiag_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p, alpha=0.0,
+                   v=None, grid=(n, 1, 1), s_bound=4.0, Glin=np.ascontiguousarray(g))
+    return prob, x0
+
+
+EXCHANGE_GAMMA = 2.0 * (3.0 / np.pi) ** (1.0 / 3.0)   # gamma of Problem 6
+
+
+def ks_exchange(n: int = 10000, p: int = 1000, block: int = 5, config: int = 8):
+    """Problem 6 as in Section 5.5: 1/2 tr(X^T L X) + 1/2 rho^T L^{-1} rho
+    - 3/4 gamma rho^T rho^{1/3}, L as in ``ks1d_block`` (alpha = 2 in the
+    alpha/4 convention of the other problems), gamma = 2 (3/pi)^{1/3}."""
+    rng = rng_for(config)
+    x0 = orthonormal_start(rng, n, p)
+    prob = Problem(name=f"ks_exchange_block{block}_n{n}_p{p}", kind=KIND_STENCIL1D, n=n, p=p,
+                   alpha=2.0, v=None, grid=(n, 1, 1), s_bound=4.0, block=int(block),
+                   gamma=EXCHANGE_GAMMA)
+    return prob, x0
+
+
+def ocqp_dense(n: int = 1000, p: int = 20, config: int = 9, kappa: float = 1.0,
+               theta: float = 1.01, zeta: float = 1.01, xi: float = 1.0):
+    """Problem 2 of Section 5.2 with its generator: A = P Lambda P^T, P the Q
+    factor of a U(0,1) n x n matrix, Lambda_ii = +-theta^{1-i} (+ with
+    probability xi); G = kappa Q D, Q the columns of a U(0,1) n x p matrix
+    scaled to unit norm, D_jj = zeta^{j-1}."""
+    rng = rng_for(config)
+    P, _ = np.linalg.qr(rng.uniform(0.0, 1.0, (n, n)))
+    lam = theta ** (-np.arange(n, dtype=np.float64))
+    lam = np.where(rng.uniform(0.0, 1.0, n) < xi, lam, -lam)
+    A = (P * lam[None, :]) @ P.T
+    A = 0.5 * (A + A.T)
+    qt = rng.uniform(0.0, 1.0, (n, p))
+    Q = qt / np.linalg.norm(qt, axis=0)[None, :]
+    G = kappa * Q * (zeta ** np.arange(p, dtype=np.float64))[None, :]
+    x0 = orthonormal_start(rng, n, p)
+    prob = Problem(name=f"ocqp_dense_n{n}_p{p}", kind=KIND_DENSE, n=n, p=p, alpha=0.0,
+                   A=np.ascontiguousarray(A), grid=(n, 1, 1),
+                   s_bound=float(np.max(np.abs(lam))), Glin=np.ascontiguousarray(G))
+    return prob, x0
+
+
+def qap_dense(n: int = 1000, p: int = 20, config: int = 10):
+    """Problem 4 of Section 5.2: f = 1/2 tr(A^T X B X^T), A = sym(randn(n)),
+    B = sym(randn(p)); s = ||A||_2 ||B||_2."""
+    rng = rng_for(config)
+    a = rng.standard_normal((n, n))
+    A = 0.5 * (a + a.T)
+    b = rng.standard_normal((p, p))
+    B = 0.5 * (b + b.T)
+    x0 = orthonormal_start(rng, n, p)
+    sa = float(np.max(np.abs(np.linalg.eigvalsh(A))))
+    sb = float(np.max(np.abs(np.linalg.eigvalsh(B))))
+    prob = Problem(name=f"qap_dense_n{n}_p{p}", kind=KIND_DENSE, n=n, p=p, alpha=0.0,
+                   A=np.ascontiguousarray(A), grid=(n, 1, 1), s_bound=sa * sb,
+                   B=np.ascontiguousarray(B))
+    return prob, x0
+
+
 def alternate_start(config: int, n: int, p: int, start: int) -> np.ndarray:
     """Another seeded X0 for the same operator (start >= 1; start 0 is the
     workload's own X0): the iteration count of the Barzilai-Borwein method
@@ -195,4 +275,11 @@ FULL_SIZES = {
     3: dict(kind="dense", n=32768, p=512),
     4: dict(kind="batched_ks1d", nprob=256),
     5: dict(kind="ks3d", grid=(64, 64, 64), p=256),
+}
+
+# The shapes of the parallel experiments of Section 5.5 (Figs. 7-11).
+PARALLEL_SIZES = {
+    "P1": dict(kind="ks1d_block", n=10000, ps=(500, 1000, 1500, 2000, 2500)),
+    "P2": dict(kind="ocqp_tridiag", n=10000, ps=(500, 1000, 1500, 2000, 2500)),
+    "P6": dict(kind="ks_exchange", n=10000, ps=(1000,)),
 }
