@@ -363,6 +363,142 @@ def batched_main(args, torch, S, W):
     print(json.dumps(line), flush=True)
 
 
+def _timed_and_profiled(dp, x0, opts, steps, warmup, S, torch):
+    """ms per iteration over exactly `steps` iterations (device events) and the
+    per-group averages of a second, profiled pass."""
+    stream = torch.cuda.Stream()
+    ws = S.alloc_workspace(dp, opts)
+    X = torch.empty((dp.n, dp.p), dtype=torch.float64, device="cuda")
+    x0d = torch.as_tensor(x0, device="cuda")
+    base = {k: getattr(opts, k) for k in opts.__dataclass_fields__}
+    with torch.cuda.stream(stream):
+        X.copy_(x0d)
+        torch.cuda.synchronize()
+        S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0, "max_iter": max(1, warmup),
+                                        "orth_final": False, "check_every": max(1, warmup),
+                                        "use_graph": False}), workspace=ws, stream=stream)
+        X.copy_(x0d)
+        torch.cuda.synchronize()
+        r, _, _ = S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0, "max_iter": steps,
+                                                   "orth_final": False, "check_every": steps,
+                                                   "use_graph": False}),
+                          workspace=ws, stream=stream)
+        X.copy_(x0d)
+        torch.cuda.synchronize()
+        pr, _, _ = S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0, "max_iter": steps,
+                                                    "orth_final": False, "check_every": steps,
+                                                    "use_graph": False, "profile": True}),
+                           workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        # to the tolerance, graph-replayed
+        X.copy_(x0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            c, _, _ = S.solve(dp, X, opts, workspace=ws, stream=stream)
+        except S.StiefelError as e:
+            c = {"rc": e.code, "iters": None, "kkt_rel": None, "fval": None, "feas": None,
+                 "ms_loop": None, "ms_orth": None}
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    n_it = max(1, pr["prof_iters"])
+    km = {k: v / n_it for k, v in pr["kernel_ms"].items()}
+    return {"ms_per_iter": r["ms_loop"] / steps,
+            "func_ms": km["hartree"] + km["grad"],
+            "blas3_ms": km["gram"] + km["stage1"] + km["residual"] + km["stage2"],
+            "orth_ms": km["update"],
+            "kernel_avg_ms": km,
+            "to_tol": {"rc": c["rc"], "iters": c["iters"], "kkt_rel": c["kkt_rel"],
+                       "f": c["fval"], "feas": c["feas"], "ms_loop": c["ms_loop"],
+                       "ms_orth": c["ms_orth"], "wall_s": wall}}
+
+
+def parallel_main(args, torch, S, W):
+    """The workloads of the parallel experiments of Section 5.5 (Figs. 7-11):
+    Problem 1 with the block-diagonal 5 x 5 operator, Problem 2 with the
+    tridiagonal A and a uniform random G, Problem 6 (exchange term), n = 10000,
+    PCAL (beta = 1) against MOptQR with the Cholesky-QR retraction, both float64
+    with ABB steps, max 1000 iterations, tol 1e-8.  Per iteration the time is
+    split as in the paper: Func (Hartree + gradient), BLAS3 (Grams, p x p
+    stages, the row-block product) and Orth (the PCAL update, or MOptQR's
+    retraction: V, V^T V, Cholesky, inverse, V R^{-1})."""
+    ps = [int(v) for v in args.parallel_p.split(",")]
+    n = 10000
+    rows = []
+    for name, gen in [("P1", W.ks1d_block), ("P2", W.ocqp_tridiag), ("P6", W.ks_exchange)]:
+        for p in ps:
+            if name == "P6" and p != 1000 and not args.parallel_all:
+                continue
+            prob, x0 = gen(n=n, p=p)
+            dp = S.DeviceProblem.from_host(prob)
+            for solver in ["pcal", "moptqr"]:
+                beta = 1.0 if solver == "pcal" else 0.0
+                opts = S.SolveOptions(variant=solver, mult="psi_phi" if solver == "pcal" else "psi",
+                                      eta_rule="abb", precision="fp64", beta=beta,
+                                      eta0=beta + prob.s_bound, tol=1e-8, max_iter=1000,
+                                      orth_final=True, check_every=50, use_graph=True)
+                log(f"parallel {name} n={n} p={p} {solver}")
+                r = _timed_and_profiled(dp, x0, opts, args.steps, args.warmup, S, torch)
+                r.update({"problem": name, "n": n, "p": p, "solver": solver})
+                log(json.dumps(r))
+                rows.append(r)
+            del dp
+            torch.cuda.empty_cache()
+    print(json.dumps({"metric": "Section 5.5 workloads: PCAL vs MOptQR, float64, one GPU",
+                      "unit": "ms/iteration", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic", "rows": rows}), flush=True)
+
+
+def sweep_main(args, torch, S, W):
+    """The parameter studies of Section 5.3 on GPU (Problems 1-4 at n = 1000,
+    p = 20; Problem 1 with the 3D Kohn-Sham operator on a 10^3 grid): step-size rules
+    (Fig. 1) at beta = s + 0.1, beta in {0, 0.01s, 0.1s, s + 0.1, 10s + 1}
+    with ABB steps (Figs. 2-3), and the closed-form multipliers against dual
+    ascent (PLAM-DA / PCAL-DA, Fig. 4).  Iterations and time to relative KKT
+    1e-8 (max 3000), float64."""
+    probs = {"P1": W.ks3d(grid=(10, 10, 10), p=20)[:2],
+             "P2": W.ocqp_dense(n=1000, p=20),
+             "P3": W.ocqp_dense(n=1000, p=20, kappa=0.0),
+             "P4": W.qap_dense(n=1000, p=20)}
+    stream = torch.cuda.Stream()
+    rows = []
+    for pname, (prob, x0) in probs.items():
+        if pname == "P3":
+            prob.Glin = None
+        dp = S.DeviceProblem.from_host(prob)
+        s = prob.s_bound
+        runs = []
+        for var in ["plam", "pcal"]:
+            for rule in ["const", "diff", "bb1", "bb2", "abb"]:
+                runs.append(("eta", var, "psi_phi" if var == "pcal" else "psi", rule, s + 0.1))
+            for bname, b in [("0", 0.0), ("0.01s", 0.01 * s), ("0.1s", 0.1 * s),
+                             ("s+0.1", s + 0.1), ("10s+1", 10 * s + 1)]:
+                runs.append(("beta=" + bname, var, "psi_phi" if var == "pcal" else "psi",
+                             "abb", b))
+            b = s + 0.1 if var == "plam" else 1.0
+            runs.append(("closed_form", var, "psi_phi" if var == "pcal" else "psi", "abb", b))
+            runs.append(("dual_ascent", var, "dual", "abb", b))
+        for study, var, mult, rule, beta in runs:
+            eta0 = beta + s
+            o = S.SolveOptions(variant=var, mult=mult, eta_rule=rule, precision="fp64",
+                               beta=beta, eta0=eta0, eta_const=eta0, tol=1e-8, max_iter=3000,
+                               orth_final=True, check_every=100, use_graph=True)
+            X = torch.as_tensor(x0, device="cuda").contiguous()
+            with torch.cuda.stream(stream):
+                try:
+                    r, _, _ = S.solve(dp, X, o, stream=stream, raise_on_error=False)
+                except S.StiefelError as e:
+                    r = {"rc": e.code, "iters": None, "kkt_rel": None, "fval": None,
+                         "ms_loop": None, "ms_orth": None}
+            torch.cuda.synchronize()
+            rows.append({"problem": pname, "study": study, "variant": var, "mult": mult,
+                         "eta_rule": rule, "beta": beta, "rc": r["rc"], "iters": r["iters"],
+                         "kkt_rel": r["kkt_rel"], "f": r["fval"], "ms": r["ms_loop"]})
+            log(json.dumps(rows[-1]))
+    print(json.dumps({"metric": "Section 5.3 parameter studies on GPU (iterations to 1e-8)",
+                      "n_gpus": 1, "data": "synthetic", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +512,14 @@ def main():
                     help="skip the time-to-KKT solves (short runs under hardware counters)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched solver on the 256-problem 1D workload instead")
+    ap.add_argument("--parallel", action="store_true",
+                    help="measure the Section 5.5 workloads (PCAL vs MOptQR, n = 10000)")
+    ap.add_argument("--parallel-p", default="1000",
+                    help="comma-separated p of --parallel (the paper: 500,1000,1500,2000,2500)")
+    ap.add_argument("--parallel-all", action="store_true",
+                    help="run Problem 6 at every p too (the paper: p = 1000 only)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the Section 5.3 step-size / beta / dual-ascent studies")
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times: the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -402,6 +546,12 @@ def main():
         del a, b
     if args.batched:
         batched_main(args, torch, S, W)
+        return
+    if args.parallel:
+        parallel_main(args, torch, S, W)
+        return
+    if args.sweep:
+        sweep_main(args, torch, S, W)
         return
     log("generating the 64^3 p=256 workload (seeded)")
     prob, x0, _ = W.ks3d(grid=GRID, p=P, alpha=ALPHA)

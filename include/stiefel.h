@@ -52,12 +52,20 @@ extern "C" {
 #define STF_F64 0
 #define STF_F32 1
 
-#define STF_PLAM 0
-#define STF_PCAL 1
+/* algorithm: PLAM (Algorithm 2), PCAL (Algorithm 3), or the retraction-based
+ * comparator MOptQR of Table 1 with the Cholesky-QR retraction of Section 5.5
+ * (float64 only; mult_rule and beta are not used) */
+#define STF_PLAM   0
+#define STF_PCAL   1
+#define STF_MOPTQR 2
 
-/* multiplier: eq. (Lambda1) Psi(G^T X); eq. (lambda2) adds the Phi term (PCAL) */
+/* multiplier: eq. (Lambda1) Psi(G^T X); eq. (lambda2) adds the Phi term (PCAL);
+ * DUAL is the dual ascent of the augmented Lagrangian method, eq. (Lambda-alm),
+ * Lam^k = Lam^{k-1} - beta (X^k^T X^k - I) from Lam^0 = Psi(G^0^T X^0): Step 3
+ * of Algorithms 2 / 3 replaced as in PLAM-DA / PCAL-DA of Section 5.3 */
 #define STF_MULT_PSI     0
 #define STF_MULT_PSI_PHI 1
+#define STF_MULT_DUAL    2
 
 /* proximal parameter eta (Section 5.1): constant, differential, BB1, BB2,
  * alternating BB (BB1 at odd k, BB2 at even k) */
@@ -102,13 +110,31 @@ extern "C" {
 #define STF_E_CHOLESKY      -6   /* CholeskyQR2 met a non-positive pivot (rank-deficient X) */
 
 /* ---- problem descriptor ---------------------------------------------------
+ * The objective is
+ *   f(X) = 1/2 tr(X^T H0 X B) + tr(Glin^T X) + alpha/4 rho^T L^{-1} rho
+ *          - 3/4 gamma rho^T rho^{1/3},        rho = diag(X X^T),
+ * with H0 = L + Diag v (stencil kinds) or A (dense kind), B = I when NULL:
+ * Problems 1 and 3 of Section 5.2 (Glin, B NULL, gamma 0), Problem 2 (Glin),
+ * Problem 4 (B) and Problem 6 (gamma, the exchange term).
  * kind   : STF_KIND_*
- * n, p   : sizes, 1 <= p, 2p <= n (Section 1); p <= 1024
+ * n, p   : sizes, 1 <= p, 2p <= n (Section 1); p <= 4096
  * grid   : (nx, ny, nz); STENCIL1D requires (n, 1, 1); STENCIL3D nx*ny*nz == n
  * alpha  : weight of the Hartree-like term alpha/4 rho^T L^{-1} rho (stencil kinds)
  * v      : device, float64, length n: diagonal potential added to L; may be NULL
  * A      : device, dense symmetric n x n (STF_KIND_DENSE), dtype A_dtype
- *          (STF_F64 or STF_F32); its symmetry is assumed, not checked.       */
+ *          (STF_F64 or STF_F32); its symmetry is assumed, not checked.
+ * block  : STENCIL1D only: L = Diag(L_1, ..., L_s) with tridiag(-1,2,-1)
+ *          blocks of this order (the last one shorter when it does not divide
+ *          n), the operator of the parallel experiments of Section 5.5;
+ *          0 = one block (the whole tridiagonal matrix)
+ * gamma  : exchange weight of Problem 6 (stencil kinds); 0 = no exchange term.
+ *          Its gradient -2 gamma Diag(rho^{1/3}) X enters the row diagonal.
+ * Glin   : device, float64, n x p row-major, or NULL: the linear term of
+ *          Problem 2 (gradient Glin)
+ * B      : device, float64, p x p symmetric, or NULL: the right factor of
+ *          Problem 4 (gradient H0 X B); only with alpha = gamma = 0.
+ * With Glin or B the product X^T grad f(X) is not symmetric: the iteration
+ * then forms the whole of X^T G instead of its upper blocks.                */
 typedef struct stf_problem {
     int32_t kind;
     int32_t p;
@@ -118,6 +144,11 @@ typedef struct stf_problem {
     double alpha;
     const double* v;
     const void* A;
+    int32_t block;
+    int32_t reserved;
+    double gamma;
+    const double* Glin;
+    const double* B;
 } stf_problem;
 
 /* ---- options --------------------------------------------------------------

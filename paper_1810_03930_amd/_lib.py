@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(HERE, "libstiefel.so")
 # enums (mirrors of the #defines in stiefel.h)
 KIND_STENCIL1D, KIND_STENCIL3D, KIND_DENSE = 0, 1, 2
 F64, F32 = 0, 1
-PLAM, PCAL = 0, 1
-MULT_PSI, MULT_PSI_PHI = 0, 1
+PLAM, PCAL, MOPTQR = 0, 1, 2
+MULT_PSI, MULT_PSI_PHI, MULT_DUAL = 0, 1, 2
 ETA_CONST, ETA_DIFF, ETA_BB1, ETA_BB2, ETA_ABB = 0, 1, 2, 3, 4
 BB_STANDARD, BB_LAGGED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
@@ -33,6 +33,11 @@ class StfProblem(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("v", ctypes.c_void_p),
         ("A", ctypes.c_void_p),
+        ("block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("Glin", ctypes.c_void_p),
+        ("B", ctypes.c_void_p),
     ]
 
 

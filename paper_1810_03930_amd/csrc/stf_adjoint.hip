@@ -217,7 +217,11 @@ static void hess_apply(const AdjCtx& c, const double* d, double* Hd, hipStream_t
     const stf_problem* prob = c.prob;
     const int64_t n = prob->n;
     const int p = prob->p;
-    launch_grad(prob, STF_F64, d, Hd, c.at<double>(c.L.phi), nullptr, s);
+    // H0 d + alpha Diag(phi) d (the operator's block structure, no other terms)
+    GradExtra ex;
+    memset(&ex, 0, sizeof(ex));
+    ex.block = grad_extra(prob, nullptr).block;
+    launch_grad(prob, STF_F64, d, Hd, c.at<double>(c.L.phi), ex, nullptr, s);
     if (prob->kind != STF_KIND_DENSE && prob->alpha != 0.0) {
         k_rowdot<<<grid_rows_a(n), 256, 0, s>>>(c.X, d, n, p, 2.0, c.at<double>(c.L.drho));
         launch_hartree(prob, c.at<double>(c.L.drho), c.at<double>(c.L.dphi),
@@ -253,6 +257,10 @@ static int adjoint_impl(const stf_problem* prob, const double* X, const double* 
     if (!prob || !X || !Lam || !gradX || !gradV || !ws) return STF_E_INVALID;
     if (prob->p <= 0 || prob->p > 1024 || prob->n < 2 * (int64_t)prob->p) return STF_E_INVALID;
     if (prob->kind == STF_KIND_DENSE && prob->A_dtype != STF_F64) return STF_E_UNSUPPORTED;
+    if (check_problem(prob) != STF_OK) return STF_E_INVALID;
+    // the Hessian products cover Problem 1 / 3 objectives (no linear, exchange or
+    // right-factor terms)
+    if (prob->Glin || prob->B || prob->gamma != 0.0) return STF_E_UNSUPPORTED;
     if (!(cg_tol > 0.0) || cg_maxit < 1) return STF_E_INVALID;
     AdjCtx c;
     c.prob = prob;

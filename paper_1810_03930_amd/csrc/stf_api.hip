@@ -70,7 +70,7 @@ ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(const stf_problem* prob, int precision) {
+Layout make_layout(const stf_problem* prob, int precision, bool moptqr) {
     Layout L;
     memset(&L, 0, sizeof(L));
     const int64_t n = prob->n;
@@ -133,7 +133,7 @@ Layout make_layout(const stf_problem* prob, int precision) {
                                      (size_t)L.resmx.nrb * L.resmx.ncb});
     L.res_col = take(nrb_max * p * 2 * 8);
     L.res_scal = take(nwg_max * 4 * 8);
-    L.dots = take(512 * 2 * 8);
+    L.dots = take(512 * 4 * 8);
     if (prob->kind == STF_KIND_STENCIL3D) {
         const size_t nx = prob->grid[0], ny = prob->grid[1], nz = prob->grid[2];
         L.dst = take((nx * nx + ny * ny + nz * nz + nx + ny + nz) * 8);
@@ -144,6 +144,15 @@ Layout make_layout(const stf_problem* prob, int precision) {
         const size_t prow = (size_t)L.res64.ncb * 64, pk = (size_t)(p + 31) / 32 * 32;
         L.mix = take(2 * 3 * prow * pk * 2);
     }
+    L.lam2 = take(2 * pp);
+    L.cwork = take(pp);
+    L.gtmp = prob->B ? take(np * 8) : (size_t)-1;  // room for either dtype
+    if (moptqr) {
+        L.xalt = take(np * 8);
+        L.vbuf = take(np * 8);
+    } else {
+        L.xalt = L.vbuf = (size_t)-1;
+    }
     L.total = off;
     return L;
 }
@@ -152,7 +161,7 @@ Layout make_layout(const stf_problem* prob, int precision) {
 
 int check_problem(const stf_problem* prob) {
     if (!prob) return STF_E_INVALID;
-    if (prob->p <= 0 || prob->p > 1024) return STF_E_INVALID;
+    if (prob->p <= 0 || prob->p > 4096) return STF_E_INVALID;
     if (prob->n < 2 * (int64_t)prob->p) return STF_E_INVALID;
     if (prob->kind == STF_KIND_STENCIL1D) {
         if (prob->grid[0] != prob->n || prob->grid[1] != 1 || prob->grid[2] != 1)
@@ -168,12 +177,33 @@ int check_problem(const stf_problem* prob) {
     } else {
         return STF_E_INVALID;
     }
-    if (!isfinite(prob->alpha)) return STF_E_INVALID;
+    if (!isfinite(prob->alpha) || !isfinite(prob->gamma)) return STF_E_INVALID;
+    if (prob->block < 0) return STF_E_INVALID;
+    if (prob->block > 0 && prob->kind != STF_KIND_STENCIL1D) return STF_E_INVALID;
+    if (prob->gamma != 0.0 && prob->kind == STF_KIND_DENSE) return STF_E_INVALID;
+    // the right factor of Problem 4 only for quadratic objectives
+    if (prob->B && (prob->alpha != 0.0 || prob->gamma != 0.0)) return STF_E_UNSUPPORTED;
     return STF_OK;
 }
 
 bool has_hartree(const stf_problem* prob) {
     return prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
+}
+
+bool needs_rho(const stf_problem* prob) {
+    return prob->kind != STF_KIND_DENSE && (prob->alpha != 0.0 || prob->gamma != 0.0);
+}
+
+bool w_symmetric(const stf_problem* prob) { return !prob->Glin && !prob->B; }
+
+GradExtra grad_extra(const stf_problem* prob, const double* rho) {
+    GradExtra e;
+    memset(&e, 0, sizeof(e));
+    e.glin = prob->Glin;
+    e.rho = rho;
+    e.gamma = (prob->kind != STF_KIND_DENSE) ? prob->gamma : 0.0;
+    e.block = (prob->kind == STF_KIND_STENCIL1D && prob->block < prob->n) ? prob->block : 0;
+    return e;
 }
 
 #define HIPCHK(x)                                  \
@@ -183,15 +213,30 @@ bool has_hartree(const stf_problem* prob) {
 
 int last_launch() { return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP; }
 
+// G = grad f(X) given rho / phi of X in the workspace; with the right factor B
+// of Problem 4, H0 X goes to the workspace's gtmp and G = gtmp B.  Xm: the
+// float64 master copy the float32 forms evaluate the stencil on.
+static void enqueue_grad_core(const stf_problem* prob, const Ws& w, int dtype, const void* X,
+                              void* G, const DevState* st, hipStream_t s,
+                              const double* Xm = nullptr) {
+    const GradExtra ex = grad_extra(prob, needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr);
+    if (prob->B) {
+        void* T = w.base + w.L.gtmp;
+        launch_grad(prob, dtype, X, T, w.at<double>(w.L.phi), ex, st, s, Xm);
+        launch_apply(dtype, w.L.res, T, G, prob->B, prob->n, prob->p, s, 0, st);
+    } else {
+        launch_grad(prob, dtype, X, G, w.at<double>(w.L.phi), ex, st, s, Xm);
+    }
+}
+
 // G = grad f(X) using the workspace's rho / phi (no device state).
 static int enqueue_gradient(const stf_problem* prob, const Ws& w, int dtype, const void* X,
                             void* G, const DevState* st, hipStream_t s) {
-    if (has_hartree(prob)) {
-        launch_rowsq(dtype, X, prob->n, prob->p, w.at<double>(w.L.rho), st, s);
+    if (needs_rho(prob)) launch_rowsq(dtype, X, prob->n, prob->p, w.at<double>(w.L.rho), st, s);
+    if (has_hartree(prob))
         launch_hartree(prob, w.at<double>(w.L.rho), w.at<double>(w.L.phi),
                        w.at<double>(w.L.hscr), w.at<double>(w.L.dst), st, s);
-    }
-    launch_grad(prob, dtype, X, G, w.at<double>(w.L.phi), st, s);
+    enqueue_grad_core(prob, w, dtype, X, G, st, s);
     return last_launch();
 }
 
@@ -205,8 +250,8 @@ int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp
     for (int pass = 0; pass < 2; ++pass) {
         launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, a, a, n, p, w.at<double>(w.L.gram_part),
                     w.at<double>(w.L.S), nullptr, nullptr, s);
-        launch_chol_inv(w.at<double>(w.L.S), w.at<double>(w.L.Rm), w.at<double>(w.L.Rinv), p, st,
-                        s);
+        launch_chol_inv(w.at<double>(w.L.S), w.at<double>(w.L.Rm), w.at<double>(w.L.Rinv),
+                        w.at<double>(w.L.cwork), p, st, s);
         launch_apply(STF_F64, w.L.res, a, b, w.at<double>(w.L.Rinv), n, p, s);
         std::swap(a, b);
     }
@@ -255,6 +300,8 @@ struct IterCtx {
     size_t g[2]; // G / gradL double buffer (workspace offsets)
     DevState* st;
     DevParams* prm;
+    bool moptqr;
+    double* xb[2];  // MOptQR: X^k lives in xb[k & 1] (the caller's X and the workspace's xalt)
 };
 
 // ev (optional): STF_NPROF + 1 events bracketing the kernel groups.
@@ -269,35 +316,53 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     const int p = prob->p;
     void* Gc = w.base + c.g[parity];
     void* Gp = w.base + c.g[parity ^ 1];
-    double* rho = has_hartree(prob) ? w.at<double>(w.L.rho) : nullptr;
+    double* rho = needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr;
+    // MOptQR iterates between two buffers; the others update X in place
+    void* X = c.moptqr ? (void*)c.xb[parity] : c.X;
     mark(0);
     if (has_hartree(prob))
         launch_hartree(prob, rho, w.at<double>(w.L.phi), w.at<double>(w.L.hscr),
                        w.at<double>(w.L.dst), c.st, s);
     mark(1);
-    launch_grad(prob, c.dtype, c.X, Gc, w.at<double>(w.L.phi), c.st, s,
-                prob->kind == STF_KIND_DENSE ? nullptr : c.Xm);
+    enqueue_grad_core(prob, w, c.dtype, X, Gc, c.st, s,
+                      prob->kind == STF_KIND_DENSE ? nullptr : c.Xm);
     mark(2);
     // groups 2..4: the Gram kernel | chunk reduction, p x p stage, KKT products,
     // split of M_L | the residual kernel (events 3 and 4 recorded by the launchers)
-    launch_gram(c.dtype, c.precision, w.L.gram, c.X, Gc, n, p, w.at<double>(w.L.gram_part),
+    launch_gram(c.dtype, c.precision, w.L.gram, X, Gc, n, p, w.at<double>(w.L.gram_part),
                 w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s, ev ? ev[3] : nullptr,
-                /*w_sym=*/true);
+                /*w_sym=*/w_symmetric(prob));
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
-                  w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s);
+                  w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s,
+                  w.at<double>(w.L.lam2));
     launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
                         w.at<double>(w.L.W), w.at<double>(w.L.T1), p, c.st, s);
     const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.mixed_plan() : w.L.res;
-    launch_residual(c.dtype, c.precision, rp, c.X, Gc, Gp, w.at<double>(w.L.ML),
+    launch_residual(c.dtype, c.precision, rp, X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
                     w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
-                    RES_ITERATE, w.base + w.L.mix, s, ev ? ev[4] : nullptr);
+                    RES_ITERATE, w.base + w.L.mix, s, ev ? ev[4] : nullptr,
+                    c.moptqr ? c.xb[parity ^ 1] : nullptr);
     mark(5);
     launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
                   w.at<double>(w.L.S), w.at<double>(w.L.T1), w.at<double>(w.L.fpart),
                   w.at<double>(w.L.colpart), w.at<double>(w.L.nu), p, c.st, s);
     mark(6);
-    launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s, c.Xm);
+    if (c.moptqr) {
+        // the Cholesky-QR retraction (Table 1, Section 5.5): V = X - D / eta,
+        // V^T V = R^T R, X^{k+1} = V R^{-1} into the buffer of X^{k-1}
+        double* V = w.at<double>(w.L.vbuf);
+        double* Xn = c.xb[parity ^ 1];
+        launch_vform((const double*)X, (const double*)Gc, V, n, p, c.st, s);
+        launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, V, V, n, p, w.at<double>(w.L.gram_part),
+                    w.at<double>(w.L.Rm), nullptr, c.st, s);
+        launch_chol_inv(w.at<double>(w.L.Rm), w.at<double>(w.L.Lam), w.at<double>(w.L.Rinv),
+                        w.at<double>(w.L.cwork), p, c.st, s, /*stop_on_fail=*/1);
+        launch_apply(STF_F64, w.L.res, V, Xn, w.at<double>(w.L.Rinv), n, p, s, 0, c.st);
+        if (rho) launch_rowsq(STF_F64, Xn, n, p, rho, c.st, s);
+    } else {
+        launch_update(c.dtype, c.X, Gc, n, p, w.at<double>(w.L.nu), rho, c.st, s, c.Xm);
+    }
     mark(7);
 }
 
@@ -307,10 +372,18 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     int rc = check_problem(prob);
     if (rc) return rc;
     if (!X || !opt || !ws || !res) return STF_E_INVALID;
-    if (opt->variant != STF_PLAM && opt->variant != STF_PCAL) return STF_E_INVALID;
-    if (opt->mult_rule != STF_MULT_PSI && opt->mult_rule != STF_MULT_PSI_PHI)
+    if (opt->variant != STF_PLAM && opt->variant != STF_PCAL && opt->variant != STF_MOPTQR)
         return STF_E_INVALID;
-    if (opt->mult_rule == STF_MULT_PSI_PHI && opt->variant != STF_PCAL) return STF_E_UNSUPPORTED;
+    const bool moptqr = opt->variant == STF_MOPTQR;
+    if (!moptqr) {
+        if (opt->mult_rule != STF_MULT_PSI && opt->mult_rule != STF_MULT_PSI_PHI &&
+            opt->mult_rule != STF_MULT_DUAL)
+            return STF_E_INVALID;
+        if (opt->mult_rule == STF_MULT_PSI_PHI && opt->variant != STF_PCAL)
+            return STF_E_UNSUPPORTED;
+    } else if (opt->precision != STF_PREC_FP64) {
+        return STF_E_UNSUPPORTED;  // the comparator runs in float64 only
+    }
     if (opt->eta_rule < STF_ETA_CONST || opt->eta_rule > STF_ETA_ABB) return STF_E_INVALID;
     if (opt->bb_index != STF_BB_STANDARD && opt->bb_index != STF_BB_LAGGED) return STF_E_INVALID;
     if (opt->precision < STF_PREC_FP64 || opt->precision > STF_PREC_MIXED) return STF_E_INVALID;
@@ -322,7 +395,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
 
     Ws w;
     w.base = (char*)ws;
-    w.L = make_layout(prob, opt->precision);
+    w.L = make_layout(prob, opt->precision, moptqr);
     if (ws_bytes < w.L.total) return STF_E_WORKSPACE;
     memset(res, 0, sizeof(*res));
     const int64_t n = prob->n;
@@ -339,6 +412,9 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     c.g[1] = w.L.g[1];
     c.st = w.at<DevState>(w.L.state);
     c.prm = w.at<DevParams>(w.L.params);
+    c.moptqr = moptqr;
+    c.xb[0] = (double*)X;
+    c.xb[1] = moptqr ? w.at<double>(w.L.xalt) : nullptr;
 
     DevParams hp;
     memset(&hp, 0, sizeof(hp));
@@ -348,7 +424,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     hp.tol = opt->tol;
     hp.feas_blowup = opt->feas_blowup > 0.0 ? opt->feas_blowup : INFINITY;
     hp.variant = opt->variant;
-    hp.mult_rule = opt->mult_rule;
+    hp.mult_rule = moptqr ? STF_MULT_PSI : opt->mult_rule;
     hp.eta_rule = opt->eta_rule;
     hp.bb_index = opt->bb_index;
     hp.max_iter = opt->max_iter;
@@ -362,7 +438,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);
     // the float32 forms iterate on a float64 master copy; X holds its rounding
     if (c.Xm) launch_convert(STF_F64, X, STF_F32, c.Xm, (size_t)n * p, s);
-    if (has_hartree(prob))
+    if (needs_rho(prob))
         launch_rowsq(c.Xm ? STF_F64 : dtype, c.Xm ? (const void*)c.Xm : X, n, p,
                      w.at<double>(w.L.rho), c.st, s);
     if ((rc = last_launch())) return rc;
@@ -492,6 +568,9 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         return STF_E_DIVERGED;
     }
 
+    // MOptQR: the returned iterate X^k sits in buffer k & 1
+    if (moptqr && (hs.final_iter & 1))
+        HIPCHK(hipMemcpyAsync(X, c.xb[1], (size_t)n * p * 8, hipMemcpyDeviceToDevice, s));
     // float64 copy of the returned iterate, CholeskyQR2, float64 evaluation
     double* Xd;
     double* tmp;
@@ -556,8 +635,8 @@ extern "C" {
 
 size_t stf_workspace_size(const stf_problem* prob, const stf_options* opt) {
     if (check_problem(prob) != STF_OK) return 0;
-    if (opt) return make_layout(prob, opt->precision).total;
-    const size_t a = make_layout(prob, STF_PREC_FP64).total;
+    if (opt) return make_layout(prob, opt->precision, opt->variant == STF_MOPTQR).total;
+    const size_t a = make_layout(prob, STF_PREC_FP64, true).total;
     const size_t b = make_layout(prob, STF_PREC_FP32).total;
     return a > b ? a : b;
 }

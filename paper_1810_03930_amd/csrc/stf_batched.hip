@@ -66,8 +66,10 @@ int batch_check(int32_t nprob, const stf_problem* probs, const stf_options* opts
     for (int b = 0; b < nprob; ++b) {
         const int rc = check_problem(&probs[b]);
         if (rc) return rc;
-        // the grouped Hartree and gradient passes are the 1D ones
+        // the grouped Hartree and gradient passes are the 1D ones of Problem 1
         if (probs[b].kind != STF_KIND_STENCIL1D) return STF_E_UNSUPPORTED;
+        if (probs[b].Glin || probs[b].B || probs[b].gamma != 0.0 || probs[b].block != 0)
+            return STF_E_UNSUPPORTED;
     }
     if (opts) {
         const int prec = opts[0].precision;

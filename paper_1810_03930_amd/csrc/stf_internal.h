@@ -44,6 +44,17 @@ struct DevParams {
     double* history;        // optional per-iteration record, (max_iter + 1) x 4
 };
 
+// Terms of the gradient beyond (L + Diag v + alpha Diag phi) X: the linear
+// term of Problem 2, the exchange term -2 gamma Diag(rho^{1/3}) X of Problem 6
+// and the block structure of the 1D operator of Section 5.5.
+struct GradExtra {
+    const double* glin;   // n x p float64, added to G, or null
+    const double* rho;    // the density rho = diag(X X^T) (read when gamma != 0)
+    double gamma;         // exchange weight
+    int32_t block;        // 1D: order of the tridiagonal blocks (0: one block)
+    int32_t pad;
+};
+
 // Internal status of a reduced-precision phase that reached switch_tol, and
 // (batched solves) of one whose float64 continuation has taken over.
 #define STF_SWITCH 16
@@ -94,6 +105,11 @@ struct Layout {
     size_t res_col, res_scal, dots;
     size_t dst;           // sine tables and 1D eigenvalues (3D Hartree solve)
     size_t mix;           // split-bf16 copies of M_L^T and Psi^T (MIXED precision)
+    size_t lam2;          // two p x p float64: the dual-ascent multiplier, by iteration parity
+    size_t cwork;         // p x p float64: the working matrix of the blocked Cholesky
+    size_t gtmp;          // n x p (iteration dtype): H0 X before the right factor B
+    size_t xalt;          // n x p float64 (MOptQR): the other iterate buffer
+    size_t vbuf;          // n x p float64 (MOptQR): V = X - D / eta before the retraction
     size_t total;
     GramPlan gram;        // plan for the iteration dtype
     GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)
@@ -151,7 +167,7 @@ int elem_size(int dtype);
 // target_wg: workgroups the plan aims at (the single-problem defaults when omitted)
 GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 512, bool wup = false);
 ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
-Layout make_layout(const stf_problem* prob, int precision);
+Layout make_layout(const stf_problem* prob, int precision, bool moptqr = false);
 size_t align256(size_t x);
 
 // A problem's workspace: base address and layout.
@@ -164,6 +180,11 @@ struct Ws {
 // Shared by the single-problem and batched drivers (stf_api.hip).
 int check_problem(const stf_problem* prob);
 bool has_hartree(const stf_problem* prob);
+// the density rho is needed by the gradient (Hartree or exchange term)
+bool needs_rho(const stf_problem* prob);
+// X^T grad f(X) is symmetric (no linear term, no right factor)
+bool w_symmetric(const stf_problem* prob);
+GradExtra grad_extra(const stf_problem* prob, const double* rho);
 int last_launch();
 // In-place CholeskyQR2 of a float64 X (tmp: n x p float64 scratch).
 int enqueue_cholqr2(const stf_problem* prob, const Ws& w, double* X, double* tmp,
@@ -175,22 +196,27 @@ int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* 
 // ---- launchers (stf_kernels.hip); all enqueue on `s` -----------------------
 void launch_rowsq(int dtype, const void* X, int64_t n, int p, double* rho,
                   const DevState* st, hipStream_t s);
+// stencil kinds: the right factor B of Problem 4 applied after the stencil
+// (tmp: n x p of dtype); G = tmp B.  Dense: the same with A X in tmp.
 void launch_hartree(const stf_problem* prob, const double* rho, double* phi,
                     double* scratch, double* dst_tables, const DevState* st,
                     hipStream_t s);
 void launch_dst_init(const stf_problem* prob, double* dst_tables, hipStream_t s);
-// Xm (float32 G only): the stencil reads this float64 copy of X instead of X
+// Xm (float32 G only): the stencil reads this float64 copy of X instead of X.
+// ex: the further gradient terms (grad_extra); with a right factor B the
+// caller applies it afterwards (launch_apply).
 void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
-                 const double* phi, const DevState* st, hipStream_t s,
+                 const double* phi, const GradExtra& ex, const DevState* st, hipStream_t s,
                  const double* Xm = nullptr);
 // S = X^T X (if S) and W = X^T G (if W), float64 p x p, full
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
                  double* W, const DevState* st, hipStream_t s,
                  hipEvent_t after_main = nullptr, bool w_sym = false);
+// lam2: two p x p buffers of the dual-ascent multiplier (STF_MULT_DUAL), else null
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
-                   DevState* st, hipStream_t s);
+                   DevState* st, hipStream_t s, double* lam2 = nullptr);
 // per-tile partials of <B, S B - 2 (W - S M_L)> into part[((p+15)/16)^2]
 void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
                          double* part, int p, DevState* st, hipStream_t s);
@@ -198,7 +224,8 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      void* G, const void* Gprev, const double* ML, const double* Psi,
                      const double* nu, int64_t n, int p, double* part_col,
                      double* part_scal, const DevParams* prm, DevState* st,
-                     int mode, void* mix, hipStream_t s, hipEvent_t before_main = nullptr);
+                     int mode, void* mix, hipStream_t s, hipEvent_t before_main = nullptr,
+                     const void* Xprev = nullptr);
 // pp_part: the ((p+15)/16)^2 tile partials of the KKT identity's p x p term
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* pp_part,
@@ -208,11 +235,20 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
                    const double* nu, double* rho, const DevState* st, hipStream_t s,
                    double* Xm = nullptr);
-// Out = X M (subtract = 0) or Out -= X M (subtract = 1); M float64 p x p
+// Out = X M (subtract = 0) or Out -= X M (subtract = 1); M float64 p x p;
+// nothing once st (if given) says "done"
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out,
-                  const double* M, int64_t n, int p, hipStream_t s, int subtract = 0);
-void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,
-                     hipStream_t s);
+                  const double* M, int64_t n, int p, hipStream_t s, int subtract = 0,
+                  const DevState* st = nullptr);
+// Blocked Cholesky S = R^T R (R upper) and Rinv = R^{-1}, float64, on the device
+// (work: p x p scratch).  A non-positive pivot sets st->info to its index + 1;
+// with stop_on_fail it also ends the iteration (st->done, STF_E_DIVERGED).
+// Every kernel returns at once when st->done is already set.
+void launch_chol_inv(const double* S, double* R, double* Rinv, double* work, int p,
+                     DevState* st, hipStream_t s, int stop_on_fail = 0);
+// MOptQR: V = X - D / eta (eta from the state), out of place, float64
+void launch_vform(const double* X, const double* D, double* V, int64_t n, int p,
+                  const DevState* st, hipStream_t s);
 void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,
                     hipStream_t s);
 void launch_eval_finish(const stf_problem* prob, const double* X, const double* G,

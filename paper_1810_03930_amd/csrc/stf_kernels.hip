@@ -247,6 +247,44 @@ __global__ __launch_bounds__(1024) void k_hartree1d(const double* __restrict__ r
                                                     const DevState* __restrict__ st) {
     body_hartree1d(rho, phi, n, st, blockIdx.x, gridDim.x);
 }
+// Block-diagonal L = Diag(L_1, ..., L_s) (blocks of order `block`, the last one
+// shorter): L^{-1} is block-diagonal and each block is the Green's function
+// above of the block's order.  Long blocks: one workgroup per block (the scan
+// above on the block's range); short blocks: one thread per block, the two
+// sums of the Green's function formula taken serially.
+__global__ __launch_bounds__(1024) void k_hartree1d_wg(const double* __restrict__ rho,
+                                                       double* __restrict__ phi, int64_t n,
+                                                       int64_t block,
+                                                       const DevState* __restrict__ st) {
+    const int64_t b0 = (int64_t)blockIdx.x * block;
+    if (b0 >= n) return;
+    const int64_t m = min(block, n - b0);
+    body_hartree1d(rho + b0, phi + b0, m, st, 0, 1);
+}
+__global__ __launch_bounds__(256) void k_hartree1d_short(const double* __restrict__ rho,
+                                                         double* __restrict__ phi, int64_t n,
+                                                         int block,
+                                                         const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b0 = b * block;
+    if (b0 >= n) return;
+    const int m = (int)min((int64_t)block, n - b0);
+    const double mp1 = (double)(m + 1);
+    // phi_i = ((m+1-i) sum_{j<=i} j rho_j + i sum_{j>i} (m+1-j) rho_j) / (m+1), 1-based
+    double A = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double j = (double)(i + 1);
+        A += j * rho[b0 + i];
+        phi[b0 + i] = (mp1 - j) * A;
+    }
+    double B = 0.0;
+    for (int i = m - 1; i >= 0; --i) {
+        const double j = (double)(i + 1);
+        phi[b0 + i] = (phi[b0 + i] + j * B) / mp1;
+        B += (mp1 - j) * rho[b0 + i];
+    }
+}
 
 
 // 3D: the orthonormal DST-I matrix S_m[k][j] = sqrt(2/(m+1)) sin(pi (k+1)(j+1)/(m+1))
@@ -410,7 +448,7 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                                                       int nx, int ny, int nz,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
-                                                      double alpha,
+                                                      double alpha, const GradExtra ex,
                                                       const DevState* __restrict__ st, int bid_, int nblk_) {
     if (st && st->done) return;
     constexpr int V = 16 / (int)sizeof(T);
@@ -423,13 +461,18 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
         double dg = (ND == 6) ? 6.0 : 2.0;
         if (v) dg += v[r];
         if (phi) dg += alpha * phi[r];
+        // exchange term of Problem 6: -2 gamma rho_r^{1/3} on the row diagonal
+        if (ex.gamma != 0.0) dg -= 2.0 * ex.gamma * cbrt(ex.rho[r]);
         int64_t nb[ND];
         T w[ND];
         if (ND == 2) {
-            nb[0] = r > 0 ? r - 1 : r;
-            w[0] = r > 0 ? (T)1 : (T)0;
-            nb[1] = r + 1 < n ? r + 1 : r;
-            w[1] = r + 1 < n ? (T)1 : (T)0;
+            // blocks of order ex.block: no coupling across a block boundary
+            const bool lo = r > 0 && (ex.block <= 0 || r % ex.block != 0);
+            const bool hi = r + 1 < n && (ex.block <= 0 || (r + 1) % ex.block != 0);
+            nb[0] = lo ? r - 1 : r;
+            w[0] = lo ? (T)1 : (T)0;
+            nb[1] = hi ? r + 1 : r;
+            w[1] = hi ? (T)1 : (T)0;
         } else {
             const int64_t sxy = (int64_t)nx * ny;
             const int64_t x = r % nx, y = (r / nx) % ny, z = r / sxy;
@@ -453,6 +496,12 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                 tv acc = tdg * xc;
 #pragma unroll
                 for (int q = 0; q < ND; ++q) acc -= w[q] * xn[q];
+                if (ex.glin) {
+                    // linear term of Problem 2
+                    const double* gl = ex.glin + (size_t)r * p + c;
+#pragma unroll
+                    for (int e = 0; e < V; ++e) acc[e] += (T)gl[e];
+                }
                 typedef TO ov __attribute__((ext_vector_type(V)));
                 ov o;
 #pragma unroll
@@ -464,6 +513,7 @@ __device__ __forceinline__ void body_grad_stencil(const T* __restrict__ X,
                 T acc = tdg * xr[c];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) acc -= w[q] * X[(size_t)nb[q] * p + c];
+                if (ex.glin) acc += (T)ex.glin[(size_t)r * p + c];
                 gr[c] = (TO)acc;
             }
         }
@@ -475,9 +525,9 @@ __global__ __launch_bounds__(256) void k_grad_stencil(const T* __restrict__ X,
                                                       int nx, int ny, int nz,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ phi,
-                                                      double alpha,
+                                                      double alpha, const GradExtra ex,
                                                       const DevState* __restrict__ st) {
-    body_grad_stencil<T, TO, ND>(X, G, n, p, nx, ny, nz, v, phi, alpha, st, blockIdx.x,
+    body_grad_stencil<T, TO, ND>(X, G, n, p, nx, ny, nz, v, phi, alpha, ex, st, blockIdx.x,
                                  gridDim.x);
 }
 
@@ -1661,6 +1711,7 @@ template <typename T, int WM>
 __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
                                                     const T* __restrict__ X, T* __restrict__ G,
                                                     int64_t n, int p, int nbp,
+                                                    const double* __restrict__ glin,
                                                     const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int WT = 16 * WM, BT = 2 * WT;
@@ -1686,7 +1737,11 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = zc0 + i * 16 + Mma<T>::row(lk, q);
                 const int c = yc0 + j * 16 + lr;
-                if (r < n && c < p) G[(size_t)r * p + c] = acc[i][j][q];
+                if (r < n && c < p) {
+                    const size_t idx = (size_t)r * p + c;
+                    // the linear term of Problem 2 (if any)
+                    G[idx] = glin ? (T)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
+                }
             }
 }
 
@@ -1696,6 +1751,13 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
 // = [W - S Psi + beta S C]_ii (eq. (lambda2)); M_L = Psi - beta C + Diag(d), so
 // that grad_X L_beta(X, Lam) = G - X M_L; Bm = beta C - Diag(d) (so that
 // G - X Psi = gradL - X Bm); feas_part[i] = sum_j C_ij^2.
+//
+// Dual ascent (STF_MULT_DUAL, PLAM-DA / PCAL-DA of Section 5.3): Step 3 takes
+// Lam^k = Lam^{k-1} - beta C (eq. (Lambda-alm)) from Lam^0 = Psi, kept in lam2
+// by iteration parity (so that an iteration redone after a precision hand-over
+// reads the untouched Lam^{k-1}); M_L = Lam^k - beta C.
+// MOptQR (Table 1): D = G - X G^T X = G - X W^T, i.e. M_L = W^T.
+// In both, Bm = Psi - M_L (G - X Psi = D - X Bm).
 __device__ __forceinline__ void body_stage1(const DevParams* __restrict__ prm,
                                                 const double* __restrict__ S,
                                                 const double* __restrict__ W,
@@ -1703,8 +1765,40 @@ __device__ __forceinline__ void body_stage1(const DevParams* __restrict__ prm,
                                                 double* __restrict__ ML,
                                                 double* __restrict__ Bm,
                                                 double* __restrict__ feas_part, int p,
-                                                const DevState* __restrict__ st, int bid_, int nblk_) {
+                                                const DevState* __restrict__ st, int bid_, int nblk_,
+                                                double* __restrict__ lam2 = nullptr) {
     if (st->done) return;
+    if (prm->variant == STF_MOPTQR || prm->mult_rule == STF_MULT_DUAL) {
+        __shared__ double shf[4];
+        const int i = bid_;
+        const double beta = prm->beta;
+        const bool dual = prm->variant != STF_MOPTQR;
+        const int k = st->iter;
+        const size_t p2 = (size_t)p * p;
+        const double* Lprev = dual ? lam2 + (size_t)((k + 1) & 1) * p2 : nullptr;
+        double* Lcur = dual ? lam2 + (size_t)(k & 1) * p2 : nullptr;
+        double f2 = 0.0;
+        for (int j = threadIdx.x; j < p; j += 256) {
+            const size_t e = (size_t)i * p + j;
+            const double psi = 0.5 * (W[e] + W[(size_t)j * p + i]);
+            const double c = S[e] - (i == j ? 1.0 : 0.0);
+            f2 += c * c;
+            double ml;
+            if (dual) {
+                const double lam = (k == 0) ? psi : Lprev[e] - beta * c;
+                Lcur[e] = lam;
+                ml = lam - beta * c;
+            } else {
+                ml = W[(size_t)j * p + i];
+            }
+            Psi[e] = psi;
+            ML[e] = ml;
+            if (Bm) Bm[e] = psi - ml;
+        }
+        f2 = block_sum256(f2, shf);
+        if (threadIdx.x == 0) feas_part[i] = f2;
+        return;
+    }
     __shared__ double sh[4];
     __shared__ double s_d;
     const int i = bid_, tid = threadIdx.x;
@@ -1745,8 +1839,9 @@ __global__ __launch_bounds__(256) void k_stage1(const DevParams* __restrict__ pr
                                                 double* __restrict__ ML,
                                                 double* __restrict__ Bm,
                                                 double* __restrict__ feas_part, int p,
-                                                const DevState* __restrict__ st) {
-    body_stage1(prm, S, W, Psi, ML, Bm, feas_part, p, st, blockIdx.x, gridDim.x);
+                                                const DevState* __restrict__ st,
+                                                double* __restrict__ lam2) {
+    body_stage1(prm, S, W, Psi, ML, Bm, feas_part, p, st, blockIdx.x, gridDim.x, lam2);
 }
 
 
@@ -1762,13 +1857,16 @@ constexpr int kResBC = 64;
 // identity X^{k-1} = nu^{k-1} X^k + gradL^{k-1} / eta^{k-1} (the PCAL scaling
 // undone), so S^k = (1 - nu^{k-1}) X^k - gradL^{k-1} / eta^{k-1}.
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
-template <typename T, typename TG, bool APPLY, bool KKT, int WC>
+// XP = true (MOptQR, whose retraction is not a column scaling) reads the
+// previous iterate X^{k-1} from Xprev instead: S^k = X^k - X^{k-1}.
+template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false>
 __device__ __forceinline__ void body_residual(
     const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
-    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_) {
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_,
+    const T* __restrict__ Xprev = nullptr) {
     if (st && st->done) return;
     constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // rows of M_L (columns of X) per LDS stage
     constexpr int XS = KC + 1;
@@ -1812,7 +1910,7 @@ __device__ __forceinline__ void body_residual(
     for (int j = 0; j < JT; ++j) {
         const int c = c0 + j * 16 + lr;
         cok[j] = c < p;
-        onu[j] = (!APPLY && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
+        onu[j] = (!APPLY && !XP && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
     }
     // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x BC),
     // 16-byte vectors when the row pitch allows it, prefetched one chunk ahead
@@ -1935,7 +2033,7 @@ __device__ __forceinline__ void body_residual(
         // round's loads are issued before this round's arithmetic
         constexpr int NR = 4 * JT;
         TG eg[2][4], ep[2][4];
-        T ex[2][4];
+        T ex[2][4], exp_[XP ? 2 : 1][4];
         auto eload = [&](int rr, int sb) {
             const int i = rr / JT, j = rr % JT;
 #pragma unroll
@@ -1946,6 +2044,7 @@ __device__ __forceinline__ void body_residual(
                 eg[sb][q] = ok ? G[idx] : (TG)0;
                 ex[sb][q] = (ok && iterate) ? X[idx] : (T)0;
                 ep[sb][q] = (ok && have_prev) ? Gprev[idx] : (TG)0;
+                if constexpr (XP) exp_[sb][q] = (ok && have_prev) ? Xprev[idx] : (T)0;
             }
         };
         eload(0, 0);
@@ -1971,7 +2070,11 @@ __device__ __forceinline__ void body_residual(
                 cgg[j] += gl * gl;
                 if (have_prev) {
                     const double glp = (double)ep[sb][q];
-                    const double sd = onu[j] * x - glp * rinv_eta;
+                    double sd;
+                    if constexpr (XP)
+                        sd = x - (double)exp_[sb][q];
+                    else
+                        sd = onu[j] * x - glp * rinv_eta;
                     const double yd = gl - glp;
                     sss += sd * sd;
                     ssy += sd * yd;
@@ -2019,15 +2122,17 @@ __device__ __forceinline__ void body_residual(
         ps[3] = t3;
     }
 }
-template <typename T, typename TG, bool APPLY, bool KKT, int WC>
+template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false>
 __global__ __launch_bounds__(128 * WC, 2) void k_residual(
     const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
-    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode) {
-    body_residual<T, TG, APPLY, KKT, WC>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt, part_col,
-                                     part_scal, prm, st, mode, blockIdx.x, gridDim.x);
+    const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode,
+    const T* __restrict__ Xprev = nullptr) {
+    body_residual<T, TG, APPLY, KKT, WC, XP>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt,
+                                             part_col, part_scal, prm, st, mode, blockIdx.x,
+                                             gridDim.x, Xprev);
 }
 
 
@@ -2343,56 +2448,206 @@ __global__ __launch_bounds__(256) void k_update(T* __restrict__ X, double* __res
 
 
 // --------------------------------------------------------- CholeskyQR ------
-// R upper with R^T R = S (right-looking, one workgroup), then Rinv = R^{-1}.
-__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ S,
+// Blocked right-looking Cholesky S = R^T R (R upper) and R^{-1}, float64, in
+// 64 x 64 blocks (nb = ceil(p / 64) block rows) without a host round trip:
+//   k_chol_init        A <- S (working copy), R, Rinv <- 0
+//   for j = 0 .. nb-1:
+//     k_chol_diag(j)   R_jj = chol(A_jj) and Z_jj = R_jj^{-1}, in LDS (one workgroup)
+//     k_chol_step(j)   for every upper block pair j < m <= l of the trailing
+//                      matrix: P_m = Z_jj^T A_jm, P_l = Z_jj^T A_jl (the row
+//                      panel R_jm, R_jl), A_ml -= P_m^T P_l; the pair (l, l)
+//                      writes R_jl
+//   k_chol_inv_off(s)  for s = 1 .. nb-1, every block Rinv_{i,i+s} =
+//                      -Z_ii sum_{k=i+1}^{i+s} R_ik Rinv_{k,i+s} (blocks of
+//                      smaller offset are complete)
+// Every 64 x 64 product is sixteen 16 x 16 float64 MFMA tiles (dst_tile), one
+// per wave of a 1024-thread workgroup, on zero-padded LDS operands.  Rows and
+// columns past p are padded with the identity, so ragged last blocks need no
+// special case.
+constexpr int kCB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ S,
+                                                   double* __restrict__ A,
                                                    double* __restrict__ R,
                                                    double* __restrict__ Rinv, int p,
-                                                   DevState* __restrict__ st) {
-    const int t = threadIdx.x, nt = blockDim.x;
+                                                   const DevState* __restrict__ st) {
+    if (st && st->done) return;
     const size_t p2 = (size_t)p * p;
-    __shared__ int bad;
-    if (t == 0) bad = 0;
-    for (size_t e = t; e < p2; e += nt) {
-        const int i = (int)(e / p), j = (int)(e % p);
-        R[e] = (j >= i) ? S[e] : 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < p2;
+         e += (size_t)gridDim.x * blockDim.x) {
+        A[e] = S[e];
+        R[e] = 0.0;
         Rinv[e] = 0.0;
     }
+}
+
+// block (bi, bj) of a p x p row-major matrix into a padded LDS tile; rows or
+// columns past p read as the identity when `eye`, else as zero; `trans`
+// stores the transpose
+__device__ __forceinline__ void chol_load(double* D, const double* M, int p, int bi, int bj,
+                                          bool eye, bool trans) {
+    for (int e = threadIdx.x; e < kCB * kCB; e += blockDim.x) {
+        const int r = e / kCB, c = e % kCB;
+        const int gr = bi * kCB + r, gc = bj * kCB + c;
+        double v;
+        if (gr < p && gc < p)
+            v = M[(size_t)gr * p + gc];
+        else
+            v = (eye && gr == gc) ? 1.0 : 0.0;
+        if (trans)
+            D[c * kDP + r] = v;
+        else
+            D[r * kDP + c] = v;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_chol_diag(double* __restrict__ A,
+                                                    double* __restrict__ R,
+                                                    double* __restrict__ Rinv, int p, int j,
+                                                    DevState* __restrict__ st,
+                                                    int stop_on_fail) {
+    if (st && st->done) return;
+    __shared__ double a[kCB * kDP], z[kCB * kDP];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    chol_load(a, A, p, j, j, true, false);
     __syncthreads();
-    for (int j = 0; j < p; ++j) {
-        __shared__ double piv;
+    // upper Cholesky of the block, one column at a time
+    for (int c = 0; c < kCB; ++c) {
+        const double d = a[c * kDP + c];
+        const bool ok = d > 0.0 && isfinite(d);
+        const double piv = ok ? sqrt(d) : 1.0;
+        __syncthreads();
         if (t == 0) {
-            const double d = R[(size_t)j * p + j];
-            if (!(d > 0.0) || !isfinite(d)) {
-                bad = j + 1;
-                piv = 1.0;
-            } else {
-                piv = sqrt(d);
-            }
-            R[(size_t)j * p + j] = piv;
+            a[c * kDP + c] = piv;
+            if (!ok && bad == 0) bad = j * kCB + c + 1;
         }
+        if (t > c && t < kCB) a[c * kDP + t] /= piv;
         __syncthreads();
-        for (int i = j + 1 + t; i < p; i += nt) R[(size_t)j * p + i] /= piv;
-        __syncthreads();
-        // trailing update of the upper triangle: R[i][l] -= R[j][i] R[j][l], j < i <= l
-        const int m = p - j - 1;
-        const size_t cnt = (size_t)m * m;
-        for (size_t e = t; e < cnt; e += nt) {
-            const int i = j + 1 + (int)(e / m), l = j + 1 + (int)(e % m);
-            if (l >= i) R[(size_t)i * p + l] -= R[(size_t)j * p + i] * R[(size_t)j * p + l];
+        // trailing update of the upper triangle: a[i][l] -= a[c][i] a[c][l], c < i <= l
+        for (int e = t; e < kCB * kCB; e += blockDim.x) {
+            const int i = e / kCB, l = e % kCB;
+            if (i > c && l >= i) a[i * kDP + l] -= a[c * kDP + i] * a[c * kDP + l];
         }
         __syncthreads();
     }
-    // Rinv column by column: R x = e_c by back substitution (upper triangular)
-    for (int c = t; c < p; c += nt) {
-        Rinv[(size_t)c * p + c] = 1.0 / R[(size_t)c * p + c];
-        for (int i = c - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int l = i + 1; l <= c; ++l) s += R[(size_t)i * p + l] * Rinv[(size_t)l * p + c];
-            Rinv[(size_t)i * p + c] = -s / R[(size_t)i * p + i];
+    // Z = R^{-1} (upper), one row at a time from the bottom; 16 threads per
+    // column share the dot product z[i][c] = (delta_ic - sum_{i<l<=c} r[i][l] z[l][c]) / r[i][i]
+    {
+        const int c = t >> 4, part = t & 15;
+        for (int e = t; e < kCB * kCB; e += blockDim.x) z[(e / kCB) * kDP + e % kCB] = 0.0;
+        __syncthreads();
+        for (int i = kCB - 1; i >= 0; --i) {
+            double acc = 0.0;
+            if (c >= i)
+                for (int l = i + 1 + part; l <= c; l += 16) acc += a[i * kDP + l] * z[l * kDP + c];
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            if (c >= i && part == 0) z[i * kDP + c] = ((i == c ? 1.0 : 0.0) - acc) / a[i * kDP + i];
+            __syncthreads();
         }
+    }
+    // store R_jj and Z_jj (upper parts; the lower parts stay zero)
+    for (int e = t; e < kCB * kCB; e += blockDim.x) {
+        const int r = e / kCB, c = e % kCB;
+        const int gr = j * kCB + r, gc = j * kCB + c;
+        if (gr < p && gc < p && c >= r) {
+            R[(size_t)gr * p + gc] = a[r * kDP + c];
+            Rinv[(size_t)gr * p + gc] = z[r * kDP + c];
+        }
+    }
+    if (t == 0 && st && bad) {
+        if (st->info == 0) st->info = bad;
+        if (stop_on_fail) {
+            st->status = STF_E_DIVERGED;
+            st->final_iter = st->iter > 0 ? st->iter - 1 : 0;
+            st->done = 1;
+        }
+    }
+}
+
+// one upper block pair (m, l) of the trailing matrix per workgroup
+__global__ __launch_bounds__(1024) void k_chol_step(double* __restrict__ A,
+                                                    double* __restrict__ R,
+                                                    const double* __restrict__ Rinv, int p,
+                                                    int j, int nb,
+                                                    const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double zt[kCB * kDP], am[kCB * kDP], al[kCB * kDP];
+    // pair index -> (m, l), m <= l, both in (j, nb)
+    const int t2 = nb - j - 1;
+    int u = blockIdx.x, m = 0;
+    while (u >= t2 - m) {
+        u -= t2 - m;
+        ++m;
+    }
+    const int bm = j + 1 + m, bl = bm + u;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
+    chol_load(zt, Rinv, p, j, j, true, true);   // Z_jj^T
+    chol_load(am, A, p, j, bm, false, false);
+    chol_load(al, A, p, j, bl, false, false);
+    __syncthreads();
+    const d4 pm = dst_tile(zt, am, ti, tj, lr, lk);
+    const d4 pl = (bl == bm) ? pm : dst_tile(zt, al, ti, tj, lr, lk);
+    __syncthreads();
+    // am <- P_m^T, al <- P_l
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + Mma<double>::row(lk, q), c = 16 * tj + lr;
+        am[c * kDP + r] = pm[q];
+        al[r * kDP + c] = pl[q];
     }
     __syncthreads();
-    if (t == 0 && st) st->info = bad;
+    const d4 up = dst_tile(am, al, ti, tj, lr, lk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + Mma<double>::row(lk, q), c = 16 * tj + lr;
+        const int gr = bm * kCB + r, gc = bl * kCB + c;
+        if (gr < p && gc < p) A[(size_t)gr * p + gc] -= up[q];
+        if (bm == bl) {
+            const int hr = j * kCB + r;
+            if (hr < p && gc < p) R[(size_t)hr * p + gc] = pl[q];
+        }
+    }
+}
+
+// blocks (i, i + s) of R^{-1}, one per workgroup
+__global__ __launch_bounds__(1024) void k_chol_inv_off(const double* __restrict__ R,
+                                                       double* __restrict__ Rinv, int p,
+                                                       int s_off,
+                                                       const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double ra[kCB * kDP], zb[kCB * kDP];
+    const int i = blockIdx.x, jb = i + s_off;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = i + 1; k <= jb; ++k) {
+        __syncthreads();
+        chol_load(ra, R, p, i, k, false, false);
+        chol_load(zb, Rinv, p, k, jb, false, false);
+        __syncthreads();
+        const d4 t = dst_tile(ra, zb, ti, tj, lr, lk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += t[q];
+    }
+    __syncthreads();
+    chol_load(ra, Rinv, p, i, i, false, false);  // Z_ii
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + Mma<double>::row(lk, q), c = 16 * tj + lr;
+        zb[r * kDP + c] = acc[q];
+    }
+    __syncthreads();
+    const d4 o = dst_tile(ra, zb, ti, tj, lr, lk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + Mma<double>::row(lk, q), c = 16 * tj + lr;
+        const int gr = i * kCB + r, gc = jb * kCB + c;
+        if (gr < p && gc < p) Rinv[(size_t)gr * p + gc] = -o[q];
+    }
 }
 
 // ---------------------------------------------------------- conversions ----
@@ -2404,58 +2659,85 @@ __global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, size_t 
 }
 
 // --------------------------------------------------------- evaluation ------
-// Partial dot products <x, g> over n*p and <rho, phi> over n.
+// Partial sums of <X, G> over n*p, <rho, phi> over n, <X, Glin> over n*p and
+// sum rho^{4/3} over n (each only when its operands are given).
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ X,
                                               const double* __restrict__ G, size_t np,
                                               const double* __restrict__ rho,
                                               const double* __restrict__ phi, int64_t n,
+                                              const double* __restrict__ glin, int exch,
                                               double* __restrict__ out) {
     __shared__ double sh[4];
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < np;
-         e += (size_t)gridDim.x * blockDim.x)
+         e += (size_t)gridDim.x * blockDim.x) {
         a += X[e] * G[e];
-    if (rho && phi)
+        if (glin) c += X[e] * glin[e];
+    }
+    if (rho)
         for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-             e += (int64_t)gridDim.x * blockDim.x)
-            b += rho[e] * phi[e];
+             e += (int64_t)gridDim.x * blockDim.x) {
+            if (phi) b += rho[e] * phi[e];
+            if (exch) d += rho[e] * cbrt(rho[e]);
+        }
     const double ta = block_sum256(a, sh);
     const double tb = block_sum256(b, sh);
+    const double tc = block_sum256(c, sh);
+    const double td = block_sum256(d, sh);
     if (threadIdx.x == 0) {
-        out[blockIdx.x * 2] = ta;
-        out[blockIdx.x * 2 + 1] = tb;
+        out[blockIdx.x * 4] = ta;
+        out[blockIdx.x * 4 + 1] = tb;
+        out[blockIdx.x * 4 + 2] = tc;
+        out[blockIdx.x * 4 + 3] = td;
     }
 }
 
-// f = 1/2 <X, G> - alpha/4 rho^T phi  (since G = H0 X + alpha Diag(phi) X),
+// f from <X, G>: with G = H0 X B + Glin + alpha Diag(phi) X - 2 gamma Diag(rho^{1/3}) X,
+//   f = 1/2 <X, G> + 1/2 <X, Glin> - alpha/4 rho^T phi + gamma/4 sum rho^{4/3};
 // kkt = sqrt(sum of the residual partials), feas = ||S - I||_F.
 __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ dots, int nd,
                                                      const double* __restrict__ part_scal,
                                                      int nps, const double* __restrict__ S,
-                                                     int p, double alpha,
+                                                     int p, double alpha, double gamma,
                                                      DevState* __restrict__ st) {
     __shared__ double sh[4];
-    double a = 0.0, b = 0.0, k2 = 0.0, f2 = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0, k2 = 0.0, f2 = 0.0;
     for (int i = threadIdx.x; i < nd; i += 256) {
-        a += dots[2 * i];
-        b += dots[2 * i + 1];
+        a += dots[4 * i];
+        b += dots[4 * i + 1];
+        c += dots[4 * i + 2];
+        d += dots[4 * i + 3];
     }
     for (int i = threadIdx.x; i < nps; i += 256) k2 += part_scal[(size_t)i * 4];
     const size_t p2 = (size_t)p * p;
     for (size_t e = threadIdx.x; e < p2; e += 256) {
         const int i = (int)(e / p), j = (int)(e % p);
-        const double c = S[e] - (i == j ? 1.0 : 0.0);
-        f2 += c * c;
+        const double cc = S[e] - (i == j ? 1.0 : 0.0);
+        f2 += cc * cc;
     }
     a = block_sum256(a, sh);
     b = block_sum256(b, sh);
+    c = block_sum256(c, sh);
+    d = block_sum256(d, sh);
     k2 = block_sum256(k2, sh);
     f2 = block_sum256(f2, sh);
     if (threadIdx.x == 0) {
-        st->red[0] = 0.5 * a - 0.25 * alpha * b;
+        st->red[0] = 0.5 * a + 0.5 * c - 0.25 * alpha * b + 0.25 * gamma * d;
         st->red[1] = sqrt(k2);
         st->red[2] = sqrt(f2);
     }
+}
+
+// MOptQR: V = X - D / eta^k (out of place).
+__global__ __launch_bounds__(256) void k_vform(const double* __restrict__ X,
+                                               const double* __restrict__ D,
+                                               double* __restrict__ V, size_t np,
+                                               const DevState* __restrict__ st) {
+    if (st->done) return;
+    const double eta = st->eta;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < np;
+         e += (size_t)gridDim.x * blockDim.x)
+        V[e] = X[e] - D[e] / eta;
 }
 
 // ================================================================ batched ===
@@ -2510,7 +2792,8 @@ __global__ __launch_bounds__(256) void kb_grad(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
     const T* x = d.Xm ? (const T*)d.Xm : (const T*)d.X;
     body_grad_stencil<T, TO, 2>(x, (TO*)d.g[parity], d.n, d.p, (int)d.n, 1, 1, d.v,
-                                d.alpha != 0.0 ? d.phi : nullptr, d.alpha, d.st, lid_, nb_);
+                                d.alpha != 0.0 ? d.phi : nullptr, d.alpha, GradExtra{}, d.st,
+                                lid_, nb_);
 }
 
 template <typename T, int WM>
@@ -2684,6 +2967,16 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi, dou
                     double* dst, const DevState* st, hipStream_t s) {
     const int64_t n = prob->n;
     if (prob->kind == STF_KIND_STENCIL1D) {
+        const int64_t blk = prob->block;
+        if (blk > 0 && blk < n) {
+            const int64_t nblk = (n + blk - 1) / blk;
+            if (blk <= 256)
+                k_hartree1d_short<<<(unsigned)((nblk + 255) / 256), 256, 0, s>>>(rho, phi, n,
+                                                                                (int)blk, st);
+            else
+                k_hartree1d_wg<<<(unsigned)nblk, 1024, 0, s>>>(rho, phi, n, blk, st);
+            return;
+        }
         k_hartree1d<<<1, 1024, 0, s>>>(rho, phi, n, st);
         return;
     }
@@ -2714,10 +3007,11 @@ void launch_hartree(const stf_problem* prob, const double* rho, double* phi, dou
 }
 
 void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, const double* phi,
-                 const DevState* st, hipStream_t s, const double* Xm) {
+                 const GradExtra& ex, const DevState* st, hipStream_t s, const double* Xm) {
     const int64_t n = prob->n;
     const int p = prob->p;
     if (prob->kind == STF_KIND_DENSE) {
+        const double* gl = ex.glin;
         // WG tile 128 x 128 for wide p, 32 x 32 otherwise
         if (p > 64) {
             const int nbp = (p + 127) / 128;
@@ -2725,22 +3019,22 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
             if (dtype == STF_F64)
                 k_dense_grad<double, 4><<<nwg, 256, 0, s>>>((const double*)prob->A,
                                                             (const double*)X, (double*)G, n, p,
-                                                            nbp, st);
+                                                            nbp, gl, st);
             else
                 k_dense_grad<float, 4><<<nwg, 256, 0, s>>>((const float*)prob->A,
                                                            (const float*)X, (float*)G, n, p,
-                                                           nbp, st);
+                                                           nbp, gl, st);
         } else {
             const int nbp = (p + 31) / 32;
             const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
             if (dtype == STF_F64)
                 k_dense_grad<double, 1><<<nwg, 256, 0, s>>>((const double*)prob->A,
                                                             (const double*)X, (double*)G, n, p,
-                                                            nbp, st);
+                                                            nbp, gl, st);
             else
                 k_dense_grad<float, 1><<<nwg, 256, 0, s>>>((const float*)prob->A,
                                                            (const float*)X, (float*)G, n, p,
-                                                           nbp, st);
+                                                           nbp, gl, st);
         }
         return;
     }
@@ -2757,7 +3051,7 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
         // too short for runs to fill the chip)
         if constexpr (ND == 6 && sizeof(TO) == 4) {
             constexpr int kRun = 64;
-            if (p % (16 / (int)sizeof(TI)) == 0) {
+            if (p % (16 / (int)sizeof(TI)) == 0 && !ex.glin && ex.gamma == 0.0) {
                 const int64_t gl = ((n + kRun - 1) / kRun + 3) / 4;
                 const unsigned glr = (unsigned)(gl > 65536 ? 65536 : (gl < 1 ? 1 : gl));
                 k_grad_line<TI, TO, ND, kRun><<<glr, 256, 0, s>>>(
@@ -2766,7 +3060,7 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
             }
         }
         k_grad_stencil<TI, TO, ND><<<g, 256, 0, s>>>((const TI*)XP, (TO*)G, n, p, nx, ny, nz,
-                                                     prob->v, ph, prob->alpha, st);
+                                                     prob->v, ph, prob->alpha, ex, st);
     };
     typedef std::integral_constant<int, 6> D3;
     typedef std::integral_constant<int, 2> D1;
@@ -2853,8 +3147,8 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
 
 void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
                    double* ML, double* Bm, double* feas_part, int p, DevState* st,
-                   hipStream_t s) {
-    k_stage1<<<p, 256, 0, s>>>(prm, S, W, Psi, ML, Bm, feas_part, p, st);
+                   hipStream_t s, double* lam2) {
+    k_stage1<<<p, 256, 0, s>>>(prm, S, W, Psi, ML, Bm, feas_part, p, st, lam2);
 }
 
 void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
@@ -2867,7 +3161,7 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
                      const void* Gprev, const double* ML, const double* Psi, const double* nu,
                      int64_t n, int p, double* part_col, double* part_scal,
                      const DevParams* prm, DevState* st, int mode, void* mix, hipStream_t s,
-                     hipEvent_t before_main) {
+                     hipEvent_t before_main, const void* Xprev) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     auto mark = [&]() {
         if (before_main) (void)hipEventRecord(before_main, s);
@@ -2903,7 +3197,12 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     // iterations evaluate the stop test by the p x p identity (no second product)
     const bool kkt_prod = (mode == RES_KKT_ONLY);
     mark();
-    if (dtype == STF_F64) {
+    if (Xprev) {
+        // MOptQR (float64 only): the BB pair from the stored previous iterate
+        k_residual<double, double, false, false, 2, true><<<nwg, 256, 0, s>>>(
+            (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
+            rp.ncb, rp.nrt, part_col, part_scal, prm, st, mode, (const double*)Xprev);
+    } else if (dtype == STF_F64) {
         if (kkt_prod)
             k_residual<double, double, false, true, 2><<<nwg, 256, 0, s>>>(
                 (const double*)X, (double*)G, (const double*)Gprev, ML, Psi, nu, n, p, rp.nrb,
@@ -2944,21 +3243,40 @@ void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const d
 }
 
 void launch_apply(int dtype, const ResPlan& rp, const void* X, void* Out, const double* M,
-                  int64_t n, int p, hipStream_t s, int subtract) {
+                  int64_t n, int p, hipStream_t s, int subtract, const DevState* st) {
     const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
     if (dtype == STF_F64)
         k_residual<double, double, true, false, 2><<<nwg, 256, 0, s>>>(
             (const double*)X, (double*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
-            rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
+            rp.nrt, nullptr, nullptr, nullptr, st, subtract);
     else
         k_residual<float, float, true, false, 2><<<nwg, 256, 0, s>>>(
             (const float*)X, (float*)Out, nullptr, M, nullptr, nullptr, n, p, rp.nrb, rp.ncb,
-            rp.nrt, nullptr, nullptr, nullptr, nullptr, subtract);
+            rp.nrt, nullptr, nullptr, nullptr, st, subtract);
 }
 
-void launch_chol_inv(const double* S, double* R, double* Rinv, int p, DevState* st,
-                     hipStream_t s) {
-    k_chol_inv<<<1, 1024, 0, s>>>(S, R, Rinv, p, st);
+void launch_chol_inv(const double* S, double* R, double* Rinv, double* work, int p,
+                     DevState* st, hipStream_t s, int stop_on_fail) {
+    const int nb = (p + kCB - 1) / kCB;
+    const size_t p2 = (size_t)p * p;
+    unsigned gi = (unsigned)((p2 + 255) / 256);
+    if (gi > 4096) gi = 4096;
+    k_chol_init<<<gi, 256, 0, s>>>(S, work, R, Rinv, p, st);
+    for (int j = 0; j < nb; ++j) {
+        k_chol_diag<<<1, 1024, 0, s>>>(work, R, Rinv, p, j, st, stop_on_fail);
+        const int t = nb - j - 1;
+        if (t > 0) k_chol_step<<<(unsigned)(t * (t + 1) / 2), 1024, 0, s>>>(work, R, Rinv, p, j, nb, st);
+    }
+    for (int so = 1; so < nb; ++so)
+        k_chol_inv_off<<<(unsigned)(nb - so), 1024, 0, s>>>(R, Rinv, p, so, st);
+}
+
+void launch_vform(const double* X, const double* D, double* V, int64_t n, int p,
+                  const DevState* st, hipStream_t s) {
+    const size_t np = (size_t)n * p;
+    unsigned g = (unsigned)((np + 255) / 256);
+    if (g > 8192) g = 8192;
+    k_vform<<<g, 256, 0, s>>>(X, D, V, np, st);
 }
 
 void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,
@@ -2982,9 +3300,11 @@ void launch_eval_finish(const stf_problem* prob, const double* X, const double* 
                         hipStream_t s) {
     const int nd = 512;
     const bool hart = prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
-    k_dots<<<nd, 256, 0, s>>>(X, G, (size_t)n * p, hart ? rho : nullptr, hart ? phi : nullptr,
-                              n, dots);
-    k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, S, p, hart ? prob->alpha : 0.0, st);
+    const bool exch = prob->kind != STF_KIND_DENSE && prob->gamma != 0.0;
+    k_dots<<<nd, 256, 0, s>>>(X, G, (size_t)n * p, (hart || exch) ? rho : nullptr,
+                              hart ? phi : nullptr, n, prob->Glin, exch ? 1 : 0, dots);
+    k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, S, p, hart ? prob->alpha : 0.0,
+                                    exch ? prob->gamma : 0.0, st);
 }
 
 

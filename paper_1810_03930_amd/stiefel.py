@@ -18,6 +18,8 @@ _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32, "mixed": L.PREC_MIXED}
 _ETA = {"const": L.ETA_CONST, "diff": L.ETA_DIFF, "bb1": L.ETA_BB1, "bb2": L.ETA_BB2,
         "abb": L.ETA_ABB}
 _KIND = {"stencil1d": L.KIND_STENCIL1D, "stencil3d": L.KIND_STENCIL3D, "dense": L.KIND_DENSE}
+_VARIANT = {"plam": L.PLAM, "pcal": L.PCAL, "moptqr": L.MOPTQR}
+_MULT = {"psi": L.MULT_PSI, "psi_phi": L.MULT_PSI_PHI, "dual": L.MULT_DUAL}
 
 
 class StiefelError(RuntimeError):
@@ -52,6 +54,10 @@ class DeviceProblem:
     A: Optional[torch.Tensor] = None     # dense n x n, float64 or float32
     s_bound: float = 0.0
     name: str = ""
+    block: int = 0                       # 1D: order of the tridiagonal blocks (0: one)
+    gamma: float = 0.0                   # exchange weight (Problem 6)
+    Glin: Optional[torch.Tensor] = None  # float64 n x p linear term (Problem 2)
+    B: Optional[torch.Tensor] = None     # float64 p x p right factor (Problem 4)
     _c: Optional[L.StfProblem] = field(default=None, repr=False)
 
     @staticmethod
@@ -64,9 +70,16 @@ class DeviceProblem:
             dt = A_dtype or (torch.float32 if prob.A.dtype == np.float32 else torch.float64)
             A = torch.as_tensor(np.ascontiguousarray(prob.A), device=device).to(dt)
         grid = tuple(int(g) for g in prob.grid)
+
+        def dev64(a):
+            return None if a is None else torch.as_tensor(
+                np.ascontiguousarray(a, np.float64), device=device)
         return DeviceProblem(kind=prob.kind, n=int(prob.n), p=int(prob.p), grid=grid,
                              alpha=float(prob.alpha), v=v, A=A, s_bound=float(prob.s_bound),
-                             name=prob.name)
+                             name=prob.name, block=int(getattr(prob, "block", 0) or 0),
+                             gamma=float(getattr(prob, "gamma", 0.0) or 0.0),
+                             Glin=dev64(getattr(prob, "Glin", None)),
+                             B=dev64(getattr(prob, "B", None)))
 
     def c(self) -> L.StfProblem:
         cp = L.StfProblem()
@@ -78,6 +91,10 @@ class DeviceProblem:
         cp.alpha = self.alpha
         cp.v = _ptr(self.v)
         cp.A = _ptr(self.A)
+        cp.block = int(self.block)
+        cp.gamma = float(self.gamma)
+        cp.Glin = _ptr(self.Glin)
+        cp.B = _ptr(self.B)
         return cp
 
 
@@ -103,8 +120,8 @@ class SolveOptions:
 
     def c(self) -> L.StfOptions:
         o = L.StfOptions()
-        o.variant = L.PCAL if self.variant == "pcal" else L.PLAM
-        o.mult_rule = L.MULT_PSI_PHI if self.mult == "psi_phi" else L.MULT_PSI
+        o.variant = _VARIANT[self.variant]
+        o.mult_rule = _MULT[self.mult]
         o.eta_rule = _ETA[self.eta_rule]
         o.bb_index = L.BB_LAGGED if self.bb_index == "lagged" else L.BB_STANDARD
         o.precision = _PREC[self.precision]

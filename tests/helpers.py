@@ -46,3 +46,12 @@ def assert_converged(rc, kkt_rel, tol, slack=1.01):
     assert rc in (0, 2), rc
     assert (rc == 0) == (kkt_rel <= tol), (rc, kkt_rel, tol)
     assert kkt_rel <= slack * tol, (kkt_rel, tol)
+
+
+def maxrel(a, b):
+    """Elementwise bound: max |a - b| / max |b| (a relative Frobenius norm can
+    hide a localized error, e.g. one wrong boundary plane)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0)) if b.size else 0.0

@@ -44,8 +44,10 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # offsets and sizes that the C compiler gives the structs on x86-64
-    assert ctypes.sizeof(L.StfProblem) == 56
+    assert ctypes.sizeof(L.StfProblem) == 88
     assert L.StfProblem.alpha.offset == 32 and L.StfProblem.A.offset == 48
+    assert L.StfProblem.block.offset == 56 and L.StfProblem.gamma.offset == 64
+    assert L.StfProblem.Glin.offset == 72 and L.StfProblem.B.offset == 80
     assert ctypes.sizeof(L.StfOptions) == 48 + 56
     assert L.StfOptions.beta.offset == 48 and L.StfOptions.history.offset == 96
     assert ctypes.sizeof(L.StfResult) == 8 + 8 * 8 + 8 * 8 + 8
@@ -74,10 +76,13 @@ def test_workspace_size_host_only():
     opt = L.StfOptions()
     opt.precision = L.PREC_FP64
     s64 = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    opt.variant = L.MOPTQR                     # the comparator keeps a second iterate
+    s64m = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    opt.variant = L.PCAL
     opt.precision = L.PREC_FP32
     s32 = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
-    assert s64 > 0 and s32 > 0
-    assert lib.stf_workspace_size(ctypes.byref(ok), None) == max(s64, s32)
+    assert s64 > 0 and s32 > 0 and s64m >= s64 + 2 * 1000 * 10 * 8
+    assert lib.stf_workspace_size(ctypes.byref(ok), None) == max(s64m, s32)
 
 
 def test_invalid_arguments_rejected_before_device_work():
@@ -146,3 +151,54 @@ def test_batched_host_checks():
                                  vp(res), None) == L.E_UNSUPPORTED
     assert lib.stf_solve_batched(2, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
                                  vp(res), None) == L.E_WORKSPACE
+
+
+def test_problem_terms_and_comparator_host_checks():
+    """The Problem 2 / 4 / 6 terms, the block operator and MOptQR are validated on
+    the host before any device work."""
+    lib = L.load()
+    res = L.StfResult()
+    ok = _problem()
+    ok.block = 5
+    assert lib.stf_workspace_size(ctypes.byref(ok), None) > 0
+    bad = _problem(kind=L.KIND_STENCIL3D, n=1000, grid=(10, 10, 10))
+    bad.block = 5                               # blocks belong to the 1D operator
+    assert lib.stf_workspace_size(ctypes.byref(bad), None) == 0
+    neg = _problem()
+    neg.block = -1
+    assert lib.stf_workspace_size(ctypes.byref(neg), None) == 0
+    rf = _problem()
+    rf.B = 1                                    # right factor with a Hartree term
+    assert lib.stf_workspace_size(ctypes.byref(rf), None) == 0
+    rf.alpha = 0.0
+    assert lib.stf_workspace_size(ctypes.byref(rf), None) > 0
+    dn = _problem(kind=L.KIND_DENSE)
+    dn.A = 1
+    dn.alpha = 0.0
+    dn.gamma = 1.0                              # the exchange term needs a density
+    assert lib.stf_workspace_size(ctypes.byref(dn), None) == 0
+    # MOptQR is a float64 comparator
+    o = _valid_options(L.PREC_FP32)
+    o.variant = L.MOPTQR
+    rc = lib.stf_solve(ctypes.byref(_problem()), ctypes.c_void_p(1), ctypes.byref(o),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_UNSUPPORTED
+    o.precision = L.PREC_FP64
+    rc = lib.stf_solve(ctypes.byref(_problem()), ctypes.c_void_p(1), ctypes.byref(o),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_WORKSPACE
+    # dual ascent for both variants; an unknown multiplier rule is refused
+    o.variant, o.mult_rule = L.PLAM, L.MULT_DUAL
+    rc = lib.stf_solve(ctypes.byref(_problem()), ctypes.c_void_p(1), ctypes.byref(o),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_WORKSPACE
+    o.mult_rule = 9
+    rc = lib.stf_solve(ctypes.byref(_problem()), ctypes.c_void_p(1), ctypes.byref(o),
+                       ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+    assert rc == L.E_INVALID
+    # the batched solver covers Problem 1 only
+    vp = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    ex = _problem()
+    ex.gamma = 1.0
+    probs = (L.StfProblem * 1)(ex)
+    assert lib.stf_batched_workspace_size(1, vp(probs), None) == 0
