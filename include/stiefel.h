@@ -108,6 +108,8 @@ extern "C" {
 #define STF_E_UNSUPPORTED   -4   /* option combination not supported */
 #define STF_E_WORKSPACE     -5   /* workspace smaller than stf_workspace_size() */
 #define STF_E_CHOLESKY      -6   /* CholeskyQR2 met a non-positive pivot (rank-deficient X) */
+#define STF_E_SCRATCH       -7   /* the problem needs more than the library's static
+                                    scratch buffer (stf_gram_noalloc) */
 
 /* ---- problem descriptor ---------------------------------------------------
  * The objective is
@@ -395,6 +397,22 @@ int stf_batched_tune(int32_t nprob, const stf_problem* probs, void* const* X,
                      const stf_options* opts, void* ws, size_t ws_bytes, int32_t iters,
                      int32_t* best_gram, int32_t* best_res, double* best_ms_per_iter,
                      hipStream_t stream);
+
+/* ---- no allocation -------------------------------------------------------
+ * stf_gram without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same inputs, outputs and arithmetic as stf_gram;
+ * the split-K partial sums go to a static device buffer of
+ * STF_NOALLOC_SCRATCH_BYTES that the library owns on each GPU it runs on (held
+ * until the process ends), so the call allocates nothing.  Calls that overlap
+ * on one GPU (other streams or threads) share that buffer and race: serialize
+ * them.  When even one split-K chunk of the Gram tiles does not fit the
+ * buffer (p above about 2048) it returns STF_E_SCRATCH; the chunk count is
+ * otherwise capped to fit, so the summation order can differ from stf_gram's
+ * (results equal to rounding).  Host-synchronous. */
+#define STF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int stf_gram_noalloc(const stf_problem* prob, const void* X, const void* G, int32_t dtype,
+                     int32_t precision, double* S, double* W, hipStream_t stream);
 
 /* Human-readable name of a return code (static string). */
 const char* stf_strerror(int code);

@@ -21,6 +21,8 @@ BB_STANDARD, BB_LAGGED = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
 OK, MAX_ITER, TOL_UNMET = 0, 1, 2
 E_INVALID, E_DIVERGED, E_HIP, E_UNSUPPORTED, E_WORKSPACE, E_CHOLESKY = -1, -2, -3, -4, -5, -6
+E_SCRATCH = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class StfProblem(ctypes.Structure):
@@ -117,6 +119,8 @@ SIGNATURES = {
     "stf_batched_tune": (ctypes.c_int, [ctypes.c_int32, _VP, _VP, _VP, _VP, _SZ,
                                         ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
                                         _P(ctypes.c_double), _VP]),
+    "stf_gram_noalloc": (ctypes.c_int, [_P(StfProblem), _VP, _VP, ctypes.c_int32,
+                                        ctypes.c_int32, _VP, _VP, _VP]),
     "stf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stf_version": (ctypes.c_char_p, []),
 }

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_NAME = "libstiefel.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["stf_kernels.hip", "stf_api.hip", "stf_batched.hip", "stf_adjoint.hip"]
+SOURCES = ["stf_kernels.hip", "stf_api.hip", "stf_batched.hip", "stf_adjoint.hip",
+           "stf_noalloc.hip"]
 
 
 def hipcc_path() -> str:

@@ -764,6 +764,7 @@ const char* stf_strerror(int code) {
         case STF_E_UNSUPPORTED: return "unsupported option combination";
         case STF_E_WORKSPACE: return "workspace too small";
         case STF_E_CHOLESKY: return "CholeskyQR2 met a non-positive pivot";
+        case STF_E_SCRATCH: return "problem too large for the static scratch buffer";
         default: return "unknown status";
     }
 }

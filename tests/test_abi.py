@@ -113,7 +113,7 @@ def test_invalid_arguments_rejected_before_device_work():
 
 
 def test_strerror_and_version():
-    for code in [0, 1, -1, -2, -3, -4, -5, -6]:
+    for code in [0, 1, 2, -1, -2, -3, -4, -5, -6, -7]:
         assert len(L.strerror(code)) > 5
     assert L.strerror(12345) == "unknown status"
     assert L.load().stf_version().decode().startswith("stiefel")
