@@ -40,7 +40,8 @@ SWITCH_TOL = 1e-5   # relative KKT at which the fast form continues in float64
 BATCH_SWITCH_TOL = 1e-3
 MAX_ITER = 6000
 HBM_PEAK_GBS = 8000.0
-FORM_DTYPE = {"fp32": "f32", "mixed": "bf16x3/bf16x6 MFMA, f32 storage, f64 master"}
+FORM_DTYPE = {"fp32": "f32", "mixed": "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
+              "mixed32": "bf16x3/bf16x6 MFMA, f32 storage, no f64 master"}
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed_bf16": 2500.0}
 
 
@@ -57,14 +58,21 @@ def kernel_algorithmic(name, n, p, precision):
     """
     npe = float(n) * p
     s = 8 if precision == "fp64" else 4
-    if name == "grad":        # read X (float64 master in the float32 forms) + v, phi; write G
-        return npe * (8 + s) + 16.0 * n, 14.0 * npe
+    master = precision in ("fp32", "mixed")   # float64 master iterate beside the float32 X
+    if name == "grad":        # read X (the float64 master when there is one) + v, phi; write G
+        return npe * ((8 if master or precision == "fp64" else 4) + s) + 16.0 * n, 14.0 * npe
     if name == "gram":        # read X, G: upper halves of S and W (W = X^T H X is symmetric)
         return 2 * npe * s, 2.0 * n * p * (p + 1)
     if name == "residual":    # read X, G, gradL^{k-1}; write gradL over G: G - X M_L
         return 4 * npe * s, 2.0 * n * p * p
-    if name == "update":      # read X (+ master), gradL; write X (+ master), rho
-        return (3 * npe * 8 if precision == "fp64" else npe * (8 + 4 + 8 + 4)) + 8.0 * n, 4.0 * npe
+    if name == "update":      # read X (or the master), gradL; write X (+ master), rho
+        if precision == "fp64":
+            by = 3 * npe * 8
+        elif master:
+            by = npe * (8 + 4 + 8 + 4)
+        else:
+            by = 3 * npe * 4
+        return by + 8.0 * n, 4.0 * npe
     if name == "hartree":     # six 1D sine transforms over the grid
         return 7 * 8.0 * n, 6 * 2.0 * n * max(GRID)
     return 0.0, 0.0
@@ -118,16 +126,20 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         # time to relative KKT <= TOL from X0 resident in HBM, graph-replayed loop
         sw = SWITCH_TOL if precision != "fp64" else 0.0
 
+        x64_first = []
+
         def solve_to_tol():
             # a start whose final CholeskyQR2 fails (a rank-deficient iterate
             # after an unconverged run) counts as not reached
             t = time.perf_counter()
             try:
-                r, _, _ = S.solve(dp, X, S.SolveOptions(**common, tol=TOL, max_iter=MAX_ITER,
-                                                        orth_final=True, check_every=50,
-                                                        use_graph=True, switch_tol=sw),
-                                  workspace=ws, stream=stream)
+                r, x64, _ = S.solve(dp, X, S.SolveOptions(**common, tol=TOL, max_iter=MAX_ITER,
+                                                          orth_final=True, check_every=50,
+                                                          use_graph=True, switch_tol=sw),
+                                    workspace=ws, stream=stream, want_x64=not x64_first)
                 torch.cuda.synchronize()
+                if not x64_first:
+                    x64_first.append(x64)
                 return r
             except S.StiefelError as e:
                 torch.cuda.synchronize()
@@ -147,6 +159,7 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
             torch.cuda.synchronize()
             more.append(solve_to_tol())
     runs = [conv] + more
+    x_first = x64_first[0] if x64_first else None
     ttk_all = [(r["ms_loop"] + r["ms_orth"]) / 1000.0 for r in runs]
     reached = [r["rc"] == 0 and r["kkt_rel"] is not None and r["kkt_rel"] <= TOL for r in runs]
     # a start that did not reach the tolerance counts as infinitely slow
@@ -170,9 +183,10 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "time_to_kkt_s_per_start": ttk_all,
         "iters_to_kkt_per_start": [r["iters"] for r in runs],
         "reached_per_start": reached,
+        "reached": f"{sum(reached)}/{len(reached)}",
         "time_to_kkt_s_median": med if np.isfinite(med) else None,
     }
-    return out, None
+    return out, x_first
 
 
 KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_residual",
@@ -182,10 +196,14 @@ KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gr
                ("fp64", "grad"): "body_grad_stencil", ("fp64", "update"): "body_update",
                ("mixed", "residual"): "body_residual_bf6_lds",
                ("mixed", "gram"): "body_gram_bf3_lds", ("mixed", "grad"): "body_grad_line",
-               ("mixed", "update"): "body_update"}
+               ("mixed", "update"): "body_update",
+               ("mixed32", "residual"): "body_residual_bf6_lds",
+               ("mixed32", "gram"): "body_gram_bf3_lds", ("mixed32", "grad"): "body_grad_line",
+               ("mixed32", "update"): "body_update"}
 # kernels that differ from KERNEL_NAMES in one form (the 3D gradient with a
 # float32 G walks runs of rows)
-KERNEL_NAMES_FORM = {("mixed", "grad"): "k_grad_line", ("fp32", "grad"): "k_grad_line"}
+KERNEL_NAMES_FORM = {("mixed", "grad"): "k_grad_line", ("fp32", "grad"): "k_grad_line",
+                     ("mixed32", "grad"): "k_grad_line"}
 
 
 def body_digest(name):
@@ -449,6 +467,87 @@ def parallel_main(args, torch, S, W):
                       "warmup": args.warmup, "data": "synthetic", "rows": rows}), flush=True)
 
 
+def dense_main(args, torch, S, W):
+    """The dense Rayleigh-Ritz workload: A = (B + B^T)/(2 sqrt n) + 4I in
+    float32, B ~ N(0,1), n = 32768, p = 512.  Forms: float64 (A widened
+    exactly, float64 MFMA products), float32 MFMA, and the split-bf16 form
+    (A X as three bf16 MFMA products with float32 accumulation, split-bf16
+    Grams) handing over to float64 at 1e-4.  Per-iteration costs, the dense
+    product's roofline, and time to relative KKT 1e-6."""
+    n, p = args.dense_n, args.dense_p
+    log(f"generating the dense workload n={n} p={p} (seeded)")
+    prob, x0 = W.dense_quadratic(n=n, p=p, dtype=np.float32)
+    dp = S.DeviceProblem.from_host(prob)
+    beta = prob.s_bound + 0.1          # above the p-th eigenvalue (positive definite A)
+    stream = torch.cuda.Stream()
+    out = {}
+    for prec in args.dense_forms.split(","):
+        sw = 1e-4 if prec in ("mixed", "mixed32", "fp32") else 0.0
+        opts = S.SolveOptions(variant="pcal", mult="psi_phi", eta_rule="abb", precision=prec,
+                              beta=beta, eta0=beta + prob.s_bound, tol=TOL,
+                              max_iter=args.dense_max_iter, orth_final=True, check_every=20,
+                              use_graph=True, switch_tol=sw)
+        dt = S.storage_dtype(prec)
+        ws = S.alloc_workspace(dp, opts)
+        X = torch.empty((n, p), dtype=dt, device="cuda")
+        x0d = torch.as_tensor(x0, device="cuda").to(dt)
+        base = {k: getattr(opts, k) for k in opts.__dataclass_fields__}
+        with torch.cuda.stream(stream):
+            X.copy_(x0d)
+            torch.cuda.synchronize()
+            S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0, "max_iter": args.warmup,
+                                            "orth_final": False, "use_graph": False,
+                                            "check_every": max(1, args.warmup)}),
+                    workspace=ws, stream=stream)
+            X.copy_(x0d)
+            torch.cuda.synchronize()
+            pr, _, _ = S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0,
+                                                        "max_iter": args.steps,
+                                                        "orth_final": False,
+                                                        "use_graph": False, "profile": True,
+                                                        "check_every": args.steps}),
+                               workspace=ws, stream=stream)
+            X.copy_(x0d)
+            torch.cuda.synchronize()
+            r, _, _ = S.solve(dp, X, S.SolveOptions(**{**base, "tol": 0.0,
+                                                       "max_iter": args.steps,
+                                                       "orth_final": False, "use_graph": False,
+                                                       "check_every": args.steps}),
+                              workspace=ws, stream=stream)
+            X.copy_(x0d)
+            torch.cuda.synchronize()
+            log(f"dense {prec}: solve to {TOL}")
+            try:
+                c, _, _ = S.solve(dp, X, opts, workspace=ws, stream=stream)
+            except S.StiefelError as e:
+                c = {"rc": e.code, "iters": None, "kkt_rel": None, "fval": None,
+                     "ms_loop": None, "ms_orth": None, "switch_iter": None}
+            torch.cuda.synchronize()
+        n_it = max(1, pr["prof_iters"])
+        km = {k: v / n_it for k, v in pr["kernel_ms"].items()}
+        flops = 2.0 * n * n * p
+        if prec == "fp64":
+            peak, unit_peak = PEAK_TFLOPS["fp64"], "fp64"
+        elif prec == "fp32":
+            peak, unit_peak = PEAK_TFLOPS["fp32"], "fp32"
+        else:
+            peak, unit_peak = PEAK_TFLOPS["mixed_bf16"] / 3.0, "bf16 peak / 3 products"
+        ach = flops / (km["grad"] * 1e-3) / 1e12
+        out[prec] = {"ms_per_iter": r["ms_loop"] / args.steps, "kernel_avg_ms": km,
+                     "dense_product": {"achieved_tflops": ach, "peak_tflops": peak,
+                                       "peak_of": unit_peak, "frac": ach / peak},
+                     "to_tol": {"rc": c["rc"], "iters": c["iters"], "kkt_rel": c["kkt_rel"],
+                                "f": c["fval"], "switch_iter": c.get("switch_iter"),
+                                "s": None if c["ms_loop"] is None
+                                else (c["ms_loop"] + c["ms_orth"]) / 1000.0}}
+        log(f"dense {prec}: {json.dumps(out[prec])}")
+        del ws, X, x0d
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "dense Rayleigh-Ritz PCAL, n=%d p=%d: ms/iteration and time to "
+                      "relative KKT 1e-6 per form" % (n, p), "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic", "forms": out}), flush=True)
+
+
 def sweep_main(args, torch, S, W):
     """The parameter studies of Section 5.3 on GPU (Problems 1-4 at n = 1000,
     p = 20; Problem 1 with the 3D Kohn-Sham operator on a 10^3 grid): step-size rules
@@ -504,9 +603,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fast-form", default="mixed", choices=["fp32", "mixed"])
+    ap.add_argument("--fast-form", default="mixed", choices=["fp32", "mixed", "mixed32"])
+    ap.add_argument("--extra-forms", default="",
+                    help="comma-separated further forms to measure beside fp64 and the fast form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--starts", type=int, default=5,
+    ap.add_argument("--starts", type=int, default=15,
                     help="seeded starting points of the time-to-KKT solves (the median is reported)")
     ap.add_argument("--skip-ttk", action="store_true",
                     help="skip the time-to-KKT solves (short runs under hardware counters)")
@@ -518,6 +619,12 @@ def main():
                     help="comma-separated p of --parallel (the paper: 500,1000,1500,2000,2500)")
     ap.add_argument("--parallel-all", action="store_true",
                     help="run Problem 6 at every p too (the paper: p = 1000 only)")
+    ap.add_argument("--dense", action="store_true",
+                    help="measure the dense Rayleigh-Ritz workload (n = 32768, p = 512)")
+    ap.add_argument("--dense-n", type=int, default=32768)
+    ap.add_argument("--dense-p", type=int, default=512)
+    ap.add_argument("--dense-forms", default="fp64,fp32,mixed")
+    ap.add_argument("--dense-max-iter", type=int, default=3000)
     ap.add_argument("--sweep", action="store_true",
                     help="run the Section 5.3 step-size / beta / dual-ascent studies")
     ap.add_argument("--copy-ref", action="store_true",
@@ -553,18 +660,41 @@ def main():
     if args.sweep:
         sweep_main(args, torch, S, W)
         return
+    if args.dense:
+        dense_main(args, torch, S, W)
+        return
     log("generating the 64^3 p=256 workload (seeded)")
     prob, x0, _ = W.ks3d(grid=GRID, p=P, alpha=ALPHA)
     dp = S.DeviceProblem.from_host(prob)
     starts = [W.alternate_start(5, prob.n, P, s) for s in range(1, args.starts)]
     forms = {}
-    for prec in ["fp64", args.fast_form]:
+    finals = {}
+    extra = [f for f in args.extra_forms.split(",") if f and f not in ("fp64", args.fast_form)]
+    for prec in ["fp64", args.fast_form] + extra:
         log(f"form {prec}: {args.warmup} warmup + {args.steps} timed steps, then time-to-KKT")
-        forms[prec], _ = run_form(dp, x0, prec, args.steps, args.warmup, S, torch,
-                                  ttk=not args.skip_ttk, starts=starts)
+        forms[prec], finals[prec] = run_form(dp, x0, prec, args.steps, args.warmup, S, torch,
+                                             ttk=not args.skip_ttk, starts=starts)
         log(f"form {prec}: {json.dumps(forms[prec])}")
     fast = forms[args.fast_form]
     base = forms["fp64"]
+    # per-result error of each reduced-precision form against the float64 form
+    # (seed 0's returned points): objective, KKT and feasibility, and the
+    # distance of the subspaces ||X X^T - Y Y^T||_F (X* is unique only up to
+    # X* Q), via ||X^T X||^2 + ||Y^T Y||^2 - 2 ||X^T Y||^2
+    errors = {}
+    if finals.get("fp64") is not None:
+        Y = finals["fp64"]
+        for prec, Xf in finals.items():
+            if prec == "fp64" or Xf is None:
+                continue
+            a = (torch.linalg.norm(Xf.T @ Xf) ** 2 + torch.linalg.norm(Y.T @ Y) ** 2
+                 - 2 * torch.linalg.norm(Xf.T @ Y) ** 2).item()
+            fb, ff = base["f"], forms[prec]["f"]
+            errors[prec] = {
+                "f_rel_diff": None if (fb is None or ff is None) else abs(ff - fb) / abs(fb),
+                "kkt_rel": forms[prec]["kkt_rel"], "kkt_rel_fp64": base["kkt_rel"],
+                "feas": forms[prec]["feas"], "feas_fp64": base["feas"],
+                "projector_distance": float(np.sqrt(max(a, 0.0)))}
     roof = roofline_for(fast, args.fast_form, prob.n, P)
     roof64 = roofline_for(base, "fp64", prob.n, P)
     cpu = None
@@ -591,8 +721,7 @@ def main():
         "time_to_kkt_s": None if args.skip_ttk else
         {"fp64": base["time_to_kkt_s"], args.fast_form: fast["time_to_kkt_s"]},
         "time_to_kkt_s_median": None if args.skip_ttk else
-        {"fp64": base["time_to_kkt_s_median"], args.fast_form: fast["time_to_kkt_s_median"],
-         "starts": args.starts},
+        {**{f: forms[f]["time_to_kkt_s_median"] for f in forms}, "starts": args.starts},
         # seed 0 alone: only when both forms reached the tolerance from it
         "speedup_time_to_kkt": None if (args.skip_ttk or not base["reached_per_start"][0]
                                         or not fast["reached_per_start"][0]) else
@@ -600,6 +729,9 @@ def main():
         "speedup_time_to_kkt_median": None if (args.skip_ttk or not fast["time_to_kkt_s_median"]
                                                or not base["time_to_kkt_s_median"]) else
         base["time_to_kkt_s_median"] / fast["time_to_kkt_s_median"],
+        "reached": None if args.skip_ttk else {f: forms[f]["reached"] for f in forms},
+        "iters_per_s": {f: forms[f]["iters_per_s"] for f in forms},
+        "result_error_vs_fp64": errors,
         "forms": forms,
         "roofline": roof,
         "roofline_fp64": roof64,

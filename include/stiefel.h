@@ -93,9 +93,13 @@ extern "C" {
  * Both float32 forms stall near relative KKT 5e-6 (see switch_tol).  The
  * p x p multiplier stage, the KKT test and CholeskyQR2 are float64 in every
  * mode. */
-#define STF_PREC_FP64  0
-#define STF_PREC_FP32  1
-#define STF_PREC_MIXED 2
+#define STF_PREC_FP64    0
+#define STF_PREC_FP32    1
+#define STF_PREC_MIXED   2
+/* MIXED32 - the MIXED kernels with the iterate kept in float32 only (no
+ *           float64 master: the stencil and the update read and write the
+ *           float32 X); the float64 hand-over starts from that X. */
+#define STF_PREC_MIXED32 3
 
 /* ---- return codes -------------------------------------------------------- */
 #define STF_OK               0   /* the float64 check of the returned point meets tol */
@@ -124,7 +128,10 @@ extern "C" {
  * alpha  : weight of the Hartree-like term alpha/4 rho^T L^{-1} rho (stencil kinds)
  * v      : device, float64, length n: diagonal potential added to L; may be NULL
  * A      : device, dense symmetric n x n (STF_KIND_DENSE), dtype A_dtype
- *          (STF_F64 or STF_F32); its symmetry is assumed, not checked.
+ *          (STF_F64 or STF_F32); its symmetry is assumed, not checked.  A
+ *          float32 A serves every precision form (the float64 form widens it
+ *          exactly; the MIXED forms take A X in split bf16, three bf16 MFMA
+ *          products with float32 accumulation); a float64 A only STF_PREC_FP64.
  * block  : STENCIL1D only: L = Diag(L_1, ..., L_s) with tridiag(-1,2,-1)
  *          blocks of this order (the last one shorter when it does not divide
  *          n), the operator of the parallel experiments of Section 5.5;
@@ -284,10 +291,11 @@ int pcal_solve(const stf_problem* prob, void* X, const stf_options* opt,
  * the gradients of Problem 1 (the simplified Kohn-Sham energy, with the
  * operators of the workloads) and Problem 3 (Rayleigh-Ritz) of Section 5.2,
  * "Func" in Table 1.
- * X, G: device n x p of dtype (STF_F64 / STF_F32); the dense kind requires
- * dtype == A_dtype.  Computes rho and the Hartree solve internally (in the
- * workspace).  Errors: STF_E_INVALID (NULL, bad dtype), STF_E_UNSUPPORTED
- * (dense dtype mismatch), STF_E_WORKSPACE, STF_E_HIP.  Host-synchronous. */
+ * X, G: device n x p of dtype (STF_F64 / STF_F32); a float32 A serves both
+ * dtypes (widened exactly for float64), a float64 A only dtype STF_F64.
+ * Computes rho and the Hartree solve internally (in the workspace).  Errors:
+ * STF_E_INVALID (NULL, bad dtype), STF_E_UNSUPPORTED (float64 A with a
+ * float32 X), STF_E_WORKSPACE, STF_E_HIP.  Host-synchronous. */
 int stf_gradient(const stf_problem* prob, const void* X, void* G, int32_t dtype,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -318,8 +326,8 @@ int stf_cholqr2(const stf_problem* prob, double* X, void* ws, size_t ws_bytes,
 /* out3 (host, 3 doubles) = { f(X), ||G - X Psi(G^T X)||_F, ||X^T X - I||_F }
  * in float64 for a float64 X: the objective, the KKT violation of the stop
  * test of Section 5.1 (with X Psi in place of X G^T X, as Section 3.3 notes)
- * and the feasibility violation, the three columns of Table 2.  The dense
- * kind needs A_dtype == STF_F64.  Host-synchronous. */
+ * and the feasibility violation, the three columns of Table 2 (a float32 A is
+ * widened exactly).  Host-synchronous. */
 int stf_eval(const stf_problem* prob, const double* X, double* out3,
              void* ws, size_t ws_bytes, hipStream_t stream);
 

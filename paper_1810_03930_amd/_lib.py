@@ -18,7 +18,7 @@ PLAM, PCAL, MOPTQR = 0, 1, 2
 MULT_PSI, MULT_PSI_PHI, MULT_DUAL = 0, 1, 2
 ETA_CONST, ETA_DIFF, ETA_BB1, ETA_BB2, ETA_ABB = 0, 1, 2, 3, 4
 BB_STANDARD, BB_LAGGED = 0, 1
-PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_MIXED, PREC_MIXED32 = 0, 1, 2, 3
 OK, MAX_ITER, TOL_UNMET = 0, 1, 2
 E_INVALID, E_DIVERGED, E_HIP, E_UNSUPPORTED, E_WORKSPACE, E_CHOLESKY = -1, -2, -3, -4, -5, -6
 E_SCRATCH = -7

@@ -218,8 +218,9 @@ int last_launch() { return hipGetLastError() == hipSuccess ? STF_OK : STF_E_HIP;
 // float64 master copy the float32 forms evaluate the stencil on.
 static void enqueue_grad_core(const stf_problem* prob, const Ws& w, int dtype, const void* X,
                               void* G, const DevState* st, hipStream_t s,
-                              const double* Xm = nullptr) {
-    const GradExtra ex = grad_extra(prob, needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr);
+                              const double* Xm = nullptr, int dense_prod = 0) {
+    GradExtra ex = grad_extra(prob, needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr);
+    ex.dense_prod = dense_prod;
     if (prob->B) {
         void* T = w.base + w.L.gtmp;
         launch_grad(prob, dtype, X, T, w.at<double>(w.L.phi), ex, st, s, Xm);
@@ -324,8 +325,10 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
         launch_hartree(prob, rho, w.at<double>(w.L.phi), w.at<double>(w.L.hscr),
                        w.at<double>(w.L.dst), c.st, s);
     mark(1);
+    // the MIXED forms take the dense product A X in split bf16 too
     enqueue_grad_core(prob, w, c.dtype, X, Gc, c.st, s,
-                      prob->kind == STF_KIND_DENSE ? nullptr : c.Xm);
+                      prob->kind == STF_KIND_DENSE ? nullptr : c.Xm,
+                      c.precision == STF_PREC_MIXED ? 3 : 0);
     mark(2);
     // groups 2..4: the Gram kernel | chunk reduction, p x p stage, KKT products,
     // split of M_L | the residual kernel (events 3 and 4 recorded by the launchers)
@@ -386,12 +389,17 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     }
     if (opt->eta_rule < STF_ETA_CONST || opt->eta_rule > STF_ETA_ABB) return STF_E_INVALID;
     if (opt->bb_index != STF_BB_STANDARD && opt->bb_index != STF_BB_LAGGED) return STF_E_INVALID;
-    if (opt->precision < STF_PREC_FP64 || opt->precision > STF_PREC_MIXED) return STF_E_INVALID;
+    if (opt->precision < STF_PREC_FP64 || opt->precision > STF_PREC_MIXED32) return STF_E_INVALID;
+    // MIXED32: the split-bf16 kernels of MIXED with the iterate kept in float32 only
+    const bool nomaster = opt->precision == STF_PREC_MIXED32;
     if (opt->max_iter < 0 || opt->kkt_every < 1 || opt->check_every < 1) return STF_E_INVALID;
     if (!(opt->eta0 > 0.0) || !(opt->tol >= 0.0) || !isfinite(opt->beta)) return STF_E_INVALID;
     if (opt->eta_rule == STF_ETA_CONST && !(opt->eta_const > 0.0)) return STF_E_INVALID;
     const int dtype = (opt->precision == STF_PREC_FP64) ? STF_F64 : STF_F32;
-    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != dtype) return STF_E_UNSUPPORTED;
+    // a float32 A serves every form (the float64 form widens it exactly); a
+    // float64 A only the float64 form
+    if (prob->kind == STF_KIND_DENSE && prob->A_dtype == STF_F64 && dtype != STF_F64)
+        return STF_E_UNSUPPORTED;
 
     Ws w;
     w.base = (char*)ws;
@@ -405,9 +413,9 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     c.prob = prob;
     c.w = w;
     c.dtype = dtype;
-    c.precision = opt->precision;
+    c.precision = nomaster ? STF_PREC_MIXED : opt->precision;
     c.X = X;
-    c.Xm = (dtype == STF_F32) ? w.at<double>(w.L.x64) : nullptr;
+    c.Xm = (dtype == STF_F32 && !nomaster) ? w.at<double>(w.L.x64) : nullptr;
     c.g[0] = w.L.g[0];
     c.g[1] = w.L.g[1];
     c.st = w.at<DevState>(w.L.state);
@@ -533,7 +541,9 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         IterCtx c64 = c;
         c64.dtype = STF_F64;
         c64.precision = STF_PREC_FP64;
-        c64.X = c.Xm;
+        if (nomaster)  // the float64 phase starts from the float32 iterate
+            launch_convert(STF_F64, X, STF_F32, w.at<double>(w.L.x64), (size_t)n * p, s);
+        c64.X = w.at<double>(w.L.x64);
         c64.Xm = nullptr;
         c64.g[k & 1] = w.L.g64;
         c64.g[(k & 1) ^ 1] = w.L.g64b;
@@ -578,8 +588,12 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         Xd = (double*)X;
         tmp = w.at<double>(w.L.g[1]);
     } else {
-        Xd = c.Xm;
+        Xd = w.at<double>(w.L.x64);
         tmp = w.at<double>(w.L.g64);
+        // without a master, the float64 copy is the float32 iterate (unless a
+        // float64 phase has taken over, which iterates on that copy)
+        if (nomaster && res->switch_iter < 0)
+            launch_convert(STF_F64, X, STF_F32, Xd, (size_t)n * p, s);
     }
     DevState* st_eval = w.at<DevState>(w.L.state_eval);
     launch_init_state(st_eval, s);
@@ -681,7 +695,8 @@ int stf_gradient(const stf_problem* prob, const void* X, void* G, int32_t dtype,
     int rc = step_ws(prob, ws, ws_bytes, w);
     if (rc) return rc;
     if (!X || !G || (dtype != STF_F64 && dtype != STF_F32)) return STF_E_INVALID;
-    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != dtype) return STF_E_UNSUPPORTED;
+    if (prob->kind == STF_KIND_DENSE && prob->A_dtype == STF_F64 && dtype != STF_F64)
+        return STF_E_UNSUPPORTED;
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), stream);
     rc = enqueue_gradient(prob, w, dtype, X, G, nullptr, stream);
     if (rc) return rc;
@@ -738,7 +753,7 @@ int stf_eval(const stf_problem* prob, const double* X, double* out3, void* ws, s
     int rc = step_ws(prob, ws, ws_bytes, w);
     if (rc) return rc;
     if (!X || !out3) return STF_E_INVALID;
-    if (prob->kind == STF_KIND_DENSE && prob->A_dtype != STF_F64) return STF_E_UNSUPPORTED;
+
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), stream);
     rc = enqueue_eval(prob, w, X, w.at<double>(w.L.g64), stream);
     if (rc) return rc;

@@ -514,8 +514,13 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
     hipEventElapsedTime(&ms_loop, e0, e1);
     if (ms_per_iter) *ms_per_iter = iters_run > 0 ? ms_loop / (double)iters_run : 0.0;
 
-    // per problem: CholeskyQR2 and the float64 evaluation, as in a single solve
+    // per problem: CholeskyQR2 and the float64 evaluation, as in a single
+    // solve, all enqueued back to back with one read-back after each phase
     int worst = STF_OK;
+    std::vector<Ws> pws(nprob);
+    std::vector<double*> xds(nprob);
+    std::vector<char> live(nprob, 0);
+    std::vector<DevState> he(nprob);
     for (int b = 0; b < nprob; ++b) {
         stf_result& r = res[b];
         const DevState& hb = cur(b);
@@ -530,36 +535,46 @@ int batched_impl(int32_t nprob, const stf_problem* probs, void* const* X,
             worst = STF_E_DIVERGED;
             continue;
         }
-        Ws pw;
+        live[b] = 1;
+        Ws& pw = pws[b];
         pw.base = w + P.pbase[b];
         pw.L = P.L[b];
-        const int64_t n = probs[b].n;
-        const int p = probs[b].p;
-        double* Xd = (P.dtype == STF_F64) ? (double*)X[b]
-                                          : pw.at<double>(pw.L.x64);  // the float64 master
+        xds[b] = (P.dtype == STF_F64) ? (double*)X[b]
+                                      : pw.at<double>(pw.L.x64);  // the float64 master
         double* tmp = (P.dtype == STF_F64) ? pw.at<double>(pw.L.g[1]) : pw.at<double>(pw.L.g64);
         DevState* st_eval = pw.at<DevState>(pw.L.state_eval);
         launch_init_state(st_eval, s);
-        const bool orth = opts[b].orth_final != 0;
-        if (orth && (rc = enqueue_cholqr2(&probs[b], pw, Xd, tmp, st_eval, s))) return rc;
-        DevState he;
-        HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (orth && he.info != 0) {
-            r.status = STF_E_CHOLESKY;
+        if (opts[b].orth_final && (rc = enqueue_cholqr2(&probs[b], pw, xds[b], tmp, st_eval, s)))
+            return rc;
+        HIPCHK(hipMemcpyAsync(&he[b], st_eval, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < nprob; ++b) {
+        if (!live[b]) continue;
+        if (opts[b].orth_final && he[b].info != 0) {
+            res[b].status = STF_E_CHOLESKY;
             worst = std::min(worst, (int)STF_E_CHOLESKY);
+            live[b] = 0;
             continue;
         }
+        const Ws& pw = pws[b];
         double* G64 = (P.dtype == STF_F64) ? pw.at<double>(pw.L.g[0]) : pw.at<double>(pw.L.g64);
-        if ((rc = enqueue_eval(&probs[b], pw, Xd, G64, s))) return rc;
-        if (P.dtype == STF_F32) launch_convert(STF_F32, Xd, STF_F64, X[b], (size_t)n * p, s);
-        HIPCHK(hipMemcpyAsync(&he, st_eval, sizeof(he), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        r.fval = he.red[0];
-        r.kkt_abs = he.red[1];
-        r.feas = he.red[2];
-        r.kkt_rel = (cur(b).kkt0 > 0.0) ? he.red[1] / cur(b).kkt0 : 0.0;
-        if (r.status == STF_OK && cur(b).kkt0 > 0.0 && !(he.red[1] <= opts[b].tol * cur(b).kkt0))
+        if ((rc = enqueue_eval(&probs[b], pw, xds[b], G64, s))) return rc;
+        if (P.dtype == STF_F32)
+            launch_convert(STF_F32, xds[b], STF_F64, X[b], (size_t)probs[b].n * probs[b].p, s);
+        HIPCHK(hipMemcpyAsync(&he[b], pw.at<DevState>(pw.L.state_eval), sizeof(DevState),
+                              hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < nprob; ++b) {
+        if (!live[b]) continue;
+        stf_result& r = res[b];
+        r.fval = he[b].red[0];
+        r.kkt_abs = he[b].red[1];
+        r.feas = he[b].red[2];
+        r.kkt_rel = (cur(b).kkt0 > 0.0) ? he[b].red[1] / cur(b).kkt0 : 0.0;
+        if (r.status == STF_OK && cur(b).kkt0 > 0.0 &&
+            !(he[b].red[1] <= opts[b].tol * cur(b).kkt0))
             r.status = STF_TOL_UNMET;
         // aggregate: the first error, else MAX_ITER, else TOL_UNMET, else OK
         if (worst >= 0 && r.status > 0)

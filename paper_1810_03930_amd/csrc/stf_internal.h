@@ -52,7 +52,7 @@ struct GradExtra {
     const double* rho;    // the density rho = diag(X X^T) (read when gamma != 0)
     double gamma;         // exchange weight
     int32_t block;        // 1D: order of the tridiagonal blocks (0: one block)
-    int32_t pad;
+    int32_t dense_prod;   // dense float32 A X: 0 = float32 MFMA, 1 = bf16, 3 = split bf16
 };
 
 // Internal status of a reduced-precision phase that reached switch_tol, and
@@ -217,7 +217,11 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
                    DevState* st, hipStream_t s, double* lam2 = nullptr);
-// per-tile partials of <B, S B - 2 (W - S M_L)> into part[((p+15)/16)^2]
+// per-tile partials of <B, S B - 2 (W - S M_L)> into part[kkt_partials(p)]
+// (64 x 64 float64 MFMA tiles of one product from p = kPPWide on, else
+// 16 x 16 tiles of two)
+constexpr int kPPWide = 128;
+int kkt_partials(int p);
 void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
                          double* part, int p, DevState* st, hipStream_t s);
 void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,

@@ -22,6 +22,8 @@
 #include "stf_internal.h"
 
 #include <math.h>
+
+#include <algorithm>
 #include <type_traits>
 
 namespace stf {
@@ -667,8 +669,8 @@ __global__ __launch_bounds__(256) void k_grad_line(const T* __restrict__ X, TO* 
 // read straight from global memory: for a fixed k the 16 lanes of a quarter
 // wave read 16 consecutive elements of one row, so every load is coalesced
 // for row-major Z and Y.
-template <typename T, int WM>
-__device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int zc0, int zlim,
+template <typename T, int WM, typename TZ = T>
+__device__ __forceinline__ void tn_mac(const TZ* __restrict__ Z, int64_t ldz, int zc0, int zlim,
                                        const T* __restrict__ Y, int64_t ldy, int yc0, int ylim,
                                        int64_t k0, int64_t k1,
                                        typename Mma<T>::acc (&acc)[WM][WM]) {
@@ -679,7 +681,7 @@ __device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int
         zok[i] = (zc0 + i * 16 + lr) < zlim;
         yok[i] = (yc0 + i * 16 + lr) < ylim;
     }
-    const T* zp = Z + zc0 + lr;
+    const TZ* zp = Z + zc0 + lr;
     const T* yp = Y + yc0 + lr;
     constexpr int U = 4;
     int64_t k = k0;
@@ -690,7 +692,7 @@ __device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int
             const int64_t row = k + u * 4 + lk;
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
-                a[u][i] = zok[i] ? zp[row * ldz + i * 16] : (T)0;
+                a[u][i] = zok[i] ? (T)zp[row * ldz + i * 16] : (T)0;
                 b[u][i] = yok[i] ? yp[row * ldy + i * 16] : (T)0;
             }
         }
@@ -707,7 +709,7 @@ __device__ __forceinline__ void tn_mac(const T* __restrict__ Z, int64_t ldz, int
         T a[WM], b[WM];
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
-            a[i] = (rok && zok[i]) ? zp[row * ldz + i * 16] : (T)0;
+            a[i] = (rok && zok[i]) ? (T)zp[row * ldz + i * 16] : (T)0;
             b[i] = (rok && yok[i]) ? yp[row * ldy + i * 16] : (T)0;
         }
 #pragma unroll
@@ -1706,9 +1708,11 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 }
 
 
-// Dense gradient G = A X = A^T X (A symmetric), written straight to G.
-template <typename T, int WM>
-__global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
+// Dense gradient G = A X = A^T X (A symmetric), written straight to G.  A may
+// be stored narrower than the arithmetic (TA = float with T = double: the
+// float64 form of a problem whose A is given in float32, widened exactly).
+template <typename T, int WM, typename TA = T>
+__global__ __launch_bounds__(256) void k_dense_grad(const TA* __restrict__ A,
                                                     const T* __restrict__ X, T* __restrict__ G,
                                                     int64_t n, int p, int nbp,
                                                     const double* __restrict__ glin,
@@ -1727,7 +1731,7 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
         for (int j = 0; j < WM; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
-    if (zc0 < n && yc0 < p) tn_mac<T, WM>(A, n, zc0, (int)n, X, p, yc0, p, 0, n, acc);
+    if (zc0 < n && yc0 < p) tn_mac<T, WM, TA>(A, n, zc0, (int)n, X, p, yc0, p, 0, n, acc);
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -1741,6 +1745,134 @@ __global__ __launch_bounds__(256) void k_dense_grad(const T* __restrict__ A,
                     const size_t idx = (size_t)r * p + c;
                     // the linear term of Problem 2 (if any)
                     G[idx] = glin ? (T)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
+                }
+            }
+}
+
+// Dense gradient G = A X (+ Glin) for float32 A and X on bf16 MFMA
+// (v_mfma_f32_16x16x32_bf16), the reduced-precision forms of the dense
+// Rayleigh-Ritz problem.  NPROD = 1: one product of the bf16 roundings;
+// NPROD = 3: the two-way split a = a_h + a_l of both operands and the three
+// products a_h b_h + a_h b_l + a_l b_h (a 16-bit mantissa for each operand).
+// A workgroup owns 128 rows x 512 columns of G (A is streamed once for p <=
+// 512; X, read by every row block, comes from L2), eight waves of 64 x 128
+// (4 x 8 MFMA tiles); K advances 32 at a time through LDS: A as [row][k], X
+// transposed as [col][k], both split to bf16 when staged, the next K step's
+// global loads issued before this step's products.
+constexpr int kDGM = 128, kDGN = 512, kDGK = 32, kDGP = kDGK + 8;
+template <int NPROD>
+__global__ __launch_bounds__(512) void k_dense_bf(const float* __restrict__ A,
+                                                  const float* __restrict__ X,
+                                                  float* __restrict__ G, int64_t n, int p,
+                                                  int ncb, const double* __restrict__ glin,
+                                                  const DevState* __restrict__ st) {
+    static_assert(NPROD == 1 || NPROD == 3, "one product or the three-product split");
+    if (st && st->done) return;
+    constexpr int NS = (NPROD == 1) ? 1 : 2;  // bf16 parts staged per operand
+    __shared__ __attribute__((aligned(16))) __bf16 La[NS][kDGM * kDGP];
+    __shared__ __attribute__((aligned(16))) __bf16 Lx[NS][kDGN * kDGP];
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int rb = lid / ncb, cb = lid % ncb;
+    const int64_t r0 = (int64_t)rb * kDGM;
+    const int c0 = cb * kDGN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 2, wj = wave & 3;   // 2 x 4 waves of 64 x 128
+    const int lr = lane & 15, g = lane >> 4;
+    // loaders: A row (tid >> 2), k offset 8 (tid & 3); X column tid, all 32 k
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int64_t arow = r0 + ar;
+    const bool aok = arow < n;
+    const int xc = c0 + tid;
+    const bool xok = xc < p;
+    float av[8], xv[kDGK];
+    auto load = [&](int64_t k0) {
+        const float* ap = A + (size_t)arow * n + k0 + ak;
+        if (aok && k0 + ak + 8 <= n && (n % 4) == 0) {
+            const float4 u = *(const float4*)ap;
+            const float4 w = *(const float4*)(ap + 4);
+            av[0] = u.x; av[1] = u.y; av[2] = u.z; av[3] = u.w;
+            av[4] = w.x; av[5] = w.y; av[6] = w.z; av[7] = w.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = (aok && k0 + ak + e < n) ? ap[e] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < kDGK; ++e)
+            xv[e] = (xok && k0 + e < n) ? X[(size_t)(k0 + e) * p + xc] : 0.f;
+    };
+    auto store = [&]() {
+        bf8 h, l;
+        if (NPROD == 1) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = (__bf16)av[e];
+            *(bf8*)&La[0][ar * kDGP + ak] = h;
+        } else {
+            split2(av, h, l);
+            *(bf8*)&La[0][ar * kDGP + ak] = h;
+            *(bf8*)&La[NS - 1][ar * kDGP + ak] = l;
+        }
+#pragma unroll
+        for (int q = 0; q < kDGK / 8; ++q) {
+            float t[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = xv[8 * q + e];
+            if (NPROD == 1) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = (__bf16)t[e];
+                *(bf8*)&Lx[0][tid * kDGP + 8 * q] = h;
+            } else {
+                split2(t, h, l);
+                *(bf8*)&Lx[0][tid * kDGP + 8 * q] = h;
+                *(bf8*)&Lx[NS - 1][tid * kDGP + 8 * q] = l;
+            }
+        }
+    };
+    f4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
+    load(0);
+    for (int64_t k0 = 0; k0 < n; k0 += kDGK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + kDGK < n) load(k0 + kDGK);
+        bf8 ah[4], al[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = (wi * 64 + i * 16 + lr) * kDGP + 8 * g;
+            ah[i] = *(const bf8*)&La[0][o];
+            if (NPROD == 3) al[i] = *(const bf8*)&La[NS - 1][o];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int o = (wj * 128 + j * 16 + lr) * kDGP + 8 * g;
+            const bf8 bh = *(const bf8*)&Lx[0][o];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh, acc[i][j]);
+            if (NPROD == 3) {
+                const bf8 bl = *(const bf8*)&Lx[NS - 1][o];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + wi * 64 + i * 16 + Mma<float>::row(g, q);
+                const int c = c0 + wj * 128 + j * 16 + lr;
+                if (r < n && c < p) {
+                    const size_t idx = (size_t)r * p + c;
+                    G[idx] = glin ? (float)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
                 }
             }
 }
@@ -2244,7 +2376,7 @@ __global__ __launch_bounds__(256) void k_pp_gemm2(const double* __restrict__ S,
 __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
-                                                 const double* __restrict__ pp_part,
+                                                 const double* __restrict__ pp_part, int npp,
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
@@ -2271,8 +2403,7 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
     if (ident) {
         for (int i = t; i < p; i += blockDim.x) v[5] += colpart[2 * i + 1];
         // tile partials of <B, S B - 2 (W - S M_L)> from the p x p product pass
-        const int nt = (p + 15) / 16;
-        for (int e = t; e < nt * nt; e += blockDim.x) v[6] += pp_part[e];
+        for (int e = t; e < npp; e += blockDim.x) v[6] += pp_part[e];
     }
 #pragma unroll
     for (int q = 0; q < 7; ++q) sr[q][t] = v[q];
@@ -2395,12 +2526,12 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
 __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ part_scal,
                                                  int nparts, const double* __restrict__ S,
-                                                 const double* __restrict__ pp_part,
+                                                 const double* __restrict__ pp_part, int npp,
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
                                                  DevState* __restrict__ st) {
-    body_stage2(prm, part_scal, nparts, S, pp_part, feas_part, colpart, ncolg, nu, p, st,
+    body_stage2(prm, part_scal, nparts, S, pp_part, npp, feas_part, colpart, ncolg, nu, p, st,
                 blockIdx.x, gridDim.x);
 }
 
@@ -2437,6 +2568,68 @@ __device__ __forceinline__ void body_update(T* __restrict__ X, double* __restric
         }
     }
 }
+// The same update without a master copy for rows that split into 16-byte
+// vectors: a lane holds 16 bytes of a row, a wave walks kUR rows at a time
+// with all their loads issued before the arithmetic, and the column scale
+// factors nu stay in registers (one 16-byte slice per 64 lanes).
+constexpr int kUR = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_v(T* __restrict__ X, const T* __restrict__ GL,
+                                                  int64_t n, int p,
+                                                  const double* __restrict__ nu,
+                                                  double* __restrict__ rho,
+                                                  const DevState* __restrict__ st) {
+    if (st->done) return;
+    constexpr int V = 16 / (int)sizeof(T);
+    typedef T tv __attribute__((ext_vector_type(V)));
+    const double eta = st->eta;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int c0 = 0; c0 < p; c0 += 64 * V) {
+        const int c = c0 + lane * V;
+        const bool on = c < p;
+        double nuv[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) nuv[e] = on ? nu[c + e] : 1.0;
+        for (int64_t r0 = wid * kUR; r0 < n; r0 += nw * kUR) {
+            tv xv[kUR], gv[kUR];
+#pragma unroll
+            for (int u = 0; u < kUR; ++u) {
+                const int64_t r = r0 + u;
+                if (on && r < n) {
+                    xv[u] = *(const tv*)(X + (size_t)r * p + c);
+                    gv[u] = *(const tv*)(GL + (size_t)r * p + c);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUR; ++u) {
+                const int64_t r = r0 + u;
+                double sq = 0.0;
+                if (on && r < n) {
+                    tv y;
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const double v = ((double)xv[u][e] - (double)gv[u][e] / eta) / nuv[e];
+                        y[e] = (T)v;
+                        sq += (double)y[e] * (double)y[e];
+                    }
+                    __builtin_nontemporal_store(y, (tv*)(X + (size_t)r * p + c));
+                }
+                if (rho) {
+                    sq = wave_sum(sq);
+                    if (lane == 0 && r < n) {
+                        if (c0 == 0)
+                            rho[r] = sq;
+                        else
+                            rho[r] += sq;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(T* __restrict__ X, double* __restrict__ Xm,
                                                 const T* __restrict__ GL,
@@ -2648,6 +2841,53 @@ __global__ __launch_bounds__(1024) void k_chol_inv_off(const double* __restrict_
         const int gr = i * kCB + r, gc = jb * kCB + c;
         if (gr < p && gc < p) Rinv[(size_t)gr * p + gc] = -o[q];
     }
+}
+
+// The p x p term of the float64 KKT identity with a single product for wide p:
+// <B, S B - 2 (W - S M_L)> = <B, S (B + 2 M_L)> - 2 <B, W>.  One 64 x 64 tile
+// (bx, by) of S (B + 2 M_L) per workgroup as sixteen 16 x 16 float64 MFMA
+// tiles over 64-deep LDS panels, then the tile's share of the inner product
+// reduced in the workgroup into part[by * gridDim.x + bx].
+__global__ __launch_bounds__(1024) void k_pp_kkt64(const double* __restrict__ S,
+                                                   const double* __restrict__ ML,
+                                                   const double* __restrict__ Bm,
+                                                   const double* __restrict__ W,
+                                                   double* __restrict__ part, int p,
+                                                   const DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double sa[kCB * kDP], sb[kCB * kDP];
+    __shared__ double sh[16];
+    const int bx = blockIdx.x, by = blockIdx.y, nt = gridDim.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < nt; ++kb) {
+        __syncthreads();
+        chol_load(sa, S, p, by, kb, false, false);
+        for (int e = threadIdx.x; e < kCB * kCB; e += blockDim.x) {
+            const int r = e / kCB, c = e % kCB;
+            const int gr = kb * kCB + r, gc = bx * kCB + c;
+            sb[r * kDP + c] = (gr < p && gc < p)
+                                  ? Bm[(size_t)gr * p + gc] + 2.0 * ML[(size_t)gr * p + gc]
+                                  : 0.0;
+        }
+        __syncthreads();
+        const d4 t = dst_tile(sa, sb, ti, tj, lr, lk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += t[q];
+    }
+    double c = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gr = by * kCB + 16 * ti + Mma<double>::row(lk, q);
+        const int gc = bx * kCB + 16 * tj + lr;
+        if (gr < p && gc < p) {
+            const size_t e = (size_t)gr * p + gc;
+            c += Bm[e] * (acc[q] - 2.0 * W[e]);
+        }
+    }
+    c = block_sum<16>(c, sh);
+    if (threadIdx.x == 0) part[by * nt + bx] = c;
 }
 
 // ---------------------------------------------------------- conversions ----
@@ -2879,7 +3119,8 @@ __global__ __launch_bounds__(256) void kb_colreduce(STF_BATCH_ARGS) {
 
 __global__ __launch_bounds__(1024) void kb_stage2(STF_BATCH_ARGS) {
     STF_BATCH_PROLOGUE
-    body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.T1, d.fpart,
+    const int npt = (d.p + 15) / 16;
+    body_stage2(d.prm, d.res_scal, d.res.nrb * d.res.ncb, d.S, d.T1, npt * npt, d.fpart,
                 d.colpart, col_groups(d.res.nrb), d.nu, d.p, d.st, 0, 1);
 }
 
@@ -3012,6 +3253,33 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
     const int p = prob->p;
     if (prob->kind == STF_KIND_DENSE) {
         const double* gl = ex.glin;
+        if (dtype == STF_F32 && ex.dense_prod != 0) {
+            // split-bf16 (or plain bf16) MFMA products, 128 x 512 tiles
+            const int ncb = (p + kDGN - 1) / kDGN;
+            const unsigned nwg = (unsigned)(((n + kDGM - 1) / kDGM) * ncb);
+            if (ex.dense_prod == 1)
+                k_dense_bf<1><<<nwg, 512, 0, s>>>((const float*)prob->A, (const float*)X,
+                                                  (float*)G, n, p, ncb, gl, st);
+            else
+                k_dense_bf<3><<<nwg, 512, 0, s>>>((const float*)prob->A, (const float*)X,
+                                                  (float*)G, n, p, ncb, gl, st);
+            return;
+        }
+        if (dtype == STF_F64 && prob->A_dtype == STF_F32) {
+            // float64 arithmetic on a float32 A (widened exactly on load)
+            if (p > 64) {
+                const int nbp = (p + 127) / 128;
+                const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
+                k_dense_grad<double, 4, float><<<nwg, 256, 0, s>>>(
+                    (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
+            } else {
+                const int nbp = (p + 31) / 32;
+                const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
+                k_dense_grad<double, 1, float><<<nwg, 256, 0, s>>>(
+                    (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
+            }
+            return;
+        }
         // WG tile 128 x 128 for wide p, 32 x 32 otherwise
         if (p > 64) {
             const int nbp = (p + 127) / 128;
@@ -3151,8 +3419,18 @@ void launch_stage1(const DevParams* prm, const double* S, const double* W, doubl
     k_stage1<<<p, 256, 0, s>>>(prm, S, W, Psi, ML, Bm, feas_part, p, st, lam2);
 }
 
+int kkt_partials(int p) {
+    const int t = (p >= kPPWide) ? (p + kCB - 1) / kCB : (p + 15) / 16;
+    return t * t;
+}
+
 void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,
                          double* part, int p, DevState* st, hipStream_t s) {
+    if (p >= kPPWide) {
+        const int t = (p + kCB - 1) / kCB;
+        k_pp_kkt64<<<dim3(t, t), 1024, 0, s>>>(S, ML, Bm, W, part, p, st);
+        return;
+    }
     dim3 grid((p + 15) / 16, (p + 15) / 16);
     k_pp_gemm2<<<grid, 256, 0, s>>>(S, ML, Bm, W, part, p, st);
 }
@@ -3228,12 +3506,25 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
                    hipStream_t s) {
     const int ng = col_groups(rp.nrb);
     k_colreduce<<<dim3((2 * p + 63) / 64, ng), 256, 0, s>>>(part_col, rp.nrb, p, colpart, st);
-    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, pp_part, feas_part,
+    k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, pp_part, kkt_partials(p),
+                                feas_part,
                                 colpart, ng, nu, p, st);
 }
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
                    double* rho, const DevState* st, hipStream_t s, double* Xm) {
+    if (!Xm && (p % (dtype == STF_F64 ? 2 : 4)) == 0) {
+        // 16-byte rows: kUR rows per wave, 16 waves of rows per CU round
+        int64_t g = (n + 4 * kUR - 1) / (4 * kUR);
+        g = std::min<int64_t>(g, 8192);
+        if (dtype == STF_F64)
+            k_update_v<double><<<(unsigned)g, 256, 0, s>>>((double*)X, (const double*)GL, n, p,
+                                                           nu, rho, st);
+        else
+            k_update_v<float><<<(unsigned)g, 256, 0, s>>>((float*)X, (const float*)GL, n, p, nu,
+                                                          rho, st);
+        return;
+    }
     if (dtype == STF_F64)
         k_update<double><<<grid_rows(n), 256, 0, s>>>((double*)X, nullptr, (const double*)GL, n,
                                                       p, nu, rho, st);

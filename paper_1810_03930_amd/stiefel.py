@@ -14,7 +14,8 @@ import torch
 
 from . import _lib as L
 
-_PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32, "mixed": L.PREC_MIXED}
+_PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32, "mixed": L.PREC_MIXED,
+         "mixed32": L.PREC_MIXED32}
 _ETA = {"const": L.ETA_CONST, "diff": L.ETA_DIFF, "bb1": L.ETA_BB1, "bb2": L.ETA_BB2,
         "abb": L.ETA_ABB}
 _KIND = {"stencil1d": L.KIND_STENCIL1D, "stencil3d": L.KIND_STENCIL3D, "dense": L.KIND_DENSE}

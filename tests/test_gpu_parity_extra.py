@@ -1,0 +1,260 @@
+"""Parity cases beyond the per-step and small-iterate tests:
+
+* the in-loop stop-test value (the float64 p x p identity of stage 2) against
+  the oracle's explicit ||G - X Psi||_F at every iteration k <= 50, with eta^k
+  and the feasibility: 1e-9 relative in the FP64 form, stated for MIXED;
+* 32 of the seeded 256 batched problems (the largest n and the largest p among
+  them) through the batched solver: FP64 iterates after 5 steps at 1e-10;
+* the dense quadratic (Problem 3 with A = (B + B^T)/(2 sqrt n) + 4 I) at
+  n = 2048, p = 128: FP64 iterates at 1e-10 and the converged objective against
+  the Ky Fan value (half the sum of the p smallest eigenvalues);
+* the MIXED form at p = 400 and 512 (the split-bf16 residual with M_L read
+  from global memory), error stated;
+* the 1D Kohn-Sham workload at full size (n = 20000, p = 100) after a fixed
+  number of steps in the FP32 and MIXED forms against the float64 oracle.
+Each comparison also bounds the largest elementwise error (maxrel).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.problems import OracleProblem
+from oracle import solver as O
+from paper_1810_03930_amd import stiefel as S
+from tests.helpers import maxrel, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(prob, x0, gopt, history=False):
+    dp = S.DeviceProblem.from_host(prob)
+    X = to_dev(x0, S.storage_dtype(gopt.precision))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    hist = torch.empty((gopt.max_iter + 1, 4), dtype=torch.float64, device="cuda") \
+        if history else None
+    with torch.cuda.stream(s):
+        res, x64, _ = S.solve(dp, X, gopt, want_x64=True, stream=s, history=hist)
+    torch.cuda.synchronize()
+    return res, to_np(X), (to_np(hist) if history else None)
+
+
+@pytest.mark.parametrize("which,precision", [("ks3d", "fp64"), ("quad", "fp64"),
+                                             ("ks3d", "mixed")])
+def test_stop_test_history_matches_oracle(which, precision):
+    if which == "ks3d":
+        prob, x0, _ = W.ks3d(grid=(12, 10, 9), p=10)
+        beta = 4.0
+    else:
+        prob, x0 = W.quad_tridiag(n=800, p=16)
+        beta = 1.0
+    k = 50
+    eta0 = beta + prob.s_bound
+    ref = O.solve(OracleProblem(prob), x0, O.Options(variant="pcal", beta=beta, eta0=eta0,
+                                                    tol=0.0, max_iter=k, orth_final=False,
+                                                    record_history=True))
+    g = S.SolveOptions(variant="pcal", precision=precision, beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=10)
+    res, _, hist = _solve(prob, x0, g, history=True)
+    kkt_ref = np.array(ref.history["kkt_rel"]) * ref.kkt0
+    feas_ref = np.array(ref.history["feas"])
+    eta_ref = np.array(ref.history["eta"])
+    e_kkt = np.max(np.abs(hist[:, 0] - kkt_ref) / kkt_ref)
+    # feasibility of these PCAL iterates is ~1e-9, near the rounding of the
+    # p x p Gram: compared with an absolute floor
+    d_feas = np.max(np.abs(hist[:, 1] - feas_ref) - 1e-9 * feas_ref)
+    e_eta = np.max(np.abs(hist[:k, 2] - eta_ref) / eta_ref)
+    print(f"{which} {precision}: stop-test value max rel err {e_kkt:.2e}, "
+          f"feasibility abs err beyond 1e-9 rel {d_feas:.2e} (max feas {feas_ref.max():.1e}), "
+          f"eta {e_eta:.2e}")
+    assert np.array_equal(hist[:, 3], np.arange(k + 1))
+    if precision == "fp64":
+        assert e_kkt <= 1e-9 and e_eta <= 1e-9 and d_feas <= 1e-13
+    else:
+        # the MIXED trajectory leaves the float64 one at the split-bf16 level
+        # and drifts (the iteration is chaotic): 0.8 % after 50 steps measured
+        assert e_kkt <= 5e-2 and e_eta <= 5e-2
+
+
+def test_batched_subset_of_the_256_problem_workload():
+    probs, x0s = W.batched_ks1d(nprob=256)
+    ns = np.array([p.n for p in probs])
+    ps = np.array([p.p for p in probs])
+    pick = sorted(set([int(np.argmax(ns)), int(np.argmax(ps)), int(np.argmin(ns)),
+                       int(np.argmin(ps))] + list(range(0, 256, 9))))[:32]
+    assert len(pick) == 32 and int(np.argmax(ns)) in pick and int(np.argmax(ps)) in pick
+    sub = [probs[i] for i in pick]
+    xs = [x0s[i] for i in pick]
+    k = 5
+    gl, refs = [], []
+    for prob, x0 in zip(sub, xs):
+        b = prob.alpha * prob.p * prob.n / 8.0 + 10.0
+        refs.append(O.solve(OracleProblem(prob), x0,
+                            O.Options(variant="pcal", beta=b, eta0=b + prob.s_bound, tol=0.0,
+                                      max_iter=k, orth_final=False, record_iterates=[k])))
+        gl.append(S.SolveOptions(variant="pcal", precision="fp64", beta=b,
+                                 eta0=b + prob.s_bound, tol=0.0, max_iter=k,
+                                 orth_final=False, check_every=16))
+    dps = [S.DeviceProblem.from_host(p) for p in sub]
+    Xs = [to_dev(x0, torch.float64) for x0 in xs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        res, rc, _ = S.solve_batched(dps, Xs, gl, stream=s)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for r, X, ref in zip(res, Xs, refs):
+        assert r["iters"] == k
+        Xg = to_np(X)
+        worst = max(worst, rel(Xg, ref.iterates[k]), maxrel(Xg, ref.iterates[k]))
+    print(f"32 batched problems (n up to {ns.max()}, p up to {ps.max()}): worst iterate "
+          f"error {worst:.2e}")
+    assert worst <= 1e-10
+
+
+def test_dense_pcal_iterates_and_ky_fan():
+    prob, x0 = W.dense_quadratic(n=2048, p=128, dtype=np.float64)
+    op = OracleProblem(prob)
+    # PCAL's beta above the p-th eigenvalue (A is positive definite; with beta
+    # below it coincident columns attract, a rank-deficient fixed point)
+    beta = prob.s_bound + 0.1
+    eta0 = beta + prob.s_bound
+    k = 20
+    ref = O.solve(op, x0, O.Options(variant="pcal", beta=beta, eta0=eta0, tol=0.0,
+                                    max_iter=k, orth_final=False, record_iterates=[k]))
+    g = S.SolveOptions(variant="pcal", precision="fp64", beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=10)
+    res, X, _ = _solve(prob, x0, g)
+    assert res["iters"] == k
+    assert rel(X, ref.iterates[k]) <= 1e-10 and maxrel(X, ref.iterates[k]) <= 1e-10
+    g = S.SolveOptions(variant="pcal", precision="fp64", beta=beta, eta0=eta0, tol=1e-9,
+                       max_iter=5000, orth_final=True, check_every=50)
+    res, X, _ = _solve(prob, x0, g)
+    fstar = 0.5 * np.sum(np.linalg.eigvalsh(prob.A)[:prob.p])
+    print(f"dense n=2048 p=128: {res['iters']} iterations, f - f* = {res['fval'] - fstar:.2e}")
+    assert res["rc"] == 0
+    assert abs(res["fval"] - fstar) <= 1e-10 * abs(fstar)
+
+
+@pytest.mark.parametrize("p", [400, 512])
+def test_mixed_wide_p(p):
+    prob, x0, _ = W.ks3d(grid=(16, 16, 16), p=p)
+    k = 5
+    beta = 4.0
+    eta0 = beta + prob.s_bound
+    ref = O.solve(OracleProblem(prob), x0, O.Options(variant="pcal", beta=beta, eta0=eta0,
+                                                    tol=0.0, max_iter=k, orth_final=False,
+                                                    record_iterates=[k]))
+    g = S.SolveOptions(variant="pcal", precision="mixed", beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=5)
+    res, X, _ = _solve(prob, x0, g)
+    e, em = rel(X, ref.iterates[k]), maxrel(X, ref.iterates[k])
+    print(f"mixed p={p}: iterate error after {k} steps {e:.2e} (elementwise {em:.2e})")
+    assert res["iters"] == k
+    assert e <= 1e-5 * k and em <= 1e-5 * k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_ks1d_full_size_error_stated(precision):
+    """The 1D Kohn-Sham workload (n = 20000, p = 100, beta = 100) after 20
+    steps: the float32 forms against the float64 oracle."""
+    prob, x0 = W.ks1d()
+    beta = 100.0
+    eta0 = beta + prob.s_bound
+    k = 20
+    ref = O.solve(OracleProblem(prob), x0, O.Options(variant="pcal", beta=beta, eta0=eta0,
+                                                    tol=0.0, max_iter=k, orth_final=False,
+                                                    record_iterates=[k]))
+    g = S.SolveOptions(variant="pcal", precision=precision, beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=10)
+    res, X, _ = _solve(prob, x0, g)
+    e, em = rel(X, ref.iterates[k]), maxrel(X, ref.iterates[k])
+    print(f"{precision} n=20000 p=100: iterate error after {k} steps {e:.2e} "
+          f"(elementwise {em:.2e})")
+    assert res["iters"] == k
+    # the stiff 1D Hartree term (phi ~ p n / 8) magnifies the float32 rounding:
+    # measured 7e-5 (FP32) and 3.5e-4 (MIXED)
+    assert e <= 1e-3 and em <= 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed"])
+def test_dense_float32_operator_forms(precision):
+    """The dense problem with its A given in float32 (the dense workload's
+    storage): the float64 form widens A exactly and matches the oracle (which
+    works on the same float32 values in float64) at 1e-10; the float32 MFMA
+    form and the split-bf16 form (three bf16 products of A X) within their
+    stated errors after 5 steps."""
+    prob, x0 = W.dense_quadratic(n=1536, p=96, dtype=np.float32)
+    beta = prob.s_bound + 0.1
+    eta0 = beta + prob.s_bound
+    k = 5
+    ref = O.solve(OracleProblem(prob), x0, O.Options(variant="pcal", beta=beta, eta0=eta0,
+                                                    tol=0.0, max_iter=k, orth_final=False,
+                                                    record_iterates=[k]))
+    g = S.SolveOptions(variant="pcal", precision=precision, beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=5)
+    dp = S.DeviceProblem.from_host(prob)
+    X = to_dev(x0, S.storage_dtype(precision))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        res, _, _ = S.solve(dp, X, g, stream=s)
+    torch.cuda.synchronize()
+    Xg = to_np(X)
+    e, em = rel(Xg, ref.iterates[k]), maxrel(Xg, ref.iterates[k])
+    print(f"dense float32 A, {precision}: iterate error after {k} steps {e:.2e} "
+          f"(elementwise {em:.2e})")
+    assert res["iters"] == k
+    bound = 1e-10 if precision == "fp64" else 1e-5 * k
+    assert e <= bound and em <= 10 * bound
+
+
+def test_dense_mixed_hands_over_and_reaches_ky_fan():
+    """The split-bf16 dense form hands over to float64 (A widened exactly) and
+    reaches the Ky Fan value of the float32-valued A."""
+    prob, x0 = W.dense_quadratic(n=1536, p=96, dtype=np.float32)
+    beta = prob.s_bound + 0.1
+    g = S.SolveOptions(variant="pcal", precision="mixed", beta=beta, eta0=beta + prob.s_bound,
+                       tol=1e-9, max_iter=6000, orth_final=True, check_every=50,
+                       switch_tol=1e-4)
+    dp = S.DeviceProblem.from_host(prob)
+    X = to_dev(x0, torch.float32)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        res, _, _ = S.solve(dp, X, g, stream=s)
+    torch.cuda.synchronize()
+    fstar = 0.5 * np.sum(np.linalg.eigvalsh(prob.A.astype(np.float64))[:prob.p])
+    print(f"dense mixed: hand-over at {res['switch_iter']}, {res['iters']} iterations, "
+          f"f - f* = {res['fval'] - fstar:.2e}, kkt_rel {res['kkt_rel']:.2e}")
+    assert res["rc"] == 0 and res["switch_iter"] > 0
+    assert abs(res["fval"] - fstar) <= 1e-10 * abs(fstar)
+
+
+@pytest.mark.parametrize("k", [1, 5, 50])
+def test_mixed32_iterates_and_hand_over(k):
+    """MIXED32 (no float64 master): iterates within the MIXED bound after k
+    steps, and a solve handed over at 1e-4 reaches 1e-9 at the oracle's
+    minimum."""
+    prob, x0, _ = W.ks3d(grid=(12, 10, 9), p=10)
+    beta = 4.0
+    eta0 = beta + prob.s_bound
+    op = OracleProblem(prob)
+    ref = O.solve(op, x0, O.Options(variant="pcal", beta=beta, eta0=eta0, tol=0.0,
+                                    max_iter=k, orth_final=False, record_iterates=[k]))
+    g = S.SolveOptions(variant="pcal", precision="mixed32", beta=beta, eta0=eta0, tol=0.0,
+                       max_iter=k, orth_final=False, check_every=10)
+    res, X, _ = _solve(prob, x0, g)
+    e = rel(X, ref.iterates[k])
+    print(f"mixed32: iterate error after {k} steps {e:.2e}")
+    assert res["iters"] == k and e <= 1e-5 * k
+    if k == 50:
+        g = S.SolveOptions(variant="pcal", precision="mixed32", beta=beta, eta0=eta0,
+                           tol=1e-9, max_iter=3000, orth_final=True, check_every=50,
+                           switch_tol=1e-4)
+        res, X, _ = _solve(prob, x0, g)
+        ref = O.solve(op, x0, O.Options(variant="pcal", beta=beta, eta0=eta0, tol=1e-9,
+                                        max_iter=3000))
+        assert res["rc"] == 0 and 0 < res["switch_iter"] < res["iters"]
+        assert abs(res["fval"] - ref.f) <= 1e-8 * abs(ref.f)
