@@ -4,16 +4,18 @@ One "step" is one PCAL iteration (Algorithm 3): Hartree solve, gradient,
 Gram products, p x p multiplier stage, residual / step-size pass, update.
 
 Reported (one JSON line on stdout):
-  value        PCAL iterations/s of the fast form (mixed: split-bf16 MFMA
-               products, float32 storage, float64 master iterate), inputs
+  value        PCAL iterations/s of the fast form (mixed32: split-bf16 MFMA
+               products, float32 storage, no float64 master), inputs
                resident in HBM, over exactly `--steps` iterations after
                `--warmup` untimed ones (device events around the loop)
   forms        per form (fp64 and the fast form): iterations/s, per-kernel
                average times, time to relative KKT <= 1e-6 (loop +
                CholeskyQR2 + float64 check; the fast form hands over to
-               float64 at relative KKT 2e-5), iterations to that point, f,
-               KKT and feasibility at the end
-  speedup      time-to-KKT of the fp64 form / that of the fast form
+               float64 at relative KKT 1e-4) from 15 seeded starts, the
+               median and the reached/total count, f, KKT and feasibility
+  speedup      median time-to-KKT of the fp64 form / that of the fast form
+  result_error_vs_fp64  per reduced-precision form: f, KKT, feasibility and
+               the subspace distance of its returned point against fp64's
   roofline     the dominant kernel of the fast form's timed steps
   cpu_baseline the float64 oracle on this host's cores, on a bounded sample
 """
@@ -36,7 +38,7 @@ P = 256
 ALPHA = 1.0
 BETA = 4.0          # PCAL penalty for the 3D KS workload (above its p-th eigenvalue)
 TOL = 1e-6
-SWITCH_TOL = 1e-5   # relative KKT at which the fast form continues in float64
+SWITCH_TOL = 1e-4   # relative KKT at which the fast form continues in float64
 BATCH_SWITCH_TOL = 1e-3
 MAX_ITER = 6000
 HBM_PEAK_GBS = 8000.0
@@ -199,11 +201,11 @@ KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gr
                ("mixed", "update"): "body_update",
                ("mixed32", "residual"): "body_residual_bf6_lds",
                ("mixed32", "gram"): "body_gram_bf3_lds", ("mixed32", "grad"): "body_grad_line",
-               ("mixed32", "update"): "body_update"}
+               ("mixed32", "update"): "k_update_v"}
 # kernels that differ from KERNEL_NAMES in one form (the 3D gradient with a
 # float32 G walks runs of rows)
 KERNEL_NAMES_FORM = {("mixed", "grad"): "k_grad_line", ("fp32", "grad"): "k_grad_line",
-                     ("mixed32", "grad"): "k_grad_line"}
+                     ("mixed32", "grad"): "k_grad_line", ("mixed32", "update"): "k_update_v"}
 
 
 def body_digest(name):
@@ -214,7 +216,8 @@ def body_digest(name):
     src = os.path.join(ROOT, "paper_1810_03930_amd", "csrc", "stf_kernels.hip")
     with open(src) as f:
         text = f.read()
-    m = re.search(r"^__device__ __forceinline__ void " + re.escape(name) + r"\(", text, re.M)
+    m = re.search(r"^(__device__ __forceinline__|__global__ __launch_bounds__\(\d+\)) void "
+                  + re.escape(name) + r"\(", text, re.M)
     if not m:
         return None
     end = text.find("\n}\n", m.start())
@@ -313,7 +316,9 @@ def batched_main(args, torch, S, W):
 
     stream = torch.cuda.Stream()
     out = {}
-    for prec in ["fp64", args.fast_form]:
+    # the batched solver has the float64, FP32 and MIXED kernel sets
+    fast = "mixed" if args.fast_form == "mixed32" else args.fast_form
+    for prec in ["fp64", fast]:
         dt = S.storage_dtype(prec)
         Xs = [torch.as_tensor(x0, device="cuda").to(dt).contiguous() for x0 in x0s]
         x0d = [X.clone() for X in Xs]
@@ -364,14 +369,15 @@ def batched_main(args, torch, S, W):
                      "worst_kkt_rel": max(r["kkt_rel"] for r in rk)}
         log(f"batched {prec}: {json.dumps(out[prec])}")
         del Xs, x0d, ws
-    fast = out[args.fast_form]
+    fast_form = fast
+    fast = out[fast_form]
     line = {
         "metric": "batched PCAL aggregate iters/s, 256 x 1D KS (uneven n, p, alpha)",
         "value": fast["aggregate_iters_per_s"], "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": fast["ms_per_batch_iter"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": FORM_DTYPE[args.fast_form],
+        "dtype": FORM_DTYPE[fast_form],
         "data": "synthetic",
         "config": {"workload": "256 x 1D Kohn-Sham-shaped PCAL, n~U[1000,20000], "
                                "p~U[8,128], alpha~U[0.5,2], beta = alpha p n / 8 + 10",
@@ -603,7 +609,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fast-form", default="mixed", choices=["fp32", "mixed", "mixed32"])
+    ap.add_argument("--fast-form", default="mixed32", choices=["fp32", "mixed", "mixed32"])
     ap.add_argument("--extra-forms", default="",
                     help="comma-separated further forms to measure beside fp64 and the fast form")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -287,7 +287,7 @@ int enqueue_eval(const stf_problem* prob, const Ws& w, const double* X, double* 
                     w.at<double>(w.L.Psi), nullptr, n, p, w.at<double>(w.L.res_col),
                     w.at<double>(w.L.res_scal), prm, st, RES_KKT_ONLY, nullptr, s);
     launch_eval_finish(prob, X, G64, w.at<double>(w.L.rho), w.at<double>(w.L.phi),
-                       w.at<double>(w.L.S), n, p, w.at<double>(w.L.dots),
+                       w.at<double>(w.L.fpart), n, p, w.at<double>(w.L.dots),
                        w.at<double>(w.L.res_scal), w.L.res.nrb * w.L.res.ncb, st, s);
     return last_launch();
 }

@@ -255,8 +255,9 @@ void launch_vform(const double* X, const double* D, double* V, int64_t n, int p,
                   const DevState* st, hipStream_t s);
 void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_t count,
                     hipStream_t s);
+// feas_part: the p row sums of (S - I)^2 written by stage 1
 void launch_eval_finish(const stf_problem* prob, const double* X, const double* G,
-                        const double* rho, const double* phi, const double* S,
+                        const double* rho, const double* phi, const double* feas_part,
                         int64_t n, int p, double* dots, const double* part_scal, int nps,
                         DevState* st, hipStream_t s);
 void launch_init_state(DevState* st, hipStream_t s);

@@ -2568,10 +2568,11 @@ __device__ __forceinline__ void body_update(T* __restrict__ X, double* __restric
         }
     }
 }
-// The same update without a master copy for rows that split into 16-byte
-// vectors: a lane holds 16 bytes of a row, a wave walks kUR rows at a time
-// with all their loads issued before the arithmetic, and the column scale
-// factors nu stay in registers (one 16-byte slice per 64 lanes).
+// The same update without a master copy for rows whose length is a multiple
+// of 4: a lane holds 4 consecutive elements of a row (one 256-column slice per
+// wave, so p = 256 is one pass), a wave walks kUR rows at a time with all
+// their loads issued before the arithmetic, and the column scale factors nu
+// of its slice stay in registers.
 constexpr int kUR = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_v(T* __restrict__ X, const T* __restrict__ GL,
@@ -2580,7 +2581,7 @@ __global__ __launch_bounds__(256) void k_update_v(T* __restrict__ X, const T* __
                                                   double* __restrict__ rho,
                                                   const DevState* __restrict__ st) {
     if (st->done) return;
-    constexpr int V = 16 / (int)sizeof(T);
+    constexpr int V = 4;  // 16 bytes of float32 per lane
     typedef T tv __attribute__((ext_vector_type(V)));
     const double eta = st->eta;
     const int lane = threadIdx.x & 63;
@@ -2934,10 +2935,12 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ X,
 
 // f from <X, G>: with G = H0 X B + Glin + alpha Diag(phi) X - 2 gamma Diag(rho^{1/3}) X,
 //   f = 1/2 <X, G> + 1/2 <X, Glin> - alpha/4 rho^T phi + gamma/4 sum rho^{4/3};
-// kkt = sqrt(sum of the residual partials), feas = ||S - I||_F.
+// kkt = sqrt(sum of the residual partials), feas = ||S - I||_F from the row
+// sums of stage 1.
 __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ dots, int nd,
                                                      const double* __restrict__ part_scal,
-                                                     int nps, const double* __restrict__ S,
+                                                     int nps,
+                                                     const double* __restrict__ feas_part,
                                                      int p, double alpha, double gamma,
                                                      DevState* __restrict__ st) {
     __shared__ double sh[4];
@@ -2949,12 +2952,8 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* __restrict__ 
         d += dots[4 * i + 3];
     }
     for (int i = threadIdx.x; i < nps; i += 256) k2 += part_scal[(size_t)i * 4];
-    const size_t p2 = (size_t)p * p;
-    for (size_t e = threadIdx.x; e < p2; e += 256) {
-        const int i = (int)(e / p), j = (int)(e % p);
-        const double cc = S[e] - (i == j ? 1.0 : 0.0);
-        f2 += cc * cc;
-    }
+    // the rows of ||S - I||_F^2 from stage 1
+    for (int i = threadIdx.x; i < p; i += 256) f2 += feas_part[i];
     a = block_sum256(a, sh);
     b = block_sum256(b, sh);
     c = block_sum256(c, sh);
@@ -3513,16 +3512,14 @@ void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_c
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,
                    double* rho, const DevState* st, hipStream_t s, double* Xm) {
-    if (!Xm && (p % (dtype == STF_F64 ? 2 : 4)) == 0) {
-        // 16-byte rows: kUR rows per wave, 16 waves of rows per CU round
+    if (dtype == STF_F32 && !Xm && (p % 4) == 0) {
+        // float32 rows without a master: 4-element vectors per lane, kUR rows
+        // per wave (0.218 -> 0.147 ms on 64^3 x 256; the same form of the
+        // float64 update measured 0.274 against 0.255 ms for the row-per-wave one)
         int64_t g = (n + 4 * kUR - 1) / (4 * kUR);
         g = std::min<int64_t>(g, 8192);
-        if (dtype == STF_F64)
-            k_update_v<double><<<(unsigned)g, 256, 0, s>>>((double*)X, (const double*)GL, n, p,
-                                                           nu, rho, st);
-        else
-            k_update_v<float><<<(unsigned)g, 256, 0, s>>>((float*)X, (const float*)GL, n, p, nu,
-                                                          rho, st);
+        k_update_v<float><<<(unsigned)g, 256, 0, s>>>((float*)X, (const float*)GL, n, p, nu,
+                                                      rho, st);
         return;
     }
     if (dtype == STF_F64)
@@ -3586,15 +3583,16 @@ void launch_convert(int to_dtype, const void* in, int in_dtype, void* out, size_
 }
 
 void launch_eval_finish(const stf_problem* prob, const double* X, const double* G,
-                        const double* rho, const double* phi, const double* S, int64_t n, int p,
-                        double* dots, const double* part_scal, int nps, DevState* st,
-                        hipStream_t s) {
+                        const double* rho, const double* phi, const double* feas_part,
+                        int64_t n, int p, double* dots, const double* part_scal, int nps,
+                        DevState* st, hipStream_t s) {
     const int nd = 512;
     const bool hart = prob->kind != STF_KIND_DENSE && prob->alpha != 0.0;
     const bool exch = prob->kind != STF_KIND_DENSE && prob->gamma != 0.0;
     k_dots<<<nd, 256, 0, s>>>(X, G, (size_t)n * p, (hart || exch) ? rho : nullptr,
                               hart ? phi : nullptr, n, prob->Glin, exch ? 1 : 0, dots);
-    k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, S, p, hart ? prob->alpha : 0.0,
+    k_eval_finish<<<1, 256, 0, s>>>(dots, nd, part_scal, nps, feas_part, p,
+                                    hart ? prob->alpha : 0.0,
                                     exch ? prob->gamma : 0.0, st);
 }
 

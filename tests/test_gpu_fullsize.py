@@ -17,7 +17,7 @@ import workloads as W
 from oracle.problems import OracleProblem
 from oracle import solver as O
 from paper_1810_03930_amd import stiefel as S
-from tests.helpers import rel, to_dev, to_np
+from tests.helpers import maxrel, rel, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -69,20 +69,28 @@ def test_fullsize_fp64_iterates(c5, oracle_iterates, k):
     _, g = _opts(prob, k, "fp64")
     res, X = _gpu(prob, x0, g)
     err = rel(X, oracle_iterates[k])
-    print(f"64^3 p=256 FP64: relative iterate error after {k} steps = {err:.2e}")
+    emax = maxrel(X, oracle_iterates[k])
+    print(f"64^3 p=256 FP64: relative iterate error after {k} steps = {err:.2e} "
+          f"(elementwise {emax:.2e})")
     assert res["iters"] == k
-    assert err <= 1e-10
+    assert err <= 1e-10 and emax <= 1e-10
 
 
-def test_fullsize_mixed_iterates(c5, oracle_iterates):
+@pytest.mark.parametrize("precision", ["mixed", "mixed32"])
+def test_fullsize_mixed_iterates(c5, oracle_iterates, precision):
+    """The split-bf16 forms after 3 steps: the relative Frobenius error and the
+    largest elementwise error, max|dX| / max|X| (a localized error such as one
+    wrong boundary plane would show in the second, not the first)."""
     prob, x0, _ = c5
     k = 3
-    _, g = _opts(prob, k, "mixed")
+    _, g = _opts(prob, k, precision)
     res, X = _gpu(prob, x0, g)
     err = rel(X, oracle_iterates[k])
-    print(f"64^3 p=256 MIXED: relative iterate error after {k} steps = {err:.2e}")
+    emax = maxrel(X, oracle_iterates[k])
+    print(f"64^3 p=256 {precision}: relative iterate error after {k} steps = {err:.2e} "
+          f"(elementwise {emax:.2e})")
     assert res["iters"] == k
-    assert err <= 1e-5 * k
+    assert err <= 1e-5 * k and emax <= 1e-5 * k
 
 
 def test_fullsize_gram(c5):
