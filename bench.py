@@ -45,13 +45,32 @@ HBM_PEAK_GBS = 8000.0
 FORM_DTYPE = {"fp32": "f32", "mixed": "bf16x3/bf16x6 MFMA, f32 storage, f64 master",
               "mixed32": "bf16x3/bf16x6 MFMA, f32 storage, no f64 master"}
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "mixed_bf16": 2500.0}
+# --single-pass: the lagged Barzilai-Borwein pair (as printed in Section 5.1)
+# with eta^k and nu^k found before the row-block pass, which then writes
+# X^{k+1} itself (options.fused; the forms that have it)
+SINGLE_PASS = False
+SINGLE_PASS_FORMS = ("fp64", "mixed32")
+
+
+def form_options(precision):
+    """Step-rule indexing and pass structure of a form's solves."""
+    if SINGLE_PASS:
+        return {"bb_index": "lagged", "fused": precision in SINGLE_PASS_FORMS}
+    return {"bb_index": "standard", "fused": False}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_algorithmic(name, n, p, precision):
+def rho_slots(p, precision):
+    """Row partials of rho written by the single-pass residual: one per
+    64-column block (split bf16) or per 32 columns (float64)."""
+    ncb = (p + 63) // 64
+    return 2 * ncb if precision == "fp64" else ncb
+
+
+def kernel_algorithmic(name, n, p, precision, fused=False):
     """Algorithmic (bytes, flops) of one launch of a kernel per iteration.
 
     Bytes count each operand read or written once (neighbour rows of the
@@ -66,7 +85,11 @@ def kernel_algorithmic(name, n, p, precision):
     if name == "gram":        # read X, G: upper halves of S and W (W = X^T H X is symmetric)
         return 2 * npe * s, 2.0 * n * p * (p + 1)
     if name == "residual":    # read X, G, gradL^{k-1}; write gradL over G: G - X M_L
+        if fused:             # + X^{k+1} and the row partials of rho
+            return 5 * npe * s + 8.0 * n * rho_slots(p, precision), 2.0 * n * p * p + 4.0 * npe
         return 4 * npe * s, 2.0 * n * p * p
+    if name == "update" and fused:   # the row partials of rho summed: read slots x n, write n
+        return 8.0 * n * (rho_slots(p, precision) + 1), float(n) * rho_slots(p, precision)
     if name == "update":      # read X (or the master), gradL; write X (+ master), rho
         if precision == "fp64":
             by = 3 * npe * 8
@@ -85,7 +108,7 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
     dt = S.storage_dtype(precision)
     eta0 = BETA + dp.s_bound
     common = dict(variant="pcal", mult="psi_phi", eta_rule="abb", precision=precision,
-                  beta=BETA, eta0=eta0)
+                  beta=BETA, eta0=eta0, **form_options(precision))
     stream = torch.cuda.Stream()
     ws = S.alloc_workspace(dp, S.SolveOptions(**common))
     X = torch.empty((dp.n, dp.p), dtype=dt, device="cuda")
@@ -187,6 +210,7 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "reached_per_start": reached,
         "reached": f"{sum(reached)}/{len(reached)}",
         "time_to_kkt_s_median": med if np.isfinite(med) else None,
+        **form_options(precision),
     }
     return out, x_first
 
@@ -243,7 +267,8 @@ def roofline_for(form, precision, n, p):
     ka = {k: v for k, v in form["kernel_avg_ms"].items() if k in KERNEL_NAMES}
     name = max(ka, key=lambda k: ka[k])
     ms = ka[name]
-    by, fl = kernel_algorithmic(name, n, p, precision)
+    fused = form_options(precision)["fused"]
+    by, fl = kernel_algorithmic(name, n, p, precision, fused)
     # the arithmetic that bounds each kernel: the float64 MFMA/vector peak, or
     # the split-bf16 products (3 for the Gram, 6 for the residual) at bf16 peak
     mults = {"gram": 3.0, "residual": 6.0}
@@ -257,8 +282,11 @@ def roofline_for(form, precision, n, p):
         t_mma = fl * mults.get(name, 0.0) / (PEAK_TFLOPS["mixed_bf16"] * 1e12)
         peak_f = PEAK_TFLOPS["mixed_bf16"] / mults.get(name, 1.0)
     t_mem = by / (HBM_PEAK_GBS * 1e9)
-    traffic = traffic_for(name, precision)
-    common = {"kernel": KERNEL_NAMES_FORM.get((precision, name), KERNEL_NAMES[name]),
+    traffic = None if fused else traffic_for(name, precision)
+    kname = KERNEL_NAMES_FORM.get((precision, name), KERNEL_NAMES[name])
+    if fused and name == "update":
+        kname = "k_rho_reduce"
+    common = {"kernel": kname,
               "group": name, "avg_launch_ms": ms,
               "algorithmic_bytes": by, "algorithmic_flops": fl,
               "traffic": traffic}
@@ -456,16 +484,23 @@ def parallel_main(args, torch, S, W):
             prob, x0 = gen(n=n, p=p)
             dp = S.DeviceProblem.from_host(prob)
             for solver in ["pcal", "moptqr"]:
-                beta = 1.0 if solver == "pcal" else 0.0
-                opts = S.SolveOptions(variant=solver, mult="psi_phi" if solver == "pcal" else "psi",
-                                      eta_rule="abb", precision="fp64", beta=beta,
-                                      eta0=beta + prob.s_bound, tol=1e-8, max_iter=1000,
-                                      orth_final=True, check_every=50, use_graph=True)
-                log(f"parallel {name} n={n} p={p} {solver}")
-                r = _timed_and_profiled(dp, x0, opts, args.steps, args.warmup, S, torch)
-                r.update({"problem": name, "n": n, "p": p, "solver": solver})
-                log(json.dumps(r))
-                rows.append(r)
+                # PCAL takes the paper's beta = 1; where that diverges (the
+                # p-th eigenvalue of the operator is at or above beta), once
+                # more with beta above the spectrum bound
+                betas = [1.0, prob.s_bound + 1.0] if solver == "pcal" else [0.0]
+                for beta in betas:
+                    opts = S.SolveOptions(variant=solver,
+                                          mult="psi_phi" if solver == "pcal" else "psi",
+                                          eta_rule="abb", precision="fp64", beta=beta,
+                                          eta0=beta + prob.s_bound, tol=1e-8, max_iter=1000,
+                                          orth_final=True, check_every=50, use_graph=True)
+                    log(f"parallel {name} n={n} p={p} {solver} beta={beta}")
+                    r = _timed_and_profiled(dp, x0, opts, args.steps, args.warmup, S, torch)
+                    r.update({"problem": name, "n": n, "p": p, "solver": solver, "beta": beta})
+                    log(json.dumps(r))
+                    rows.append(r)
+                    if r["to_tol"]["rc"] != -2:
+                        break
             del dp
             torch.cuda.empty_cache()
     print(json.dumps({"metric": "Section 5.5 workloads: PCAL vs MOptQR, float64, one GPU",
@@ -633,10 +668,15 @@ def main():
     ap.add_argument("--dense-max-iter", type=int, default=3000)
     ap.add_argument("--sweep", action="store_true",
                     help="run the Section 5.3 step-size / beta / dual-ascent studies")
+    ap.add_argument("--single-pass", action="store_true",
+                    help="lagged Barzilai-Borwein pair and the single-pass iteration "
+                         "(options.fused) in the forms that have it (fp64, mixed32)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times: the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    global SINGLE_PASS
+    SINGLE_PASS = bool(args.single_pass)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -723,7 +763,9 @@ def main():
         "config": {"workload": "3D Kohn-Sham-shaped PCAL, 7-point Dirichlet Laplacian on a "
                                "64^3 grid + Diag(V), V~U(0,1), alpha=1, beta=4, ABB steps",
                    "n": prob.n, "p": P, "grid": list(GRID), "tol_rel_kkt": TOL,
-                   "fast_form": args.fast_form, "switch_tol": SWITCH_TOL},
+                   "fast_form": args.fast_form, "switch_tol": SWITCH_TOL,
+                   "bb_index": form_options(args.fast_form)["bb_index"],
+                   "single_pass": form_options(args.fast_form)["fused"]},
         "time_to_kkt_s": None if args.skip_ttk else
         {"fp64": base["time_to_kkt_s"], args.fast_form: fast["time_to_kkt_s"]},
         "time_to_kkt_s_median": None if args.skip_ttk else

@@ -176,6 +176,18 @@ typedef struct stf_problem {
  * profile     : 1 = bracket every kernel group of every iteration with HIP
  *               events (no graph) and report per-group times in
  *               stf_result.kernel_ms / prof_iters
+ * fused       : 1 = single-pass iteration: eta^k and the PCAL column norms
+ *               nu^k are found before the row-block pass from p x p float64
+ *               quantities (the lagged Barzilai-Borwein pair of Section 5.1,
+ *               and ||X_c - gradL_c / eta||^2 expanded through X^T X, X^T G,
+ *               M_L and the column sums of G^2 taken with the Gram products),
+ *               so that the pass that forms gradL^k also writes X^{k+1} and
+ *               its row sums of squares: one read of X, G and gradL^{k-1} per
+ *               iteration instead of two.  Needs bb_index = STF_BB_LAGGED,
+ *               eta_rule other than STF_ETA_DIFF, PLAM or PCAL, p > 64, and
+ *               precision STF_PREC_FP64 or STF_PREC_MIXED32 (the latter with
+ *               p <= 384); else STF_E_UNSUPPORTED.  The iterates are those of
+ *               the two-pass form up to rounding.  0 = two passes.
  * feas_blowup : divergence threshold on ||X^T X - I||_F (e.g. 1e3)
  * switch_tol  : STF_PREC_FP32 / STF_PREC_MIXED only; 0 = never.  Once the
  *               stop test of iteration k finds ||G - X Psi||_F <= switch_tol
@@ -205,7 +217,7 @@ typedef struct stf_options {
     int32_t check_every;
     int32_t use_graph;
     int32_t profile;
-    int32_t reserved;
+    int32_t fused;
     double beta;
     double eta0;
     double eta_const;
@@ -232,7 +244,10 @@ typedef struct stf_options {
  *           HARTREE brackets the six sine-transform passes; STAGE1 the
  *           reduction of the Gram partials, the p x p stage, the p x p KKT
  *           products (and the split of M_L in the mixed form); STAGE2 the
- *           column-dot reduction and the step-size / stop stage
+ *           column-dot reduction and the step-size / stop stage.  In the
+ *           single-pass form (fused) STAGE1 also holds the S M_L product and
+ *           the eta / nu stage, and UPDATE brackets the reduction of the row
+ *           sums of squares into rho (no launch when no term needs rho)
  * switch_iter : iteration at which a float32 / mixed solve continued in
  *           float64 (see switch_tol), or -1                                 */
 #define STF_PROF_HARTREE  0
@@ -370,7 +385,8 @@ int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* L
  *   opts   : host array of nprob option sets, one per problem (beta, eta0,
  *            tol, step rule, variant, max_iter may differ); precision must
  *            be the same for all, use_graph and check_every are taken from
- *            opts[0]; history is ignored; MIXED needs p <= 384.  switch_tol
+ *            opts[0]; history is ignored; MIXED needs p <= 384; fused must
+ *            be 0 (STF_E_UNSUPPORTED otherwise).  switch_tol
  *            acts as in stf_solve, per problem: in the float32 forms a problem
  *            that reaches it (or stalls) continues in float64 at once while
  *            the others go on in float32 in the same iterations

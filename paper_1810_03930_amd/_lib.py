@@ -56,7 +56,7 @@ class StfOptions(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
         ("beta", ctypes.c_double),
         ("eta0", ctypes.c_double),
         ("eta_const", ctypes.c_double),

@@ -70,7 +70,7 @@ ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(const stf_problem* prob, int precision, bool moptqr) {
+Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fused) {
     Layout L;
     memset(&L, 0, sizeof(L));
     const int64_t n = prob->n;
@@ -147,11 +147,15 @@ Layout make_layout(const stf_problem* prob, int precision, bool moptqr) {
     L.lam2 = take(2 * pp);
     L.cwork = take(pp);
     L.gtmp = prob->B ? take(np * 8) : (size_t)-1;  // room for either dtype
-    if (moptqr) {
-        L.xalt = take(np * 8);
-        L.vbuf = take(np * 8);
+    L.xalt = (moptqr || fused) ? take(np * 8) : (size_t)-1;
+    L.vbuf = moptqr ? take(np * 8) : (size_t)-1;
+    if (fused) {
+        L.colsq = take((size_t)L.gram.nchunks * 4 * p * 8);
+        L.nu2 = take((size_t)p * 8);
+        const size_t slots = (size_t)std::max(2 * L.res.ncb, L.resmx.ncb);
+        L.rhopart = take(slots * (size_t)n * 8);
     } else {
-        L.xalt = L.vbuf = (size_t)-1;
+        L.colsq = L.nu2 = L.rhopart = (size_t)-1;
     }
     L.total = off;
     return L;
@@ -302,7 +306,10 @@ struct IterCtx {
     DevState* st;
     DevParams* prm;
     bool moptqr;
-    double* xb[2];  // MOptQR: X^k lives in xb[k & 1] (the caller's X and the workspace's xalt)
+    bool fused;     // single-pass form (stf_options.fused)
+    // MOptQR and the single-pass form: X^k lives in xb[k & 1] (the caller's X
+    // and the workspace's xalt, or the float64 continuation's x64 and xalt)
+    void* xb[2];
 };
 
 // ev (optional): STF_NPROF + 1 events bracketing the kernel groups.
@@ -318,8 +325,9 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     void* Gc = w.base + c.g[parity];
     void* Gp = w.base + c.g[parity ^ 1];
     double* rho = needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr;
-    // MOptQR iterates between two buffers; the others update X in place
-    void* X = c.moptqr ? (void*)c.xb[parity] : c.X;
+    // MOptQR and the single-pass form iterate between two buffers; the others
+    // update X in place
+    void* X = (c.moptqr || c.fused) ? c.xb[parity] : c.X;
     mark(0);
     if (has_hartree(prob))
         launch_hartree(prob, rho, w.at<double>(w.L.phi), w.at<double>(w.L.hscr),
@@ -332,20 +340,45 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
     mark(2);
     // groups 2..4: the Gram kernel | chunk reduction, p x p stage, KKT products,
     // split of M_L | the residual kernel (events 3 and 4 recorded by the launchers)
+    // (the single-pass form also takes the column sums of G^2 from this pass)
     launch_gram(c.dtype, c.precision, w.L.gram, X, Gc, n, p, w.at<double>(w.L.gram_part),
                 w.at<double>(w.L.S), w.at<double>(w.L.W), c.st, s, ev ? ev[3] : nullptr,
-                /*w_sym=*/w_symmetric(prob));
+                /*w_sym=*/w_symmetric(prob), c.fused ? w.at<double>(w.L.colsq) : nullptr);
     launch_stage1(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.Psi),
                   w.at<double>(w.L.ML), w.at<double>(w.L.Bm), w.at<double>(w.L.fpart), p, c.st, s,
                   w.at<double>(w.L.lam2));
     launch_kkt_products(w.at<double>(w.L.S), w.at<double>(w.L.ML), w.at<double>(w.L.Bm),
                         w.at<double>(w.L.W), w.at<double>(w.L.T1), p, c.st, s);
     const ResPlan& rp = (c.precision == STF_PREC_MIXED) ? w.L.mixed_plan() : w.L.res;
+    if (c.fused) {
+        // eta^k and nu^k first (p x p work), then one pass that forms gradL^k,
+        // the step-size and stop-test dots, X^{k+1} (into the other buffer)
+        // and the row sums of its squares
+        launch_fused_pre(c.prm, w.at<double>(w.L.S), w.at<double>(w.L.W), w.at<double>(w.L.ML),
+                         w.at<double>(w.L.Rm), w.at<double>(w.L.colsq), w.L.gram.nchunks,
+                         gram_colsq_slots(c.dtype), w.at<double>(w.L.nu2), p, c.st, s);
+        launch_residual_fused(c.dtype, rp, X, c.xb[parity ^ 1], Gc, Gp, w.at<double>(w.L.ML),
+                              w.at<double>(w.L.nu), w.at<double>(w.L.nu2), n, p,
+                              w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
+                              w.at<double>(w.L.rhopart), c.prm, c.st, w.base + w.L.mix, s,
+                              ev ? ev[4] : nullptr);
+        mark(5);
+        launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
+                      w.at<double>(w.L.S), w.at<double>(w.L.T1), w.at<double>(w.L.fpart),
+                      w.at<double>(w.L.colpart), w.at<double>(w.L.nu), p, c.st, s,
+                      w.at<double>(w.L.nu2));
+        mark(6);
+        if (rho)
+            launch_rho_reduce(w.at<double>(w.L.rhopart), fused_rho_slots(c.dtype, rp), n, rho,
+                              c.st, s);
+        mark(7);
+        return;
+    }
     launch_residual(c.dtype, c.precision, rp, X, Gc, Gp, w.at<double>(w.L.ML),
                     w.at<double>(w.L.Psi), w.at<double>(w.L.nu), n, p,
                     w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal), c.prm, c.st,
                     RES_ITERATE, w.base + w.L.mix, s, ev ? ev[4] : nullptr,
-                    c.moptqr ? c.xb[parity ^ 1] : nullptr);
+                    c.moptqr ? (const void*)c.xb[parity ^ 1] : nullptr);
     mark(5);
     launch_stage2(c.prm, rp, w.at<double>(w.L.res_col), w.at<double>(w.L.res_scal),
                   w.at<double>(w.L.S), w.at<double>(w.L.T1), w.at<double>(w.L.fpart),
@@ -355,7 +388,7 @@ static void enqueue_iteration(const IterCtx& c, int parity, hipStream_t s,
         // the Cholesky-QR retraction (Table 1, Section 5.5): V = X - D / eta,
         // V^T V = R^T R, X^{k+1} = V R^{-1} into the buffer of X^{k-1}
         double* V = w.at<double>(w.L.vbuf);
-        double* Xn = c.xb[parity ^ 1];
+        double* Xn = (double*)c.xb[parity ^ 1];
         launch_vform((const double*)X, (const double*)Gc, V, n, p, c.st, s);
         launch_gram(STF_F64, STF_PREC_FP64, w.L.gram64, V, V, n, p, w.at<double>(w.L.gram_part),
                     w.at<double>(w.L.Rm), nullptr, c.st, s);
@@ -395,6 +428,18 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     if (opt->max_iter < 0 || opt->kkt_every < 1 || opt->check_every < 1) return STF_E_INVALID;
     if (!(opt->eta0 > 0.0) || !(opt->tol >= 0.0) || !isfinite(opt->beta)) return STF_E_INVALID;
     if (opt->eta_rule == STF_ETA_CONST && !(opt->eta_const > 0.0)) return STF_E_INVALID;
+    const bool fused = opt->fused != 0;
+    if (fused) {
+        // the single-pass form needs eta^k before the pass (the lagged pair),
+        // the Gram kernel with column sums (p > 64), and a row-block pass with
+        // the update in its epilogue (float64, or split bf16 with M_L in LDS)
+        if (moptqr || opt->bb_index != STF_BB_LAGGED || opt->eta_rule == STF_ETA_DIFF ||
+            prob->p <= 64)
+            return STF_E_UNSUPPORTED;
+        if (opt->precision != STF_PREC_FP64 &&
+            !(opt->precision == STF_PREC_MIXED32 && make_res_plan(prob->n, prob->p, 256).nrb > 0))
+            return STF_E_UNSUPPORTED;
+    }
     const int dtype = (opt->precision == STF_PREC_FP64) ? STF_F64 : STF_F32;
     // a float32 A serves every form (the float64 form widens it exactly); a
     // float64 A only the float64 form
@@ -403,7 +448,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
 
     Ws w;
     w.base = (char*)ws;
-    w.L = make_layout(prob, opt->precision, moptqr);
+    w.L = make_layout(prob, opt->precision, moptqr, fused);
     if (ws_bytes < w.L.total) return STF_E_WORKSPACE;
     memset(res, 0, sizeof(*res));
     const int64_t n = prob->n;
@@ -421,8 +466,10 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     c.st = w.at<DevState>(w.L.state);
     c.prm = w.at<DevParams>(w.L.params);
     c.moptqr = moptqr;
-    c.xb[0] = (double*)X;
-    c.xb[1] = moptqr ? w.at<double>(w.L.xalt) : nullptr;
+    c.fused = fused;
+    c.xb[0] = X;
+    c.xb[1] = (moptqr || fused) ? w.at<double>(w.L.xalt) : nullptr;
+    void* xb64[2] = {c.xb[0], c.xb[1]};  // where the float64 phase keeps X^k
 
     DevParams hp;
     memset(&hp, 0, sizeof(hp));
@@ -441,6 +488,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     hp.switch_tol = (opt->precision == STF_PREC_FP64) ? 0.0 : std::max(0.0, opt->switch_tol);
     hp.switch_stall = kSwitchStall;
     hp.history = opt->history;
+    hp.fused = fused ? 1 : 0;
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);
@@ -542,8 +590,16 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         c64.dtype = STF_F64;
         c64.precision = STF_PREC_FP64;
         if (nomaster)  // the float64 phase starts from the float32 iterate
-            launch_convert(STF_F64, X, STF_F32, w.at<double>(w.L.x64), (size_t)n * p, s);
+            launch_convert(STF_F64, fused ? c.xb[k & 1] : X, STF_F32, w.at<double>(w.L.x64),
+                           (size_t)n * p, s);
         c64.X = w.at<double>(w.L.x64);
+        if (fused) {
+            // X^k (now in x64) and X^{k+1} alternate between x64 and xalt
+            c64.xb[k & 1] = w.at<double>(w.L.x64);
+            c64.xb[(k & 1) ^ 1] = w.at<double>(w.L.xalt);
+            xb64[0] = c64.xb[0];
+            xb64[1] = c64.xb[1];
+        }
         c64.Xm = nullptr;
         c64.g[k & 1] = w.L.g64;
         c64.g[(k & 1) ^ 1] = w.L.g64b;
@@ -578,9 +634,18 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         return STF_E_DIVERGED;
     }
 
-    // MOptQR: the returned iterate X^k sits in buffer k & 1
-    if (moptqr && (hs.final_iter & 1))
+    // MOptQR and the single-pass form: the returned iterate X^k sits in buffer
+    // k & 1 (of the float64 phase, if the solve continued in float64)
+    const int kf1 = hs.final_iter & 1;
+    if (moptqr && kf1)
         HIPCHK(hipMemcpyAsync(X, c.xb[1], (size_t)n * p * 8, hipMemcpyDeviceToDevice, s));
+    if (fused && (dtype == STF_F64 || res->switch_iter >= 0)) {
+        // float64 iterates: into X (float64 form) or x64 (after a hand-over);
+        // a float32 final iterate is converted from its buffer below
+        void* dst = (dtype == STF_F64) ? X : (void*)w.at<double>(w.L.x64);
+        if (xb64[kf1] != dst)
+            HIPCHK(hipMemcpyAsync(dst, xb64[kf1], (size_t)n * p * 8, hipMemcpyDeviceToDevice, s));
+    }
     // float64 copy of the returned iterate, CholeskyQR2, float64 evaluation
     double* Xd;
     double* tmp;
@@ -593,7 +658,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
         // without a master, the float64 copy is the float32 iterate (unless a
         // float64 phase has taken over, which iterates on that copy)
         if (nomaster && res->switch_iter < 0)
-            launch_convert(STF_F64, X, STF_F32, Xd, (size_t)n * p, s);
+            launch_convert(STF_F64, fused ? c.xb[kf1] : X, STF_F32, Xd, (size_t)n * p, s);
     }
     DevState* st_eval = w.at<DevState>(w.L.state_eval);
     launch_init_state(st_eval, s);
@@ -649,9 +714,11 @@ extern "C" {
 
 size_t stf_workspace_size(const stf_problem* prob, const stf_options* opt) {
     if (check_problem(prob) != STF_OK) return 0;
-    if (opt) return make_layout(prob, opt->precision, opt->variant == STF_MOPTQR).total;
-    const size_t a = make_layout(prob, STF_PREC_FP64, true).total;
-    const size_t b = make_layout(prob, STF_PREC_FP32).total;
+    if (opt)
+        return make_layout(prob, opt->precision, opt->variant == STF_MOPTQR, opt->fused != 0)
+            .total;
+    const size_t a = make_layout(prob, STF_PREC_FP64, true, true).total;
+    const size_t b = make_layout(prob, STF_PREC_FP32, false, true).total;
     return a > b ? a : b;
 }
 

@@ -87,6 +87,7 @@ int batch_check(int32_t nprob, const stf_problem* probs, const stf_options* opts
             if (o.max_iter < 0 || o.kkt_every < 1 || o.check_every < 1) return STF_E_INVALID;
             if (!(o.eta0 > 0.0) || !(o.tol >= 0.0) || !isfinite(o.beta)) return STF_E_INVALID;
             if (o.eta_rule == STF_ETA_CONST && !(o.eta_const > 0.0)) return STF_E_INVALID;
+            if (o.fused) return STF_E_UNSUPPORTED;  // the single-pass form: one problem only
             if (prec == STF_PREC_MIXED && (probs[b].p + 31) / 32 * 32 > 384)
                 return STF_E_UNSUPPORTED;
         }

@@ -29,6 +29,7 @@ struct DevState {
     int32_t k_best;       // iteration of the smallest stop-test value so far
     int32_t pad[2];
     double kkt_best;      // that value
+    double eta_next;      // single-pass form: eta^k, set before the pass of iteration k
 };
 
 // Parameters the device kernels read (copied once per solve into the workspace).
@@ -42,6 +43,8 @@ struct DevParams {
                             // smallest stop-test value (with switch_tol > 0; 0 = never)
     double switch_tol;      // relative KKT at which a reduced-precision solve hands over
     double* history;        // optional per-iteration record, (max_iter + 1) x 4
+    int32_t fused;          // 1: single-pass update (eta, nu before the residual pass)
+    int32_t pad_f;
 };
 
 // Terms of the gradient beyond (L + Diag v + alpha Diag phi) X: the linear
@@ -108,8 +111,11 @@ struct Layout {
     size_t lam2;          // two p x p float64: the dual-ascent multiplier, by iteration parity
     size_t cwork;         // p x p float64: the working matrix of the blocked Cholesky
     size_t gtmp;          // n x p (iteration dtype): H0 X before the right factor B
-    size_t xalt;          // n x p float64 (MOptQR): the other iterate buffer
+    size_t xalt;          // n x p float64 (MOptQR, single-pass form): the other iterate buffer
     size_t vbuf;          // n x p float64 (MOptQR): V = X - D / eta before the retraction
+    size_t colsq;         // single-pass form: Gram chunks x 4 x p column sums of G^2
+    size_t nu2;           // single-pass form: nu^k (p float64), found before the pass
+    size_t rhopart;       // single-pass form: row partials of rho, slots x n float64
     size_t total;
     GramPlan gram;        // plan for the iteration dtype
     GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)
@@ -167,7 +173,9 @@ int elem_size(int dtype);
 // target_wg: workgroups the plan aims at (the single-problem defaults when omitted)
 GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 512, bool wup = false);
 ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
-Layout make_layout(const stf_problem* prob, int precision, bool moptqr = false);
+// fused: the buffers of the single-pass form (and the second iterate buffer xalt)
+Layout make_layout(const stf_problem* prob, int precision, bool moptqr = false,
+                   bool fused = false);
 size_t align256(size_t x);
 
 // A problem's workspace: base address and layout.
@@ -212,7 +220,11 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G,
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X,
                  const void* G, int64_t n, int p, double* part, double* S,
                  double* W, const DevState* st, hipStream_t s,
-                 hipEvent_t after_main = nullptr, bool w_sym = false);
+                 hipEvent_t after_main = nullptr, bool w_sym = false,
+                 double* colsq = nullptr);
+// colsq (single-pass form, W wanted, p > 64): per chunk, gram_colsq_slots
+// partial column sums of G^2 at colsq[(chunk * 4 + slot) * p + c]
+int gram_colsq_slots(int dtype);
 // lam2: two p x p buffers of the dual-ascent multiplier (STF_MULT_DUAL), else null
 void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
@@ -234,7 +246,27 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* pp_part,
                    const double* feas_part, double* colpart, double* nu, int p, DevState* st,
-                   hipStream_t s);
+                   hipStream_t s, const double* nu_cur = nullptr);
+// ---- single-pass form (stf_options.fused) ----
+// SM = S M_L (float64 MFMA), then eta^k into st->eta_next and the PCAL column
+// norms nu^k into nu_cur, from S, W, M_L, SM and the Gram pass's column sums
+void launch_fused_pre(const DevParams* prm, const double* S, const double* W, const double* ML,
+                      double* SM, const double* colsq, int nchunks, int nsl, double* nu_cur,
+                      int p, DevState* st, hipStream_t s);
+// the row-block pass of the single-pass form: gradL over G, the Barzilai-
+// Borwein and column dots as in launch_residual, X^{k+1} into Xn and per-slot
+// row sums of its squares into rho_part[fused_rho_slots][n].  float64 (plan
+// res) or float32 with split-bf16 products (plan resmx; M_L split into mix)
+int fused_rho_slots(int dtype, const ResPlan& rp);
+void launch_residual_fused(int dtype, const ResPlan& rp, const void* X, void* Xn, void* G,
+                           const void* Gprev, const double* ML, const double* nu,
+                           const double* nu_cur, int64_t n, int p, double* part_col,
+                           double* part_scal, double* rho_part, const DevParams* prm,
+                           DevState* st, void* mix, hipStream_t s,
+                           hipEvent_t before_main = nullptr);
+// rho[r] = sum of the nslots row partials
+void launch_rho_reduce(const double* part, int nslots, int64_t n, double* rho,
+                       const DevState* st, hipStream_t s);
 // Xm (float32 X only): float64 master iterate, read and written; X gets its rounding
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p,
                    const double* nu, double* rho, const DevState* st, hipStream_t s,

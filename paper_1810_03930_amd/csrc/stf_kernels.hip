@@ -810,7 +810,8 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
                                                   const T* __restrict__ G, int64_t n, int p,
                                                   int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
-                                                  const DevState* __restrict__ st, int bid_, int nblk_) {
+                                                  const DevState* __restrict__ st, int bid_, int nblk_,
+                                                  double* __restrict__ colsq = nullptr) {
     if (st && st->done) return;
     constexpr int KC = (sizeof(T) == 8) ? 16 : 32;
     constexpr int LS = 128 + 4;
@@ -885,6 +886,12 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
     // in a diagonal block of a symmetric result the wave below the diagonal has
     // nothing to compute (it still stages its share of the panels)
     const bool below = (bi == bj) && (isS || wup) && (wi > wj);
+    // single-pass form: the diagonal blocks of W also sum the squares of their
+    // G columns (each thread always loads the same VX columns of the block)
+    const bool csq = colsq && !isS && bi == bj;
+    double sq[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) sq[v] = 0.0;
     if (active) load(k0);
     int step = 0;
     for (int64_t kb = k0; active && kb < k1; kb += KC, ++step) {
@@ -897,6 +904,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
             for (int v = 0; v < VX; ++v) {
                 Zs[kk * LS + col + v] = zr[s2][v];
                 Ys[kk * LS + col + v] = yr[s2][v];
+                if (csq) sq[v] += (double)yr[s2][v] * (double)yr[s2][v];
             }
         }
         __syncthreads();
@@ -928,6 +936,13 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
             }
         }
     }
+    if (csq) {
+        // [chunk][wave][column] partials (4 threads share a column pair)
+        const int col = (tid % (128 / VX)) * VX;
+#pragma unroll
+        for (int v = 0; v < VX; ++v)
+            if (yc + col + v < p) colsq[((size_t)c * 4 + wave) * p + yc + col + v] = sq[v];
+    }
     if (below) return;
     double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
 #pragma unroll
@@ -949,8 +964,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_gram_lds(const 
                                                   const T* __restrict__ G, int64_t n, int p,
                                                   int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
-                                                  const DevState* __restrict__ st) {
-    body_gram_lds<T>(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x, gridDim.x);
+                                                  const DevState* __restrict__ st,
+                                                  double* __restrict__ colsq = nullptr) {
+    body_gram_lds<T>(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x, gridDim.x,
+                     colsq);
 }
 
 
@@ -1070,7 +1087,7 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
                                                   int nb, int n_s_tiles, int n_tiles, int wup,
                                                   int64_t chunk, double* __restrict__ part,
                                                   const DevState* __restrict__ st, int bid_,
-                                                  int nblk_) {
+                                                  int nblk_, double* __restrict__ colsq = nullptr) {
     if (st && st->done) return;
     constexpr int KS = 32;            // rows per step
     constexpr int KP = KS + 8;        // LDS pitch in bf16
@@ -1106,7 +1123,15 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
             yr[e] = buf_ldf(ry, oy + ob + (uint32_t)e * rowb);
         }
     };
+    // single-pass form: the diagonal blocks of W also sum the squares of their
+    // G columns (the loader thread owns column yc + lc)
+    const bool csq = colsq && !isS && bi == bj;
+    double sq = 0.0;
     auto store = [&]() {
+        if (csq) {
+#pragma unroll
+            for (int e = 0; e < RH; ++e) sq += (double)yr[e] * (double)yr[e];
+        }
 #pragma unroll
         for (int q = 0; q < RH / 8; ++q) {
             float a[8], b[8];
@@ -1166,6 +1191,7 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
             }
         }
     }
+    if (csq && yok) colsq[((size_t)c * 4 + lh) * p + yc + lc] = sq;
     if (below) return;
     double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
 #pragma unroll
@@ -1183,9 +1209,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_bf3_lds(const float* __restrict
                                                       const float* __restrict__ G, int64_t n,
                                                       int p, int nb, int n_s_tiles, int n_tiles, int wup,
                                                       int64_t chunk, double* __restrict__ part,
-                                                      const DevState* __restrict__ st) {
+                                                      const DevState* __restrict__ st,
+                                                      double* __restrict__ colsq = nullptr) {
     body_gram_bf3_lds(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x,
-                      gridDim.x);
+                      gridDim.x, colsq);
 }
 
 
@@ -1415,13 +1442,16 @@ constexpr int kMixRW = 32;
 // sum_{a+b<=2} X_a M_b give float32-level accuracy.  Epilogue, partials and BB
 // pair as in k_residual (stop test by the p x p identity, so no product with
 // Psi).
-template <int PKMAX, int RW>
+// FU = true: the single-pass form, as in body_residual (X^{k+1} to Xn, row
+// sums of its squares over the workgroup's 64 columns to rho_part[cb][r]).
+template <int PKMAX, int RW, bool FU = false>
 __device__ __forceinline__ void body_residual_bf6_lds(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
     const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
     int p, int nrb, int ncb, int64_t nrt, double* __restrict__ part_col,
     double* __restrict__ part_scal, const DevParams* __restrict__ prm,
-    const DevState* __restrict__ st, int bid_, int nblk_) {
+    const DevState* __restrict__ st, int bid_, int nblk_, float* __restrict__ Xn = nullptr,
+    const double* __restrict__ nu_cur = nullptr, double* __restrict__ rho_part = nullptr) {
     if (st->done) return;
     constexpr int LP = PKMAX + 8;  // LDS pitch (bf16) of one column's K run
     constexpr int NW = 256 / RW;   // waves
@@ -1450,12 +1480,17 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const double rinv_eta = 1.0 / st->eta;
     bool cok[4];
     double onu[4];
+    // single-pass form: the update in float32 arithmetic (the iterate is
+    // float32), with the reciprocals of eta^k and nu^k
+    float rnu[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int c = cblk + j * 16 + lr;
         cok[j] = c < p;
         onu[j] = (have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
+        rnu[j] = (FU && cok[j]) ? (float)(1.0 / nu_cur[c]) : 1.f;
     }
+    const float reta_cur = FU ? (float)(1.0 / st->eta_next) : 1.f;
     double cxg[4] = {0.0, 0.0, 0.0, 0.0}, cgg[4] = {0.0, 0.0, 0.0, 0.0};
     double sss = 0.0, ssy = 0.0, syy = 0.0;
     const bool vec = (p % 4) == 0;
@@ -1469,6 +1504,8 @@ __device__ __forceinline__ void body_residual_bf6_lds(
         const __amdgpu_buffer_rsrc_t bx = buf_rsrc(X + rbase, (uint32_t)nvr * rowb);
         const __amdgpu_buffer_rsrc_t bg = buf_rsrc(G + rbase, (uint32_t)nvr * rowb);
         const __amdgpu_buffer_rsrc_t bp = buf_rsrc(Gprev + rbase, (uint32_t)nvr * rowb);
+        const __amdgpu_buffer_rsrc_t bn = buf_rsrc(FU ? Xn + rbase : X + rbase,
+                                                   FU ? (uint32_t)nvr * rowb : 0u);
         // X fragments (16 rows x 8 consecutive columns per MFMA tile) of two
         // K-chunks in flight: chunk kc is split while kc + 64 is loaded
         float xa[2][IT][8];
@@ -1530,6 +1567,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             step(kc, xa[0]);
             if (kc + 32 < pk) step(kc + 32, xa[1]);
         }
+
         // gradL = G - X M_L over G, one 16 x 16 sub-tile per round; the next
         // round's G, X and gradL^{k-1} are loaded before this round's arithmetic.
         // The BB and column dots of the block are summed in float32 per lane
@@ -1556,6 +1594,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             }
         };
         eload(0, 0);
+        float rsq[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
             if (rr + 1 < NR) eload(rr + 1, (rr + 1) & 1);
@@ -1566,6 +1605,14 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                 const float gl = eg[sb][q] - acc[i][j][q];
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(gl), bg,
                                                       eoff(i * 16 + Mma<float>::row(g, q), j), 0, 0);
+                if constexpr (FU) {
+                    // entries past n or p: the store falls outside the buffer and
+                    // x = gl = 0 adds nothing to the row sums
+                    const float xn = (ex[sb][q] - gl * reta_cur) * rnu[j];
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __float_as_uint(xn), bn, eoff(i * 16 + Mma<float>::row(g, q), j), 0, 0);
+                    rsq[q] += cok[j] ? xn * xn : 0.f;
+                }
                 txg[j] += ex[sb][q] * gl;
                 tgg[j] += gl * gl;
                 if (have_prev) {
@@ -1574,6 +1621,19 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                     tss += sd * sd;
                     tsy += sd * yd;
                     tyy += yd * yd;
+                }
+            }
+            if constexpr (FU) {
+                if (j == 3) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float v = rsq[q];
+#pragma unroll
+                        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+                        const int64_t r = r0 + i * 16 + Mma<float>::row(g, q);
+                        if (lr == 0 && r < n) rho_part[(size_t)cb * n + r] = (double)v;
+                        rsq[q] = 0.f;
+                    }
                 }
             }
         }
@@ -1640,15 +1700,17 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     (void)sh;
     (void)prm;
 }
-template <int PKMAX, int RW>
+template <int PKMAX, int RW, bool FU = false>
 __global__ __launch_bounds__(64 * (256 / RW)) void k_residual_bf6_lds(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
     const __bf16* __restrict__ MS, int prow, int pk, const double* __restrict__ nu, int64_t n,
     int p, int nrb, int ncb, int64_t nrt, double* __restrict__ part_col,
     double* __restrict__ part_scal, const DevParams* __restrict__ prm,
-    const DevState* __restrict__ st) {
-    body_residual_bf6_lds<PKMAX, RW>(X, G, Gprev, MS, prow, pk, nu, n, p, nrb, ncb, nrt,
-                                     part_col, part_scal, prm, st, blockIdx.x, gridDim.x);
+    const DevState* __restrict__ st, float* __restrict__ Xn = nullptr,
+    const double* __restrict__ nu_cur = nullptr, double* __restrict__ rho_part = nullptr) {
+    body_residual_bf6_lds<PKMAX, RW, FU>(X, G, Gprev, MS, prow, pk, nu, n, p, nrb, ncb, nrt,
+                                         part_col, part_scal, prm, st, blockIdx.x, gridDim.x,
+                                         Xn, nu_cur, rho_part);
 }
 
 
@@ -1991,14 +2053,21 @@ constexpr int kResBC = 64;
 // APPLY = true computes Out = X M only (CholeskyQR2's X R^{-1}).
 // XP = true (MOptQR, whose retraction is not a column scaling) reads the
 // previous iterate X^{k-1} from Xprev instead: S^k = X^k - X^{k-1}.
-template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false>
+//
+// FU = true (the single-pass form) also takes the update of the same iteration
+// in the epilogue: X^{k+1} = (X^k - gradL^k / eta^k) / nu^k (eta^k and nu^k
+// are known before the pass, see k_fused_pre) written to Xn, and the squared
+// entries of X^{k+1} summed per row over the workgroup's columns into
+// rho_part[slot][r] (slot = column block x column wave).
+template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false, bool FU = false>
 __device__ __forceinline__ void body_residual(
     const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode, int bid_, int nblk_,
-    const T* __restrict__ Xprev = nullptr) {
+    const T* __restrict__ Xprev = nullptr, T* __restrict__ Xn = nullptr,
+    const double* __restrict__ nu_cur = nullptr, double* __restrict__ rho_part = nullptr) {
     if (st && st->done) return;
     constexpr int KC = sizeof(T) == 8 ? 16 : 32;  // rows of M_L (columns of X) per LDS stage
     constexpr int XS = KC + 1;
@@ -2037,13 +2106,16 @@ __device__ __forceinline__ void body_residual(
     const double rinv_eta = 1.0 / eta_prev;
     // per-column constants of this lane's four output columns
     bool cok[JT];
-    double onu[JT];
+    double onu[JT], rnu[JT];
 #pragma unroll
     for (int j = 0; j < JT; ++j) {
         const int c = c0 + j * 16 + lr;
         cok[j] = c < p;
         onu[j] = (!APPLY && !XP && have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
+        rnu[j] = (FU && cok[j]) ? 1.0 / nu_cur[c] : 1.0;
     }
+    const double reta_cur = FU ? 1.0 / st->eta_next : 1.0;
+    const int rslot = cb * WC + wc;
     // staging of one K-chunk: X rows (128 x KC) and M_L / Psi rows (KC x BC),
     // 16-byte vectors when the row pitch allows it, prefetched one chunk ahead
     constexpr int VX = 16 / (int)sizeof(T);          // elements of X per 16-byte load
@@ -2180,6 +2252,7 @@ __device__ __forceinline__ void body_residual(
             }
         };
         eload(0, 0);
+        double rsq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
             if (rr + 1 < NR) eload(rr + 1, (rr + 1) & 1);
@@ -2198,6 +2271,11 @@ __device__ __forceinline__ void body_residual(
                 G[(size_t)r * p + c0 + j * 16 + lr] = glt;
                 const double gl = (double)glt;
                 const double x = (double)ex[sb][q];
+                if constexpr (FU) {
+                    const T xn = (T)((x - gl * reta_cur) * rnu[j]);
+                    __builtin_nontemporal_store(xn, &Xn[(size_t)r * p + c0 + j * 16 + lr]);
+                    rsq[q] += (double)xn * (double)xn;
+                }
                 cxg[j] += x * gl;
                 cgg[j] += gl * gl;
                 if (have_prev) {
@@ -2211,6 +2289,20 @@ __device__ __forceinline__ void body_residual(
                     sss += sd * sd;
                     ssy += sd * yd;
                     syy += yd * yd;
+                }
+            }
+            if constexpr (FU) {
+                if (j == JT - 1) {
+                    // the row sums of this 16-row group over the wave's columns
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        double v = rsq[q];
+#pragma unroll
+                        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+                        const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
+                        if (lr == 0 && r < n) rho_part[(size_t)rslot * n + r] = v;
+                        rsq[q] = 0.0;
+                    }
                 }
             }
         }
@@ -2254,17 +2346,18 @@ __device__ __forceinline__ void body_residual(
         ps[3] = t3;
     }
 }
-template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false>
+template <typename T, typename TG, bool APPLY, bool KKT, int WC, bool XP = false, bool FU = false>
 __global__ __launch_bounds__(128 * WC, 2) void k_residual(
     const T* __restrict__ X, TG* __restrict__ G, const TG* __restrict__ Gprev,
     const double* __restrict__ ML, const double* __restrict__ Psi,
     const double* __restrict__ nu, int64_t n, int p, int nrb, int ncb, int64_t nrt,
     double* __restrict__ part_col, double* __restrict__ part_scal,
     const DevParams* __restrict__ prm, const DevState* __restrict__ st, int mode,
-    const T* __restrict__ Xprev = nullptr) {
-    body_residual<T, TG, APPLY, KKT, WC, XP>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt,
-                                             part_col, part_scal, prm, st, mode, blockIdx.x,
-                                             gridDim.x, Xprev);
+    const T* __restrict__ Xprev = nullptr, T* __restrict__ Xn = nullptr,
+    const double* __restrict__ nu_cur = nullptr, double* __restrict__ rho_part = nullptr) {
+    body_residual<T, TG, APPLY, KKT, WC, XP, FU>(X, G, Gprev, ML, Psi, nu, n, p, nrb, ncb, nrt,
+                                                 part_col, part_scal, prm, st, mode, blockIdx.x,
+                                                 gridDim.x, Xprev, Xn, nu_cur, rho_part);
 }
 
 
@@ -2380,7 +2473,8 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
-                                                 DevState* __restrict__ st, int bid_, int nblk_) {
+                                                 DevState* __restrict__ st, int bid_, int nblk_,
+                                                 const double* __restrict__ nu_cur = nullptr) {
     if (st->done) return;
     __shared__ double sr[7][1024];
     __shared__ double s_eta;
@@ -2458,7 +2552,10 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
         if (!stop) {
             const double ss = sr[1][0], sy = sr[2][0], yy = sr[3][0];
             const int rule = prm->eta_rule;
-            if (rule == STF_ETA_CONST) {
+            if (prm->fused) {
+                // single-pass form: eta^k was chosen before the pass
+                eta = st->eta_next;
+            } else if (rule == STF_ETA_CONST) {
                 eta = prm->eta_const;
             } else if (k == 0) {
                 eta = prm->eta0;
@@ -2510,6 +2607,13 @@ __device__ __forceinline__ void body_stage2(const DevParams* __restrict__ prm,
     if (s_stop) return;
     const double eta = s_eta;
     const bool pcal = prm->variant == STF_PCAL;
+    if (prm->fused) {
+        // nu^k was applied in the pass; it is the "previous" nu of the next one
+        for (int c = t; c < p; c += blockDim.x) nu[c] = nu_cur[c];
+        __syncthreads();
+        if (t == 0) st->iter = st->iter + 1;
+        return;
+    }
     for (int c = t; c < p; c += blockDim.x) {
         double nv = 1.0;
         if (pcal) {
@@ -2530,9 +2634,10 @@ __global__ __launch_bounds__(1024) void k_stage2(const DevParams* __restrict__ p
                                                  const double* __restrict__ feas_part,
                                                  double* __restrict__ colpart, int ncolg,
                                                  double* __restrict__ nu, int p,
-                                                 DevState* __restrict__ st) {
+                                                 DevState* __restrict__ st,
+                                                 const double* __restrict__ nu_cur) {
     body_stage2(prm, part_scal, nparts, S, pp_part, npp, feas_part, colpart, ncolg, nu, p, st,
-                blockIdx.x, gridDim.x);
+                blockIdx.x, gridDim.x, nu_cur);
 }
 
 
@@ -2889,6 +2994,117 @@ __global__ __launch_bounds__(1024) void k_pp_kkt64(const double* __restrict__ S,
     }
     c = block_sum<16>(c, sh);
     if (threadIdx.x == 0) part[by * nt + bx] = c;
+}
+
+// C = A B for p x p float64 matrices, 64 x 64 tiles of float64 MFMA.
+__global__ __launch_bounds__(1024) void k_pp_mm64(const double* __restrict__ A,
+                                                  const double* __restrict__ B,
+                                                  double* __restrict__ C, int p,
+                                                  const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ double sa[kCB * kDP], sb[kCB * kDP];
+    const int bx = blockIdx.x, by = blockIdx.y, nt = gridDim.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int ti = wave >> 2, tj = wave & 3;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < nt; ++kb) {
+        __syncthreads();
+        chol_load(sa, A, p, by, kb, false, false);
+        chol_load(sb, B, p, kb, bx, false, false);
+        __syncthreads();
+        const d4 t = dst_tile(sa, sb, ti, tj, lr, lk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += t[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gr = by * kCB + 16 * ti + Mma<double>::row(lk, q);
+        const int gc = bx * kCB + 16 * tj + lr;
+        if (gr < p && gc < p) C[(size_t)gr * p + gc] = acc[q];
+    }
+}
+
+// Single-pass form, before the residual pass of iteration k: eta^k by the
+// step-size rule on the lagged pair (S^{k-1}, Y^{k-1}), whose inner products
+// the previous pass left in the state, and the PCAL column norms of
+// Y = X^k - gradL^k / eta^k without forming gradL^k:
+//   ||Y_c||^2 = S_cc - 2 (W - S M_L)_cc / eta + (G^T G - 2 M_L^T W + M_L^T S M_L)_cc / eta^2
+// (X^T gradL = W - S M_L, gradL^T gradL = G^T G - W^T M_L - M_L^T W + M_L^T S M_L),
+// with diag(G^T G) from the Gram pass's column sums (nsl slots per chunk) and
+// SM = S M_L.  A workgroup takes 64 columns (one per lane, coalesced rows of
+// M_L, W and SM); its four waves split the sums over j and over the chunks.
+// Writes nu_cur and (workgroup 0) st->eta_next.
+__global__ __launch_bounds__(256) void k_fused_pre(const DevParams* __restrict__ prm,
+                                                   const double* __restrict__ S,
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ ML,
+                                                   const double* __restrict__ SM,
+                                                   const double* __restrict__ colsq,
+                                                   int nchunks, int nsl,
+                                                   double* __restrict__ nu_cur, int p,
+                                                   DevState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[3][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    // eta^k: the same scalar in every workgroup
+    const int k = st->iter;
+    const int rule = prm->eta_rule;
+    double eta = st->eta;
+    if (rule == STF_ETA_CONST) {
+        eta = prm->eta_const;
+    } else if (k < 2) {
+        eta = prm->eta0;   // the lagged pair exists from k = 2 on
+    } else {
+        const double pss = st->ss_l, psy = st->sy_l, pyy = st->yy_l;
+        double q = NAN;
+        if (rule == STF_ETA_BB1 || (rule == STF_ETA_ABB && (k & 1)))
+            q = (pss > 0.0) ? fabs(psy) / pss : NAN;
+        else
+            q = (psy != 0.0) ? pyy / fabs(psy) : NAN;
+        if (isfinite(q) && q > 0.0) eta = q;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->eta_next = eta;
+    if (prm->variant != STF_PCAL) {
+        if (wave == 0 && c < p) nu_cur[c] = 1.0;
+        return;
+    }
+    double gg = 0.0, mw = 0.0, msm = 0.0;
+    if (c < p) {
+        for (int ch = wave; ch < nchunks; ch += 4)
+            for (int q = 0; q < nsl; ++q) gg += colsq[((size_t)ch * 4 + q) * p + c];
+#pragma unroll 4
+        for (int j = wave; j < p; j += 4) {
+            const double m = ML[(size_t)j * p + c];
+            mw += m * W[(size_t)j * p + c];
+            msm += m * SM[(size_t)j * p + c];
+        }
+    }
+    red[0][wave][lane] = gg;
+    red[1][wave][lane] = mw;
+    red[2][wave][lane] = msm;
+    __syncthreads();
+    if (wave == 0 && c < p) {
+        gg = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+        mw = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
+        msm = (red[2][0][lane] + red[2][1][lane]) + (red[2][2][lane] + red[2][3][lane]);
+        const double xg = W[(size_t)c * p + c] - SM[(size_t)c * p + c];
+        const double y2 = S[(size_t)c * p + c] - 2.0 * xg / eta + (gg - 2.0 * mw + msm) / (eta * eta);
+        nu_cur[c] = sqrt(y2);
+    }
+}
+
+// rho[r] = sum over the slots of the single-pass residual's row partials.
+__global__ __launch_bounds__(256) void k_rho_reduce(const double* __restrict__ part, int nslots,
+                                                    int64_t n, double* __restrict__ rho,
+                                                    const DevState* __restrict__ st) {
+    if (st->done) return;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int q = 0; q < nslots; ++q) a += part[(size_t)q * n + r];
+        rho[r] = a;
+    }
 }
 
 // ---------------------------------------------------------- conversions ----
@@ -3377,7 +3593,7 @@ static void gram_dispatch(const GramPlan& gp, const T* X, const T* G, int64_t n,
 
 void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, const void* G,
                  int64_t n, int p, double* part, double* S, double* W, const DevState* st,
-                 hipStream_t s, hipEvent_t after_main, bool w_sym) {
+                 hipStream_t s, hipEvent_t after_main, bool w_sym, double* colsq) {
     // tiles: the upper blocks of S (when S is wanted) followed by the blocks of W
     // (the upper ones only when W is known to be symmetric)
     const int nst = S ? gp.n_s_tiles : 0;
@@ -3398,10 +3614,15 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
                                               part, st);
         else
             k_gram_bf3_lds<<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
-                                               part, st);
+                                               part, st, colsq);
     } else if (dtype == STF_F64) {
-        gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s, n_tiles,
-                              wup);
+        if (colsq && gp.wm == 4)
+            k_gram_lds<double><<<(unsigned)(n_tiles * gp.nchunks), 256, 0, s>>>(
+                (const double*)X, (const double*)G, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
+                part, st, colsq);
+        else
+            gram_dispatch<double>(g2, (const double*)X, (const double*)G, n, p, part, st, s,
+                                  n_tiles, wup);
     } else {
         gram_dispatch<float>(g2, (const float*)X, (const float*)G, n, p, part, st, s, n_tiles,
                              wup);
@@ -3499,15 +3720,74 @@ void launch_residual(int dtype, int precision, const ResPlan& rp, const void* X,
     }
 }
 
+int gram_colsq_slots(int dtype) { return dtype == STF_F64 ? 4 : 2; }
+
+int fused_rho_slots(int dtype, const ResPlan& rp) {
+    return dtype == STF_F64 ? rp.ncb * 2 : rp.ncb;
+}
+
+void launch_fused_pre(const DevParams* prm, const double* S, const double* W, const double* ML,
+                      double* SM, const double* colsq, int nchunks, int nsl, double* nu_cur,
+                      int p, DevState* st, hipStream_t s) {
+    const unsigned t = (unsigned)((p + kCB - 1) / kCB);
+    k_pp_mm64<<<dim3(t, t), 1024, 0, s>>>(S, ML, SM, p, st);
+    k_fused_pre<<<(unsigned)((p + 63) / 64), 256, 0, s>>>(prm, S, W, ML, SM, colsq, nchunks, nsl,
+                                                          nu_cur, p, st);
+}
+
+void launch_residual_fused(int dtype, const ResPlan& rp, const void* X, void* Xn, void* G,
+                           const void* Gprev, const double* ML, const double* nu,
+                           const double* nu_cur, int64_t n, int p, double* part_col,
+                           double* part_scal, double* rho_part, const DevParams* prm,
+                           DevState* st, void* mix, hipStream_t s, hipEvent_t before_main) {
+    const unsigned nwg = (unsigned)(rp.nrb * rp.ncb);
+    if (dtype == STF_F64) {
+        if (before_main) (void)hipEventRecord(before_main, s);
+        k_residual<double, double, false, false, 2, false, true><<<nwg, 256, 0, s>>>(
+            (const double*)X, (double*)G, (const double*)Gprev, ML, nullptr, nu, n, p, rp.nrb,
+            rp.ncb, rp.nrt, part_col, part_scal, prm, st, RES_ITERATE, nullptr, (double*)Xn,
+            nu_cur, rho_part);
+        return;
+    }
+    // float32 iterate, split-bf16 products with the M_L slice resident in LDS
+    const int prow = rp.ncb * 64, pk = (p + 31) / 32 * 32;
+    __bf16* MS = (__bf16*)mix;
+    const unsigned gs = (unsigned)(((size_t)prow * pk + 255) / 256);
+    k_split3_t<<<gs, 256, 0, s>>>(ML, MS, p, prow, pk, st);
+    if (before_main) (void)hipEventRecord(before_main, s);
+    const float* x = (const float*)X;
+    float* g = (float*)G;
+    const float* gp = (const float*)Gprev;
+    float* xn = (float*)Xn;
+    if (pk <= 128)
+        k_residual_bf6_lds<128, kMixRW, true><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
+            x, g, gp, MS, prow, pk, nu, n, p, rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm,
+            st, xn, nu_cur, rho_part);
+    else if (pk <= 256)
+        k_residual_bf6_lds<256, kMixRW, true><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
+            x, g, gp, MS, prow, pk, nu, n, p, rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm,
+            st, xn, nu_cur, rho_part);
+    else
+        k_residual_bf6_lds<384, kMixRW, true><<<nwg, 64 * (256 / kMixRW), 0, s>>>(
+            x, g, gp, MS, prow, pk, nu, n, p, rp.nrb, rp.ncb, rp.nrt, part_col, part_scal, prm,
+            st, xn, nu_cur, rho_part);
+}
+
+void launch_rho_reduce(const double* part, int nslots, int64_t n, double* rho,
+                       const DevState* st, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    g = std::min<int64_t>(g, 4096);
+    k_rho_reduce<<<(unsigned)g, 256, 0, s>>>(part, nslots, n, rho, st);
+}
+
 void launch_stage2(const DevParams* prm, const ResPlan& rp, const double* part_col,
                    const double* part_scal, const double* S, const double* pp_part,
                    const double* feas_part, double* colpart, double* nu, int p, DevState* st,
-                   hipStream_t s) {
+                   hipStream_t s, const double* nu_cur) {
     const int ng = col_groups(rp.nrb);
     k_colreduce<<<dim3((2 * p + 63) / 64, ng), 256, 0, s>>>(part_col, rp.nrb, p, colpart, st);
     k_stage2<<<1, 1024, 0, s>>>(prm, part_scal, rp.nrb * rp.ncb, S, pp_part, kkt_partials(p),
-                                feas_part,
-                                colpart, ng, nu, p, st);
+                                feas_part, colpart, ng, nu, p, st, nu_cur);
 }
 
 void launch_update(int dtype, void* X, const void* GL, int64_t n, int p, const double* nu,

@@ -112,6 +112,7 @@ class SolveOptions:
     check_every: int = 50
     use_graph: bool = True
     profile: bool = False
+    fused: bool = False
     beta: float = 1.0
     eta0: float = 1.0
     eta_const: float = 1.0
@@ -132,6 +133,7 @@ class SolveOptions:
         o.check_every = int(self.check_every)
         o.use_graph = 1 if self.use_graph else 0
         o.profile = 1 if self.profile else 0
+        o.fused = 1 if self.fused else 0
         o.beta = float(self.beta)
         o.eta0 = float(self.eta0)
         o.eta_const = float(self.eta_const)

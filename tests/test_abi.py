@@ -82,7 +82,17 @@ def test_workspace_size_host_only():
     opt.precision = L.PREC_FP32
     s32 = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
     assert s64 > 0 and s32 > 0 and s64m >= s64 + 2 * 1000 * 10 * 8
-    assert lib.stf_workspace_size(ctypes.byref(ok), None) == max(s64m, s32)
+    # the single-pass form keeps a second iterate and the row partials of rho
+    opt.fused = 1
+    s32f = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    opt.precision = L.PREC_FP64
+    s64f = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    opt.variant = L.MOPTQR
+    s64mf = lib.stf_workspace_size(ctypes.byref(ok), ctypes.byref(opt))
+    assert s32f >= s32 + 1000 * 10 * 8 and s64f >= s64 + 1000 * 10 * 8
+    # without options: room for every form
+    assert lib.stf_workspace_size(ctypes.byref(ok), None) == max(s64mf, s32f)
+    assert max(s64mf, s32f) >= max(s64m, s32, s64f)
 
 
 def test_invalid_arguments_rejected_before_device_work():
@@ -202,3 +212,50 @@ def test_problem_terms_and_comparator_host_checks():
     ex.gamma = 1.0
     probs = (L.StfProblem * 1)(ex)
     assert lib.stf_batched_workspace_size(1, vp(probs), None) == 0
+
+
+def test_single_pass_form_host_checks():
+    """The single-pass form (options.fused) needs eta^k before the pass (the
+    lagged pair, not eta_D), p > 64, PLAM / PCAL and the float64 or MIXED32
+    precision (p <= 384 there); the rest is refused before any device work."""
+    lib = L.load()
+    res = L.StfResult()
+    ok = _problem(n=4000, p=100)
+
+    def rc_of(o, prob=ok):
+        return lib.stf_solve(ctypes.byref(prob), ctypes.c_void_p(1), ctypes.byref(o),
+                             ctypes.c_void_p(1), 1, None, None, ctypes.byref(res), None)
+
+    o = _valid_options(L.PREC_FP64)
+    o.fused, o.bb_index = 1, L.BB_LAGGED
+    assert rc_of(o) == L.E_WORKSPACE            # accepted: only the workspace is short
+    o.precision = L.PREC_MIXED32
+    assert rc_of(o) == L.E_WORKSPACE
+    for prec in (L.PREC_FP32, L.PREC_MIXED):
+        o.precision = prec
+        assert rc_of(o) == L.E_UNSUPPORTED
+    o.precision = L.PREC_FP64
+    o.bb_index = L.BB_STANDARD
+    assert rc_of(o) == L.E_UNSUPPORTED
+    o.bb_index, o.eta_rule = L.BB_LAGGED, L.ETA_DIFF
+    assert rc_of(o) == L.E_UNSUPPORTED
+    o.eta_rule = L.ETA_BB2
+    assert rc_of(o) == L.E_WORKSPACE
+    o.variant = L.MOPTQR
+    assert rc_of(o) == L.E_UNSUPPORTED
+    o.variant = L.PLAM
+    o.mult_rule = L.MULT_DUAL
+    assert rc_of(o) == L.E_WORKSPACE
+    assert rc_of(o, _problem(n=4000, p=64)) == L.E_UNSUPPORTED
+    o.precision = L.PREC_MIXED32
+    assert rc_of(o, _problem(n=4000, p=416)) == L.E_UNSUPPORTED
+    assert rc_of(o, _problem(n=4000, p=384)) == L.E_WORKSPACE
+    # not in the batched solver
+    vp = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    probs = (L.StfProblem * 1)(ok)
+    opts = (L.StfOptions * 1)(_valid_options())
+    opts[0].fused = 1
+    ptrs = (ctypes.c_void_p * 1)(1)
+    bres = (L.StfResult * 1)()
+    assert lib.stf_solve_batched(1, vp(probs), vp(ptrs), vp(opts), ctypes.c_void_p(1), 1,
+                                 vp(bres), None) == L.E_UNSUPPORTED

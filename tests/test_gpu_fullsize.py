@@ -9,6 +9,9 @@ groups, the 1024-thread Hartree passes).
   each on 16 cores).
 * MIXED: iterates after 3 steps, 1e-5 * k as for the small grids.
 * the Gram step at full size against the float64 product of the same inputs.
+* the single-pass form (options.fused, lagged Barzilai-Borwein pair) in FP64
+  and MIXED32 after 3 steps against the oracle run with the lagged pair, at
+  the same bounds.
 """
 import pytest
 import torch
@@ -30,14 +33,15 @@ def c5():
     return prob, x0, OracleProblem(prob)
 
 
-def _opts(prob, k, precision):
+def _opts(prob, k, precision, fused=False):
     eta0 = BETA + prob.s_bound
+    bb = "lagged" if fused else "standard"
     o = O.Options(variant="pcal", beta=BETA, eta_rule="abb", eta0=eta0, eta_const=2 * eta0,
-                  tol=0.0, max_iter=k, mult="psi_phi", bb_index="standard", orth_final=False,
+                  tol=0.0, max_iter=k, mult="psi_phi", bb_index=bb, orth_final=False,
                   record_iterates=list(range(1, k + 1)))
     g = S.SolveOptions(variant="pcal", mult="psi_phi", eta_rule="abb", precision=precision,
                        beta=BETA, eta0=eta0, tol=0.0, max_iter=k, orth_final=False,
-                       check_every=k, use_graph=True)
+                       check_every=k, use_graph=True, bb_index=bb, fused=fused)
     return o, g
 
 
@@ -102,3 +106,25 @@ def test_fullsize_gram(c5):
     errW = rel(to_np(Wg), x0.T @ G)
     print(f"64^3 p=256 Gram: rel err S {errS:.2e} W {errW:.2e}")
     assert errS <= 1e-13 and errW <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def oracle_iterates_lagged(c5):
+    prob, x0, op = c5
+    o, _ = _opts(prob, 3, "fp64", fused=True)
+    return O.solve(op, x0, o).iterates
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed32"])
+def test_fullsize_fused_iterates(c5, oracle_iterates_lagged, precision):
+    prob, x0, _ = c5
+    k = 3
+    _, g = _opts(prob, k, precision, fused=True)
+    res, X = _gpu(prob, x0, g)
+    ref = oracle_iterates_lagged[k]
+    err, emax = rel(X, ref), maxrel(X, ref)
+    print(f"64^3 p=256 fused {precision}: relative iterate error after {k} steps = {err:.2e} "
+          f"(elementwise {emax:.2e})")
+    assert res["iters"] == k
+    bound = 1e-10 if precision == "fp64" else 1e-5 * k
+    assert err <= bound and emax <= bound
