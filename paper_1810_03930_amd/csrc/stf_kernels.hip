@@ -30,6 +30,7 @@ namespace stf {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mma;
 template <> struct Mma<double> {
@@ -1429,6 +1430,15 @@ __global__ __launch_bounds__(256) void k_residual_bf6(
 }
 
 
+// Order LDS writes of a wave before its later LDS reads of other lanes' data
+// (a wave's LDS operations complete in issue order; this keeps the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Rows per wave of the LDS-resident split-bf16 residual pass (64: four waves
 // and one wave per SIMD; 32: eight waves, two per SIMD).
 constexpr int kMixRW = 32;
@@ -1444,6 +1454,12 @@ constexpr int kMixRW = 32;
 // Psi).
 // FU = true: the single-pass form, as in body_residual (X^{k+1} to Xn, row
 // sums of its squares over the workgroup's 64 columns to rho_part[cb][r]).
+// Wide epilogue (PKMAX <= 256, where the LDS has room): a wave stages its
+// product rows 16 at a time in LDS and reads them back row-major, so that a
+// lane holds 4 consecutive columns and every load and store of G, X,
+// gradL^{k-1}, gradL (and X^{k+1}) is a 16-byte vector (a wave instruction
+// covers 4 rows x 256 bytes); the G, X and gradL^{k-1} of the first 16 rows
+// are loaded before the K loop, those of the next 16 while the first are used.
 template <int PKMAX, int RW, bool FU = false>
 __device__ __forceinline__ void body_residual_bf6_lds(
     const float* __restrict__ X, float* __restrict__ G, const float* __restrict__ Gprev,
@@ -1457,7 +1473,10 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     constexpr int NW = 256 / RW;   // waves
     constexpr int NT = 64 * NW;    // threads
     constexpr int IT = RW / 16;    // 16-row MFMA tiles per wave
+    constexpr bool WE = PKMAX <= 256 && RW == 32;
+    constexpr int kPP = 68;        // LDS pitch (floats) of the staged product rows
     __shared__ __attribute__((aligned(16))) __bf16 Ms[3 * 64 * LP];
+    __shared__ __attribute__((aligned(16))) float Ps[WE ? NW * 16 * kPP : 4];
     __shared__ double sh[8];
     __shared__ double scol[NW][2][64];
     const int lid = xcd_remap(bid_, nblk_);
@@ -1466,6 +1485,10 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const int lr = lane & 15, g = lane >> 4;
     const int cblk = cb * 64;
     const size_t tot = (size_t)prow * pk;
+    // wide epilogue: lane (rq, cq) takes rows 4 s + rq of a 16-row group and
+    // the 4 columns cw .. cw + 3
+    const int rq = lane >> 4, cq = lane & 15;
+    const int cw = cblk + 4 * cq;
     {
         const int nv = pk / 8;
         for (int e = tid; e < 3 * 64 * nv; e += NT) {
@@ -1478,14 +1501,15 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     const int k = st->iter;
     const bool have_prev = k >= 1;
     const double rinv_eta = 1.0 / st->eta;
+    // per-column constants: columns cblk + 16 j + lr (MFMA layout), or, in the
+    // wide epilogue, cw + j.  The single-pass form updates in float32
+    // arithmetic (the iterate is float32) with the reciprocals of eta^k, nu^k
     bool cok[4];
     double onu[4];
-    // single-pass form: the update in float32 arithmetic (the iterate is
-    // float32), with the reciprocals of eta^k and nu^k
     float rnu[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int c = cblk + j * 16 + lr;
+        const int c = WE ? cw + j : cblk + j * 16 + lr;
         cok[j] = c < p;
         onu[j] = (have_prev && cok[j]) ? 1.0 - nu[c] : 0.0;
         rnu[j] = (FU && cok[j]) ? (float)(1.0 / nu_cur[c]) : 1.f;
@@ -1561,6 +1585,42 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                 for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mm, acc[i][j]);
             }
         };
+        // wide epilogue: 16-byte slices of rows of G, X and gradL^{k-1}
+        // (columns past p read zero and their stores are dropped)
+        auto wld = [&](__amdgpu_buffer_rsrc_t r, int row) -> f4 {
+            const uint32_t rbyte = (uint32_t)row * rowb;
+            if (vec) return buf_ld16<float>(r, cok[0] ? rbyte + (uint32_t)cw * 4u : kBufOob);
+            f4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[e] = buf_ldf(r, cok[e] ? rbyte + (uint32_t)(cw + e) * 4u : kBufOob);
+            return v;
+        };
+        auto wst = [&](__amdgpu_buffer_rsrc_t r, int row, f4 v) {
+            const uint32_t rbyte = (uint32_t)row * rowb;
+            if (vec) {
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    __builtin_bit_cast(v4u, v), r, cok[0] ? rbyte + (uint32_t)cw * 4u : kBufOob,
+                    0, 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __float_as_uint(v[e]), r,
+                        cok[e] ? rbyte + (uint32_t)(cw + e) * 4u : kBufOob, 0, 0);
+            }
+        };
+        f4 wg[IT][4], wx[IT][4], wp[IT][4];
+        auto wload = [&](int i) {
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int row = i * 16 + 4 * s2 + rq;
+                wg[i][s2] = wld(bg, row);
+                wx[i][s2] = wld(bx, row);
+                wp[i][s2] = have_prev ? wld(bp, row) : f4{0.f, 0.f, 0.f, 0.f};
+            }
+        };
+        if constexpr (WE) wload(0);
         load_x(0, xa[0]);
         if (32 < pk) load_x(32, xa[1]);
         for (int kc = 0; kc < pk; kc += 64) {
@@ -1578,6 +1638,59 @@ __device__ __forceinline__ void body_residual_bf6_lds(
         const float rinv_f = (float)rinv_eta;
         float tss = 0.f, tsy = 0.f, tyy = 0.f;
         float txg[4] = {0.f, 0.f, 0.f, 0.f}, tgg[4] = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (WE) {
+            float* Pw = Ps + wave * (16 * kPP);
+            float onu_f[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) onu_f[e] = (float)onu[e];
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                // the product rows i*16 .. i*16 + 15 of the wave through LDS
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        Pw[(4 * g + q) * kPP + j * 16 + lr] = acc[i][j][q];
+                // the next group's loads, in flight during this group's arithmetic
+                if (i + 1 < IT) wload(i + 1);
+                wave_lds_sync();
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const int row = i * 16 + 4 * s2 + rq;
+                    const f4 pr = *(const f4*)&Pw[(4 * s2 + rq) * kPP + 4 * cq];
+                    const f4 gv = wg[i][s2], xv = wx[i][s2], pv = wp[i][s2];
+                    f4 gl, xn;
+                    float rs = 0.f;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        gl[e] = gv[e] - pr[e];
+                        if constexpr (FU) {
+                            xn[e] = (xv[e] - gl[e] * reta_cur) * rnu[e];
+                            rs += xn[e] * xn[e];
+                        }
+                        txg[e] += xv[e] * gl[e];
+                        tgg[e] += gl[e] * gl[e];
+                        if (have_prev) {
+                            const float sd = onu_f[e] * xv[e] - pv[e] * rinv_f;
+                            const float yd = gl[e] - pv[e];
+                            tss += sd * sd;
+                            tsy += sd * yd;
+                            tyy += yd * yd;
+                        }
+                    }
+                    wst(bg, row, gl);
+                    if constexpr (FU) {
+                        // columns past p hold x = gl = 0: xn = 0
+                        wst(bn, row, xn);
+#pragma unroll
+                        for (int o = 8; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 16);
+                        const int64_t r = r0 + row;
+                        if (cq == 0 && r < n) rho_part[(size_t)cb * n + r] = (double)rs;
+                    }
+                }
+                wave_lds_sync();
+            }
+        } else {
         constexpr int NR = IT * 4;
         float eg[2][4], ex[2][4], ep[2][4];
         auto eoff = [&](int rw, int j) {
@@ -1637,6 +1750,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                 }
             }
         }
+        }  // !WE
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             cxg[j] += (double)txg[j];
@@ -1656,8 +1770,9 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     if (g == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            scol[wave][0][j * 16 + lr] = cxg[j];
-            scol[wave][1][j * 16 + lr] = cgg[j];
+            const int cc = WE ? 4 * cq + j : j * 16 + lr;
+            scol[wave][0][cc] = cxg[j];
+            scol[wave][1][cc] = cgg[j];
         }
     }
     __syncthreads();
