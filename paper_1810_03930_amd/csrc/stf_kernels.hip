@@ -2191,8 +2191,14 @@ __device__ __forceinline__ void body_residual(
     constexpr int NT = 128 * WC;       // threads: 2 x WC waves
     constexpr int WTC = BC / WC;       // columns per wave
     constexpr int JT = WTC / 16;       // 16-column MFMA tiles per wave
-    __shared__ T Xs[128 * XS];
-    __shared__ T Ms[KC * MST];
+    // float64: the K-chunks go straight from global memory into two LDS
+    // buffers (buffer_load ... lds), so the next chunk is in flight while this
+    // one is used, without staging registers and with one barrier per chunk
+    constexpr bool DL = sizeof(T) == 8 && WC == 2;
+    __shared__ T Xs[DL ? 1 : 128 * XS];
+    __shared__ T Ms[DL ? 1 : KC * MST];
+    __shared__ __attribute__((aligned(16))) double XsD[DL ? 2 * 128 * 16 : 2];
+    __shared__ __attribute__((aligned(16))) double MsD[DL ? 2 * 16 * 64 : 2];
     __shared__ double sh[2 * WC];
     __shared__ double scol[2][2][BC];
     const int nwg = nblk_;
@@ -2296,8 +2302,55 @@ __device__ __forceinline__ void body_residual(
         }
     };
 
+    // Direct chunk loads (float64): the X chunk of a 128-row tile (128 rows x
+    // 16 doubles) is 16 wave loads of 8 rows x 128 bytes, the M chunk (16 rows
+    // of M x the block's 64 columns) 8 wave loads of 2 rows x 512 bytes; a lane
+    // moves 16 bytes (2 doubles) and lands at its lane's place in the wave's
+    // 1 KiB of LDS.  Bank spread by XOR: X row r holds its k-pair j at slot
+    // j ^ ((r >> 1) & 7), M row k its column pair c at slot c ^ ((k & 1) << 3).
+    // Rows past n (X) or p (M) read zero through the buffer range check; the
+    // entries of X past p in a row read the next row's (finite) values, which
+    // meet M's zero rows, and M's columns past p only reach output columns
+    // that are never stored.
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const __amdgpu_buffer_rsrc_t rm = buf_rsrc(Mp, (uint32_t)((size_t)p * p * 8));
+    auto issue = [&](int64_t rtl, int kc, int b) {
+        if constexpr (DL) {
+            const int64_t rr0 = rtl * 128;
+            const int nvr = (int)max<int64_t>(0, min<int64_t>(128, n - rr0));
+            const __amdgpu_buffer_rsrc_t rx =
+                buf_rsrc((const double*)X + (size_t)min<int64_t>(rr0, n) * p,
+                         (uint32_t)nvr * (uint32_t)p * 8u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = wu * 4 + u;
+                const int row = 8 * t + (lane >> 3);
+                const int js = (lane & 7) ^ ((row >> 1) & 7);
+                const uint32_t off = ((uint32_t)row * (uint32_t)p + (uint32_t)(kc + 2 * js)) * 8u;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rx, (__attribute__((address_space(3))) void*)(XsD + b * 2048 + t * 128), 16,
+                    off, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = wu * 2 + u;
+                const int kr = 2 * t + (lane >> 5);
+                const int cps = (lane & 31) ^ ((lane >> 5) << 3);
+                const uint32_t off =
+                    ((uint32_t)(kc + kr) * (uint32_t)p + (uint32_t)(cblk + 2 * cps)) * 8u;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rm, (__attribute__((address_space(3))) void*)(MsD + b * 1024 + t * 128), 16,
+                    off, 0, 0, 0);
+            }
+        }
+    };
     int64_t rt = rb;
-    if (rt < nrt) load_chunk(rt * 128, 0);
+    int dbuf = 0;
+    if constexpr (DL) {
+        if (rt < nrt) issue(rt, 0, 0);
+    } else {
+        if (rt < nrt) load_chunk(rt * 128, 0);
+    }
     for (; rt < nrt; rt += nrb) {
         const int64_t r0 = rt * 128;
         typename Mma<T>::acc a1[4][JT];
@@ -2307,7 +2360,42 @@ __device__ __forceinline__ void body_residual(
             for (int j = 0; j < JT; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a1[i][j][q] = 0;
-        for (int kc = 0; kc < p; kc += KC) {
+        if constexpr (DL) {
+            for (int kc = 0; kc < p; kc += 16) {
+                // this chunk landed (every wave's loads), and every wave is done
+                // with the other buffer
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (kc + 16 < p)
+                    issue(rt, kc + 16, dbuf ^ 1);
+                else if (rt + nrb < nrt)
+                    issue(rt + nrb, 0, dbuf ^ 1);
+                const double* xs = XsD + dbuf * 2048;
+                const double* ms = MsD + dbuf * 1024;
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const int k = kk + lk;
+                    double a[4], b[JT];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = wr * 64 + i * 16 + lr;
+                        a[i] = xs[row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1)];
+                    }
+#pragma unroll
+                    for (int j = 0; j < JT; ++j) {
+                        const int col = wc * WTC + j * 16 + lr;
+                        b[j] = ms[k * 64 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < JT; ++j)
+                            a1[i][j] = Mma<T>::run((T)a[i], (T)b[j], a1[i][j]);
+                }
+                dbuf ^= 1;
+            }
+        }
+        for (int kc = 0; kc < (DL ? 0 : p); kc += KC) {
             __syncthreads();
             store_chunk();
             __syncthreads();
