@@ -819,8 +819,17 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
     constexpr int VX = 16 / (int)sizeof(T);
     constexpr int NV = KC * 128 / VX / 256;
     constexpr int FLUSH = 256 / KC;
-    __shared__ T Zs[KC * LS];
-    __shared__ T Ys[KC * LS];
+    // float64: the chunk's 16 rows of the Z and Y panels go straight from
+    // global memory into two LDS buffers (buffer_load ... lds; one 1 KiB wave
+    // load per panel row, a lane's 16 bytes at its lane's place), the next
+    // chunk in flight while this one is used, one barrier per chunk.  Row k
+    // holds its column pair c at slot c ^ ((k & 1) << 3), so the four rows of
+    // an MFMA operand read spread over both halves of the banks.
+    constexpr bool DL = sizeof(T) == 8;
+    __shared__ T Zs[DL ? 1 : KC * LS];
+    __shared__ T Ys[DL ? 1 : KC * LS];
+    __shared__ __attribute__((aligned(16))) double ZsD[DL ? 2 * 16 * 128 : 2];
+    __shared__ __attribute__((aligned(16))) double YsD[DL ? 2 * 16 * 128 : 2];
     const int nwg = nblk_;
     const int lid = xcd_remap(bid_, nwg);
     const int tile = lid % n_tiles, c = lid / n_tiles;
@@ -893,6 +902,75 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
     double sq[VX];
 #pragma unroll
     for (int v = 0; v < VX; ++v) sq[v] = 0.0;
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    auto issue = [&](int64_t kb, int b) {
+        if constexpr (DL) {
+            const uint32_t ob = (uint32_t)(kb - k0) * rowb;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kr = wu * 4 + u;
+                const int cps = lane ^ ((kr & 1) << 3);
+                const uint32_t oz = ob + (uint32_t)kr * rowb + (uint32_t)(zc + 2 * cps) * 8u;
+                const uint32_t oy = ob + (uint32_t)kr * rowb + (uint32_t)(yc + 2 * cps) * 8u;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rz, (__attribute__((address_space(3))) void*)(ZsD + b * 2048 + kr * 128), 16,
+                    oz, 0, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    ry, (__attribute__((address_space(3))) void*)(YsD + b * 2048 + kr * 128), 16,
+                    oy, 0, 0, 0);
+            }
+        }
+    };
+    if constexpr (DL) {
+        // rows past the chunk and columns past the row (the next row's values,
+        // or zero past the range) only reach partial entries the reduction skips
+        int dbuf = 0;
+        if (active) issue(k0, 0);
+        for (int64_t kb = k0; active && kb < k1; kb += 16) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (kb + 16 < k1) issue(kb + 16, dbuf ^ 1);
+            const double* zs = ZsD + dbuf * 2048;
+            const double* ys = YsD + dbuf * 2048;
+            if (csq) {
+                // rows wave, wave + 4, ... of the lane's column pair
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const int kr = wave + 4 * s2;
+                    const int slot = lane ^ ((kr & 1) << 3);
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const double y = ys[kr * 128 + 2 * slot + v];
+                        sq[v] += (yc + 2 * lane + v < p) ? y * y : 0.0;
+                    }
+                }
+            }
+            if (!below) {
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const int k = kk + lk;
+                    const int sw = (k & 1) << 3;
+                    double a[4], b[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int col = wi * 64 + i * 16 + lr;
+                        a[i] = zs[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int col = wj * 64 + j * 16 + lr;
+                        b[j] = ys[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = Mma<T>::run((T)a[i], (T)b[j], acc[i][j]);
+                }
+            }
+            dbuf ^= 1;
+        }
+    } else {
     if (active) load(k0);
     int step = 0;
     for (int64_t kb = k0; active && kb < k1; kb += KC, ++step) {
@@ -937,6 +1015,7 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
             }
         }
     }
+    }  // !DL
     if (csq) {
         // [chunk][wave][column] partials (4 threads share a column pair)
         const int col = (tid % (128 / VX)) * VX;
