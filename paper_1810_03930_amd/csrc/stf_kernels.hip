@@ -2005,6 +2005,127 @@ __global__ __launch_bounds__(256) void k_dense_grad(const TA* __restrict__ A,
             }
 }
 
+// Dense gradient in float64 arithmetic for p > 64: G = A X (+ Glin), A stored
+// as TA (float32 widened exactly, or float64).  A workgroup owns 128 rows x
+// 128 columns of G, four waves of 64 x 64 (4 x 4 tiles of the float64 MFMA);
+// K advances 16 at a time through two LDS buffers filled straight from global
+// memory (buffer_load ... lds, 16 bytes a lane), the next K step in flight
+// while this one is used, one barrier per step.  A panel: 128 rows x 16 k,
+// row r holding its k-group s (4 floats or 2 doubles) at slot
+// s ^ ((r >> 2) & 3) (float32) or s ^ ((r >> 1) & 7) (float64); X panel: 16
+// rows x 128 columns, row k holding its column pair c at slot
+// c ^ ((k & 1) << 3), so the MFMA operand reads spread over the banks.  Rows
+// of A past n and rows of X past n read zero through the range check; A's
+// entries past n in a row (the next row's finite values) meet X's zero rows,
+// and X's columns past p only reach columns of G that are not stored.
+template <typename TA>
+__global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
+                                                     const double* __restrict__ X,
+                                                     double* __restrict__ G, int64_t n, int p,
+                                                     int nbp, const double* __restrict__ glin,
+                                                     const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    constexpr int ES = (int)sizeof(TA);
+    constexpr int AP = 128 * 16;     // A panel elements (TA) per buffer
+    __shared__ __attribute__((aligned(16))) TA As[2 * AP];
+    __shared__ __attribute__((aligned(16))) double Xs[2 * 16 * 128];
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int bi = lid / nbp, bj = lid % nbp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    const int64_t r0 = (int64_t)bi * 128;
+    const int c0 = bj * 128;
+    const int nvr = (int)max<int64_t>(0, min<int64_t>(128, n - r0));
+    const uint32_t arow = (uint32_t)n * (uint32_t)ES;
+    const __amdgpu_buffer_rsrc_t ra =
+        buf_rsrc(A + (size_t)min<int64_t>(r0, n) * n, (uint32_t)nvr * arow);
+    // A panel rows per wave load: 16 (float32: 4 lanes a row) or 8 (float64)
+    constexpr int RPL = 64 / (64 / ES);   // lanes per row: 4 (float32) or 8 (float64)
+    constexpr int RPI = 64 / RPL;         // rows per wave load: 16 or 8
+    constexpr int NAI = 128 / RPI / 4;    // A wave loads per wave: 2 or 4
+    auto issue = [&](int64_t kb, int b) {
+#pragma unroll
+        for (int u = 0; u < NAI; ++u) {
+            const int t = wu * NAI + u;
+            const int row = RPI * t + lane / RPL;
+            const int slot = lane % RPL;
+            const int sg = (ES == 4) ? (slot ^ ((row >> 2) & 3)) : (slot ^ ((row >> 1) & 7));
+            const uint32_t off = (uint32_t)row * arow + (uint32_t)(kb + sg * (16 / ES)) * ES;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                ra, (__attribute__((address_space(3))) void*)(As + b * AP + t * (1024 / ES)), 16,
+                off, 0, 0, 0);
+        }
+        const int nxr = (int)max<int64_t>(0, min<int64_t>(16, n - kb));
+        const __amdgpu_buffer_rsrc_t rx =
+            buf_rsrc(X + (size_t)min<int64_t>(kb, n) * p, (uint32_t)nxr * (uint32_t)p * 8u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kr = wu * 4 + u;
+            const int cps = lane ^ ((kr & 1) << 3);
+            const uint32_t off = ((uint32_t)kr * (uint32_t)p + (uint32_t)(c0 + 2 * cps)) * 8u;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rx, (__attribute__((address_space(3))) void*)(Xs + b * 2048 + kr * 128), 16,
+                off, 0, 0, 0);
+        }
+    };
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.0;
+    int dbuf = 0;
+    issue(0, 0);
+    for (int64_t kb = 0; kb < n; kb += 16) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (kb + 16 < n) issue(kb + 16, dbuf ^ 1);
+        const TA* as = As + dbuf * AP;
+        const double* xs = Xs + dbuf * 2048;
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int k = kk + lk;
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = wi * 64 + i * 16 + lr;
+                int pos;
+                if constexpr (ES == 4)
+                    pos = row * 16 + (((k >> 2) ^ ((row >> 2) & 3)) << 2) + (k & 3);
+                else
+                    pos = row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1);
+                a[i] = (double)as[pos];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = wj * 64 + j * 16 + lr;
+                b[j] = xs[k * 128 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = Mma<double>::run(a[i], b[j], acc[i][j]);
+        }
+        dbuf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + wi * 64 + i * 16 + Mma<double>::row(lk, q);
+                const int c = c0 + wj * 64 + j * 16 + lr;
+                if (r < n && c < p) {
+                    const size_t idx = (size_t)r * p + c;
+                    G[idx] = glin ? acc[i][j][q] + glin[idx] : acc[i][j][q];
+                }
+            }
+}
+
 // Dense gradient G = A X (+ Glin) for float32 A and X on bf16 MFMA
 // (v_mfma_f32_16x16x32_bf16), the reduced-precision forms of the dense
 // Rayleigh-Ritz problem.  NPROD = 1: one product of the bf16 roundings;
@@ -3762,14 +3883,23 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
                                                   (float*)G, n, p, ncb, gl, st);
             return;
         }
+        if (dtype == STF_F64 && p > 64) {
+            // float64 arithmetic (a float32 A widened exactly on load), 128 x 128
+            // tiles staged through LDS
+            const int nbp = (p + 127) / 128;
+            const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
+            if (prob->A_dtype == STF_F32)
+                k_dense_f64<float><<<nwg, 256, 0, s>>>((const float*)prob->A, (const double*)X,
+                                                       (double*)G, n, p, nbp, gl, st);
+            else
+                k_dense_f64<double><<<nwg, 256, 0, s>>>((const double*)prob->A,
+                                                        (const double*)X, (double*)G, n, p, nbp,
+                                                        gl, st);
+            return;
+        }
         if (dtype == STF_F64 && prob->A_dtype == STF_F32) {
             // float64 arithmetic on a float32 A (widened exactly on load)
-            if (p > 64) {
-                const int nbp = (p + 127) / 128;
-                const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
-                k_dense_grad<double, 4, float><<<nwg, 256, 0, s>>>(
-                    (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
-            } else {
+            {
                 const int nbp = (p + 31) / 32;
                 const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
                 k_dense_grad<double, 1, float><<<nwg, 256, 0, s>>>(

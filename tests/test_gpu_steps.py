@@ -86,6 +86,19 @@ def test_gradient_dense(n, p, dt):
     assert maxrel(to_np(g), g_ref) <= (tol if dt == torch.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("n,p", [(520, 130), (1000, 200), (2051, 77)])
+def test_gradient_dense_float32_operator_float64_arithmetic(n, p):
+    """A stored in float32, X and G in float64: the float64 product widens A
+    exactly, so it matches the float64 product of the rounded A to 1e-13
+    (ragged n and p, several 128 x 128 tiles and 16-deep K steps)."""
+    prob, x0 = W.dense_quadratic(n=n, p=p, dtype=np.float32, power_iters=5)
+    op = OracleProblem(prob)
+    g_ref = op.grad(x0)
+    dp = S.DeviceProblem.from_host(prob, A_dtype=torch.float32)
+    g = to_np(S.gradient(dp, to_dev(x0, torch.float64)))
+    assert rel(g, g_ref) <= 1e-13 and maxrel(g, g_ref) <= 1e-13
+
+
 @pytest.mark.parametrize("kind,shape", [("stencil1d", 5003), ("stencil1d", 20000),
                                         ("stencil3d", (16, 16, 16)), ("stencil3d", (20, 18, 17)),
                                         ("stencil3d", (64, 64, 64))])
