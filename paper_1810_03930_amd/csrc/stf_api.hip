@@ -157,6 +157,9 @@ Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fus
     } else {
         L.colsq = L.nu2 = L.rhopart = (size_t)-1;
     }
+    L.xsplit = (prob->kind == STF_KIND_DENSE && precision != STF_PREC_FP64)
+                   ? take((size_t)4 * p * dense_npad(n))
+                   : (size_t)-1;
     L.total = off;
     return L;
 }
@@ -225,6 +228,7 @@ static void enqueue_grad_core(const stf_problem* prob, const Ws& w, int dtype, c
                               const double* Xm = nullptr, int dense_prod = 0) {
     GradExtra ex = grad_extra(prob, needs_rho(prob) ? w.at<double>(w.L.rho) : nullptr);
     ex.dense_prod = dense_prod;
+    if (dense_prod == 3 && w.L.xsplit != (size_t)-1) ex.xsplit = w.base + w.L.xsplit;
     if (prob->B) {
         void* T = w.base + w.L.gtmp;
         launch_grad(prob, dtype, X, T, w.at<double>(w.L.phi), ex, st, s, Xm);

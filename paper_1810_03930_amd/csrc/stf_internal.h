@@ -56,7 +56,10 @@ struct GradExtra {
     double gamma;         // exchange weight
     int32_t block;        // 1D: order of the tridiagonal blocks (0: one block)
     int32_t dense_prod;   // dense float32 A X: 0 = float32 MFMA, 1 = bf16, 3 = split bf16
+    void* xsplit;         // split bf16 X^T (2 x p x dense_npad(n) bf16) for dense_prod 3, or null
 };
+// k padding of the split X^T of the split-bf16 dense product
+inline int64_t dense_npad(int64_t n) { return (n + 63) / 64 * 64; }
 
 // Internal status of a reduced-precision phase that reached switch_tol, and
 // (batched solves) of one whose float64 continuation has taken over.
@@ -116,6 +119,7 @@ struct Layout {
     size_t colsq;         // single-pass form: Gram chunks x 4 x p column sums of G^2
     size_t nu2;           // single-pass form: nu^k (p float64), found before the pass
     size_t rhopart;       // single-pass form: row partials of rho, slots x n float64
+    size_t xsplit;        // dense kind, reduced precision: split bf16 X^T (2 x p x npad)
     size_t total;
     GramPlan gram;        // plan for the iteration dtype
     GramPlan gram64;      // plan for float64 (CholeskyQR2 / evaluation)

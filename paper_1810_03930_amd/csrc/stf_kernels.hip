@@ -2005,30 +2005,34 @@ __global__ __launch_bounds__(256) void k_dense_grad(const TA* __restrict__ A,
             }
 }
 
-// Dense gradient in float64 arithmetic for p > 64: G = A X (+ Glin), A stored
-// as TA (float32 widened exactly, or float64).  A workgroup owns 128 rows x
-// 128 columns of G, four waves of 64 x 64 (4 x 4 tiles of the float64 MFMA);
-// K advances 16 at a time through two LDS buffers filled straight from global
-// memory (buffer_load ... lds, 16 bytes a lane), the next K step in flight
-// while this one is used, one barrier per step.  A panel: 128 rows x 16 k,
-// row r holding its k-group s (4 floats or 2 doubles) at slot
-// s ^ ((r >> 2) & 3) (float32) or s ^ ((r >> 1) & 7) (float64); X panel: 16
-// rows x 128 columns, row k holding its column pair c at slot
-// c ^ ((k & 1) << 3), so the MFMA operand reads spread over the banks.  Rows
-// of A past n and rows of X past n read zero through the range check; A's
-// entries past n in a row (the next row's finite values) meet X's zero rows,
-// and X's columns past p only reach columns of G that are not stored.
-template <typename TA>
-__global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
-                                                     const double* __restrict__ X,
-                                                     double* __restrict__ G, int64_t n, int p,
-                                                     int nbp, const double* __restrict__ glin,
-                                                     const DevState* __restrict__ st) {
+// Dense gradient for p > 64 in the arithmetic of T (float64, or float32 on the
+// float32 MFMA): G = A X (+ Glin), A stored as TA (a float32 A is widened
+// exactly in the float64 form).  A workgroup owns 128 rows x 128 columns of
+// G, four waves of 64 x 64 (4 x 4 MFMA tiles); K advances 16 at a time
+// through two LDS buffers filled straight from global memory (buffer_load ...
+// lds, 16 bytes a lane), the next K step in flight while this one is used,
+// one barrier per step.  A panel: 128 rows x 16 k, row r holding its k-group
+// s (4 floats or 2 doubles) at slot s ^ ((r >> 2) & 3) (float32) or
+// s ^ ((r >> 1) & 7) (float64); X panel: 16 rows x 128 columns, row k holding
+// its column pair c at slot c ^ ((k & 1) << 3) (float64) or its column quad
+// at slot c ^ ((k & 3) << 2) (float32), so the MFMA operand reads spread over
+// the banks.  Rows of A past n and rows of X past n read zero through the
+// range check; A's entries past n in a row (the next row's finite values) meet
+// X's zero rows, and X's columns past p only reach columns of G that are not
+// stored.
+template <typename T, typename TA>
+__global__ __launch_bounds__(256, 2) void k_dense_mfma(const TA* __restrict__ A,
+                                                      const T* __restrict__ X,
+                                                      T* __restrict__ G, int64_t n, int p,
+                                                      int nbp, const double* __restrict__ glin,
+                                                      const DevState* __restrict__ st) {
     if (st && st->done) return;
     constexpr int ES = (int)sizeof(TA);
+    constexpr int XE = (int)sizeof(T);
     constexpr int AP = 128 * 16;     // A panel elements (TA) per buffer
+    constexpr int XV = 16 / XE;      // X elements per lane load: 2 doubles or 4 floats
     __shared__ __attribute__((aligned(16))) TA As[2 * AP];
-    __shared__ __attribute__((aligned(16))) double Xs[2 * 16 * 128];
+    __shared__ __attribute__((aligned(16))) T Xs[2 * 16 * 128];
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int bi = lid / nbp, bj = lid % nbp;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wi = wave >> 1, wj = wave & 1;
@@ -2040,10 +2044,12 @@ __global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
     const uint32_t arow = (uint32_t)n * (uint32_t)ES;
     const __amdgpu_buffer_rsrc_t ra =
         buf_rsrc(A + (size_t)min<int64_t>(r0, n) * n, (uint32_t)nvr * arow);
-    // A panel rows per wave load: 16 (float32: 4 lanes a row) or 8 (float64)
-    constexpr int RPL = 64 / (64 / ES);   // lanes per row: 4 (float32) or 8 (float64)
-    constexpr int RPI = 64 / RPL;         // rows per wave load: 16 or 8
+    constexpr int RPL = ES == 4 ? 4 : 8;  // lanes per A row (16 k of TA = 64 or 128 bytes)
+    constexpr int RPI = 64 / RPL;         // A rows per wave load: 16 or 8
     constexpr int NAI = 128 / RPI / 4;    // A wave loads per wave: 2 or 4
+    constexpr int XL = 128 / XV;          // lanes per X row: 64 (float64) or 32 (float32)
+    constexpr int XRI = 64 / XL;          // X rows per wave load: 1 or 2
+    constexpr int NXI = 16 / XRI / 4;     // X wave loads per wave: 4 or 2
     auto issue = [&](int64_t kb, int b) {
 #pragma unroll
         for (int u = 0; u < NAI; ++u) {
@@ -2058,24 +2064,26 @@ __global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
         }
         const int nxr = (int)max<int64_t>(0, min<int64_t>(16, n - kb));
         const __amdgpu_buffer_rsrc_t rx =
-            buf_rsrc(X + (size_t)min<int64_t>(kb, n) * p, (uint32_t)nxr * (uint32_t)p * 8u);
+            buf_rsrc(X + (size_t)min<int64_t>(kb, n) * p, (uint32_t)nxr * (uint32_t)p * XE);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kr = wu * 4 + u;
-            const int cps = lane ^ ((kr & 1) << 3);
-            const uint32_t off = ((uint32_t)kr * (uint32_t)p + (uint32_t)(c0 + 2 * cps)) * 8u;
+        for (int u = 0; u < NXI; ++u) {
+            const int t = wu * NXI + u;
+            const int kr = XRI * t + lane / XL;
+            const int slot = lane % XL;
+            const int cg = (XE == 8) ? (slot ^ ((kr & 1) << 3)) : (slot ^ ((kr & 3) << 2));
+            const uint32_t off = ((uint32_t)kr * (uint32_t)p + (uint32_t)(c0 + XV * cg)) * XE;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rx, (__attribute__((address_space(3))) void*)(Xs + b * 2048 + kr * 128), 16,
-                off, 0, 0, 0);
+                rx, (__attribute__((address_space(3))) void*)(Xs + b * 2048 + t * (1024 / XE)),
+                16, off, 0, 0, 0);
         }
     };
-    d4 acc[4][4];
+    typename Mma<T>::acc acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.0;
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
     int dbuf = 0;
     issue(0, 0);
     for (int64_t kb = 0; kb < n; kb += 16) {
@@ -2083,11 +2091,11 @@ __global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
         __syncthreads();
         if (kb + 16 < n) issue(kb + 16, dbuf ^ 1);
         const TA* as = As + dbuf * AP;
-        const double* xs = Xs + dbuf * 2048;
+        const T* xs = Xs + dbuf * 2048;
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             const int k = kk + lk;
-            double a[4], b[4];
+            T a[4], b[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = wi * 64 + i * 16 + lr;
@@ -2096,18 +2104,20 @@ __global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
                     pos = row * 16 + (((k >> 2) ^ ((row >> 2) & 3)) << 2) + (k & 3);
                 else
                     pos = row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1);
-                a[i] = (double)as[pos];
+                a[i] = (T)as[pos];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int col = wj * 64 + j * 16 + lr;
-                b[j] = xs[k * 128 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+                if constexpr (XE == 8)
+                    b[j] = xs[k * 128 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+                else
+                    b[j] = xs[k * 128 + (((col >> 2) ^ ((k & 3) << 2)) << 2) + (col & 3)];
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = Mma<double>::run(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 4; ++j) acc[i][j] = Mma<T>::run(a[i], b[j], acc[i][j]);
         }
         dbuf ^= 1;
     }
@@ -2117,11 +2127,11 @@ __global__ __launch_bounds__(256, 2) void k_dense_f64(const TA* __restrict__ A,
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t r = r0 + wi * 64 + i * 16 + Mma<double>::row(lk, q);
+                const int64_t r = r0 + wi * 64 + i * 16 + Mma<T>::row(lk, q);
                 const int c = c0 + wj * 64 + j * 16 + lr;
                 if (r < n && c < p) {
                     const size_t idx = (size_t)r * p + c;
-                    G[idx] = glin ? acc[i][j][q] + glin[idx] : acc[i][j][q];
+                    G[idx] = glin ? (T)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
                 }
             }
 }
@@ -2238,6 +2248,163 @@ __global__ __launch_bounds__(512) void k_dense_bf(const float* __restrict__ A,
                 for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
             }
         }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = r0 + wi * 64 + i * 16 + Mma<float>::row(g, q);
+                const int c = c0 + wj * 128 + j * 16 + lr;
+                if (r < n && c < p) {
+                    const size_t idx = (size_t)r * p + c;
+                    G[idx] = glin ? (float)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
+                }
+            }
+}
+
+// X^T split into bf16 h + l for the split-bf16 dense product: XhT, XlT are
+// p x npad ([column][k], npad a multiple of 64, zero for k >= n), through a
+// 64 x 64 LDS tile (coalesced reads of X rows, coalesced writes of X^T rows).
+__global__ __launch_bounds__(256) void k_split_xt(const float* __restrict__ X,
+                                                  __bf16* __restrict__ XhT,
+                                                  __bf16* __restrict__ XlT, int64_t n, int p,
+                                                  int64_t npad, const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ float t[64][65];
+    const int64_t k0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int kk = e >> 6, cc = e & 63;
+        const int64_t k = k0 + kk;
+        const int c = c0 + cc;
+        t[kk][cc] = (k < n && c < p) ? X[(size_t)k * p + c] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int cc = e >> 6, kk = e & 63;
+        const int c = c0 + cc;
+        const int64_t k = k0 + kk;
+        if (c < p && k < npad) {
+            const float x = t[kk][cc];
+            const __bf16 h = (__bf16)x;
+            XhT[(size_t)c * npad + k] = h;
+            XlT[(size_t)c * npad + k] = (__bf16)(x - (float)h);
+        }
+    }
+}
+
+// Split-bf16 dense product G = A X (+ Glin) with X split beforehand
+// (k_split_xt): three products Ah Xh + Ah Xl + Al Xh on the bf16 MFMA with
+// float32 accumulation.  A workgroup owns 128 rows x 512 columns (A is
+// streamed once for p <= 512), eight waves of 64 x 128; K advances 32 at a
+// time.  The A panel (128 x 32) is loaded into registers one step ahead and
+// split into LDS when staged; the X panels (512 columns x 32 k, h and l) go
+// straight from global memory into two LDS buffers (buffer_load ... lds), a
+// column's four 16-byte k-groups at slots g ^ ((col >> 2) & 3) so that the
+// operand reads spread over the banks.  Columns past p read zero (range
+// check); X^T is zero for k >= n.
+constexpr int kDPN = 512;
+__global__ __launch_bounds__(512) void k_dense_bfp(const float* __restrict__ A,
+                                                   const __bf16* __restrict__ XhT,
+                                                   const __bf16* __restrict__ XlT, int64_t npad,
+                                                   float* __restrict__ G, int64_t n, int p,
+                                                   int ncb, const double* __restrict__ glin,
+                                                   const DevState* __restrict__ st) {
+    if (st && st->done) return;
+    __shared__ __attribute__((aligned(16))) __bf16 La[2][kDGM * kDGP];
+    __shared__ __attribute__((aligned(16))) __bf16 Lx[2][2][kDPN * 32];
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int rb = lid / ncb, cb = lid % ncb;
+    const int64_t r0 = (int64_t)rb * kDGM;
+    const int c0 = cb * kDPN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 2, wj = wave & 3;   // 2 x 4 waves of 64 x 128
+    const int lr = lane & 15, g = lane >> 4;
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    // A loader: row (tid >> 2), k offset 8 (tid & 3)
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int64_t arow = r0 + ar;
+    const bool aok = arow < n;
+    float av[8];
+    auto load_a = [&](int64_t k0) {
+        const float* ap = A + (size_t)arow * n + k0 + ak;
+        if (aok && k0 + ak + 8 <= n && (n % 4) == 0) {
+            const float4 u = *(const float4*)ap;
+            const float4 w = *(const float4*)(ap + 4);
+            av[0] = u.x; av[1] = u.y; av[2] = u.z; av[3] = u.w;
+            av[4] = w.x; av[5] = w.y; av[6] = w.z; av[7] = w.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = (aok && k0 + ak + e < n) ? ap[e] : 0.f;
+        }
+    };
+    const int ncol = max(0, min(kDPN, p - c0));
+    const uint32_t xrange = (uint32_t)ncol * (uint32_t)npad * 2u;
+    const __amdgpu_buffer_rsrc_t rxh = buf_rsrc(XhT + (size_t)c0 * npad, xrange);
+    const __amdgpu_buffer_rsrc_t rxl = buf_rsrc(XlT + (size_t)c0 * npad, xrange);
+    // 32 wave loads per panel (16 columns x 64 bytes each), 4 per wave
+    auto issue_x = [&](int64_t k0, int b) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = wu * 4 + u;
+            const int col = 16 * t + (lane >> 2);
+            const int gs = (lane & 3) ^ ((col >> 2) & 3);
+            const uint32_t off = ((uint32_t)col * (uint32_t)npad + (uint32_t)(k0 + 8 * gs)) * 2u;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rxh, (__attribute__((address_space(3))) void*)(&Lx[b][0][t * 512]), 16, off, 0, 0,
+                0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rxl, (__attribute__((address_space(3))) void*)(&Lx[b][1][t * 512]), 16, off, 0, 0,
+                0);
+        }
+    };
+    f4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
+    int dbuf = 0;
+    load_a(0);
+    issue_x(0, 0);
+    for (int64_t k0 = 0; k0 < n; k0 += 32) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        {
+            bf8 h, l;
+            split2(av, h, l);
+            *(bf8*)&La[0][ar * kDGP + ak] = h;
+            *(bf8*)&La[1][ar * kDGP + ak] = l;
+        }
+        if (k0 + 32 < n) {
+            issue_x(k0 + 32, dbuf ^ 1);
+            load_a(k0 + 32);
+        }
+        __syncthreads();
+        bf8 ah[4], al[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = (wi * 64 + i * 16 + lr) * kDGP + 8 * g;
+            ah[i] = *(const bf8*)&La[0][o];
+            al[i] = *(const bf8*)&La[1][o];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int col = wj * 128 + j * 16 + lr;
+            const int o = col * 32 + 8 * (g ^ ((col >> 2) & 3));
+            const bf8 bh = *(const bf8*)&Lx[dbuf][0][o];
+            const bf8 bl = *(const bf8*)&Lx[dbuf][1][o];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh, acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl, acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
+        }
+        dbuf ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -3875,6 +4042,19 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
             // split-bf16 (or plain bf16) MFMA products, 128 x 512 tiles
             const int ncb = (p + kDGN - 1) / kDGN;
             const unsigned nwg = (unsigned)(((n + kDGM - 1) / kDGM) * ncb);
+            if (ex.dense_prod == 3 && ex.xsplit) {
+                // X^T split once per product, then the panels straight to LDS
+                const int64_t npad = dense_npad(n);
+                __bf16* xh = (__bf16*)ex.xsplit;
+                __bf16* xl = xh + (size_t)p * npad;
+                k_split_xt<<<dim3((unsigned)(npad / 64), (unsigned)((p + 63) / 64)), 256, 0, s>>>(
+                    (const float*)X, xh, xl, n, p, npad, st);
+                const int ncp = (p + kDPN - 1) / kDPN;
+                const unsigned nwp = (unsigned)(((n + kDGM - 1) / kDGM) * ncp);
+                k_dense_bfp<<<nwp, 512, 0, s>>>((const float*)prob->A, xh, xl, npad, (float*)G, n,
+                                                p, ncp, gl, st);
+                return;
+            }
             if (ex.dense_prod == 1)
                 k_dense_bf<1><<<nwg, 512, 0, s>>>((const float*)prob->A, (const float*)X,
                                                   (float*)G, n, p, ncb, gl, st);
@@ -3889,12 +4069,19 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
             const int nbp = (p + 127) / 128;
             const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
             if (prob->A_dtype == STF_F32)
-                k_dense_f64<float><<<nwg, 256, 0, s>>>((const float*)prob->A, (const double*)X,
-                                                       (double*)G, n, p, nbp, gl, st);
+                k_dense_mfma<double, float><<<nwg, 256, 0, s>>>(
+                    (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
             else
-                k_dense_f64<double><<<nwg, 256, 0, s>>>((const double*)prob->A,
-                                                        (const double*)X, (double*)G, n, p, nbp,
-                                                        gl, st);
+                k_dense_mfma<double, double><<<nwg, 256, 0, s>>>(
+                    (const double*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
+            return;
+        }
+        if (dtype == STF_F32 && p > 64) {
+            // float32 MFMA, the same tiling
+            const int nbp = (p + 127) / 128;
+            const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
+            k_dense_mfma<float, float><<<nwg, 256, 0, s>>>((const float*)prob->A, (const float*)X,
+                                                           (float*)G, n, p, nbp, gl, st);
             return;
         }
         if (dtype == STF_F64 && prob->A_dtype == STF_F32) {
