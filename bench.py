@@ -207,6 +207,8 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "ms_orth": conv["ms_orth"],
         "time_to_kkt_s_per_start": ttk_all,
         "iters_to_kkt_per_start": [r["iters"] for r in runs],
+        "switch_iter_per_start": [r.get("switch_iter", -1) for r in runs],
+        "kkt_rel_per_start": [r["kkt_rel"] for r in runs],
         "reached_per_start": reached,
         "reached": f"{sum(reached)}/{len(reached)}",
         "time_to_kkt_s_median": med if np.isfinite(med) else None,
