@@ -161,8 +161,18 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
                 r, x64, _ = S.solve(dp, X, S.SolveOptions(**common, tol=TOL, max_iter=MAX_ITER,
                                                           orth_final=True, check_every=50,
                                                           use_graph=True, switch_tol=sw),
-                                    workspace=ws, stream=stream, want_x64=not x64_first)
+                                    workspace=ws, stream=stream, want_x64=not x64_first,
+                                    raise_on_error=False)
                 torch.cuda.synchronize()
+                if r["rc"] < 0:
+                    # e.g. a rank-deficient final iterate (CholeskyQR2 fails):
+                    # not reached; the iteration count and hand-over are kept,
+                    # the time is the host's wall clock of the call
+                    r["error"] = S.L.strerror(r["rc"])
+                    r["kkt_rel"] = None
+                    r["ms_loop"] = (time.perf_counter() - t) * 1000.0
+                    r["ms_orth"] = 0.0
+                    return r
                 if not x64_first:
                     x64_first.append(x64)
                 return r
