@@ -55,8 +55,8 @@ struct GradExtra {
     const double* rho;    // the density rho = diag(X X^T) (read when gamma != 0)
     double gamma;         // exchange weight
     int32_t block;        // 1D: order of the tridiagonal blocks (0: one block)
-    int32_t dense_prod;   // dense float32 A X: 0 = float32 MFMA, 1 = bf16, 3 = split bf16
-    void* xsplit;         // split bf16 X^T (2 x p x dense_npad(n) bf16) for dense_prod 3, or null
+    int32_t dense_prod;   // dense float32 A X: 0 = float32 MFMA, 3 = split bf16
+    void* xsplit;         // split bf16 X^T (2 x p x dense_npad(n) bf16); required with dense_prod 3
 };
 // k padding of the split X^T of the split-bf16 dense product
 inline int64_t dense_npad(int64_t n) { return (n + 63) / 64 * 64; }

@@ -2136,133 +2136,9 @@ __global__ __launch_bounds__(256, 2) void k_dense_mfma(const TA* __restrict__ A,
             }
 }
 
-// Dense gradient G = A X (+ Glin) for float32 A and X on bf16 MFMA
-// (v_mfma_f32_16x16x32_bf16), the reduced-precision forms of the dense
-// Rayleigh-Ritz problem.  NPROD = 1: one product of the bf16 roundings;
-// NPROD = 3: the two-way split a = a_h + a_l of both operands and the three
-// products a_h b_h + a_h b_l + a_l b_h (a 16-bit mantissa for each operand).
-// A workgroup owns 128 rows x 512 columns of G (A is streamed once for p <=
-// 512; X, read by every row block, comes from L2), eight waves of 64 x 128
-// (4 x 8 MFMA tiles); K advances 32 at a time through LDS: A as [row][k], X
-// transposed as [col][k], both split to bf16 when staged, the next K step's
-// global loads issued before this step's products.
-constexpr int kDGM = 128, kDGN = 512, kDGK = 32, kDGP = kDGK + 8;
-template <int NPROD>
-__global__ __launch_bounds__(512) void k_dense_bf(const float* __restrict__ A,
-                                                  const float* __restrict__ X,
-                                                  float* __restrict__ G, int64_t n, int p,
-                                                  int ncb, const double* __restrict__ glin,
-                                                  const DevState* __restrict__ st) {
-    static_assert(NPROD == 1 || NPROD == 3, "one product or the three-product split");
-    if (st && st->done) return;
-    constexpr int NS = (NPROD == 1) ? 1 : 2;  // bf16 parts staged per operand
-    __shared__ __attribute__((aligned(16))) __bf16 La[NS][kDGM * kDGP];
-    __shared__ __attribute__((aligned(16))) __bf16 Lx[NS][kDGN * kDGP];
-    const int lid = xcd_remap(blockIdx.x, gridDim.x);
-    const int rb = lid / ncb, cb = lid % ncb;
-    const int64_t r0 = (int64_t)rb * kDGM;
-    const int c0 = cb * kDGN;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wi = wave >> 2, wj = wave & 3;   // 2 x 4 waves of 64 x 128
-    const int lr = lane & 15, g = lane >> 4;
-    // loaders: A row (tid >> 2), k offset 8 (tid & 3); X column tid, all 32 k
-    const int ar = tid >> 2, ak = (tid & 3) * 8;
-    const int64_t arow = r0 + ar;
-    const bool aok = arow < n;
-    const int xc = c0 + tid;
-    const bool xok = xc < p;
-    float av[8], xv[kDGK];
-    auto load = [&](int64_t k0) {
-        const float* ap = A + (size_t)arow * n + k0 + ak;
-        if (aok && k0 + ak + 8 <= n && (n % 4) == 0) {
-            const float4 u = *(const float4*)ap;
-            const float4 w = *(const float4*)(ap + 4);
-            av[0] = u.x; av[1] = u.y; av[2] = u.z; av[3] = u.w;
-            av[4] = w.x; av[5] = w.y; av[6] = w.z; av[7] = w.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = (aok && k0 + ak + e < n) ? ap[e] : 0.f;
-        }
-#pragma unroll
-        for (int e = 0; e < kDGK; ++e)
-            xv[e] = (xok && k0 + e < n) ? X[(size_t)(k0 + e) * p + xc] : 0.f;
-    };
-    auto store = [&]() {
-        bf8 h, l;
-        if (NPROD == 1) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = (__bf16)av[e];
-            *(bf8*)&La[0][ar * kDGP + ak] = h;
-        } else {
-            split2(av, h, l);
-            *(bf8*)&La[0][ar * kDGP + ak] = h;
-            *(bf8*)&La[NS - 1][ar * kDGP + ak] = l;
-        }
-#pragma unroll
-        for (int q = 0; q < kDGK / 8; ++q) {
-            float t[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) t[e] = xv[8 * q + e];
-            if (NPROD == 1) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) h[e] = (__bf16)t[e];
-                *(bf8*)&Lx[0][tid * kDGP + 8 * q] = h;
-            } else {
-                split2(t, h, l);
-                *(bf8*)&Lx[0][tid * kDGP + 8 * q] = h;
-                *(bf8*)&Lx[NS - 1][tid * kDGP + 8 * q] = l;
-            }
-        }
-    };
-    f4 acc[4][8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.f;
-    load(0);
-    for (int64_t k0 = 0; k0 < n; k0 += kDGK) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (k0 + kDGK < n) load(k0 + kDGK);
-        bf8 ah[4], al[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = (wi * 64 + i * 16 + lr) * kDGP + 8 * g;
-            ah[i] = *(const bf8*)&La[0][o];
-            if (NPROD == 3) al[i] = *(const bf8*)&La[NS - 1][o];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int o = (wj * 128 + j * 16 + lr) * kDGP + 8 * g;
-            const bf8 bh = *(const bf8*)&Lx[0][o];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh, acc[i][j]);
-            if (NPROD == 3) {
-                const bf8 bl = *(const bf8*)&Lx[NS - 1][o];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl, acc[i][j]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t r = r0 + wi * 64 + i * 16 + Mma<float>::row(g, q);
-                const int c = c0 + wj * 128 + j * 16 + lr;
-                if (r < n && c < p) {
-                    const size_t idx = (size_t)r * p + c;
-                    G[idx] = glin ? (float)((double)acc[i][j][q] + glin[idx]) : acc[i][j][q];
-                }
-            }
-}
+// Tile constants of the split-bf16 dense product: 128 rows per workgroup, a
+// 32-deep K step, LDS pitch of the A panel (bf16).
+constexpr int kDGM = 128, kDGP = 32 + 8;
 
 // X^T split into bf16 h + l for the split-bf16 dense product: XhT, XlT are
 // p x npad ([column][k], npad a multiple of 64, zero for k >= n), through a
@@ -4038,37 +3914,29 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
     const int p = prob->p;
     if (prob->kind == STF_KIND_DENSE) {
         const double* gl = ex.glin;
-        if (dtype == STF_F32 && ex.dense_prod != 0) {
-            // split-bf16 (or plain bf16) MFMA products, 128 x 512 tiles
-            const int ncb = (p + kDGN - 1) / kDGN;
-            const unsigned nwg = (unsigned)(((n + kDGM - 1) / kDGM) * ncb);
-            if (ex.dense_prod == 3 && ex.xsplit) {
-                // X^T split once per product, then the panels straight to LDS
-                const int64_t npad = dense_npad(n);
-                __bf16* xh = (__bf16*)ex.xsplit;
-                __bf16* xl = xh + (size_t)p * npad;
-                k_split_xt<<<dim3((unsigned)(npad / 64), (unsigned)((p + 63) / 64)), 256, 0, s>>>(
-                    (const float*)X, xh, xl, n, p, npad, st);
-                const int ncp = (p + kDPN - 1) / kDPN;
-                const unsigned nwp = (unsigned)(((n + kDGM - 1) / kDGM) * ncp);
-                k_dense_bfp<<<nwp, 512, 0, s>>>((const float*)prob->A, xh, xl, npad, (float*)G, n,
-                                                p, ncp, gl, st);
-                return;
-            }
-            if (ex.dense_prod == 1)
-                k_dense_bf<1><<<nwg, 512, 0, s>>>((const float*)prob->A, (const float*)X,
-                                                  (float*)G, n, p, ncb, gl, st);
-            else
-                k_dense_bf<3><<<nwg, 512, 0, s>>>((const float*)prob->A, (const float*)X,
-                                                  (float*)G, n, p, ncb, gl, st);
+        if (dtype == STF_F32 && ex.dense_prod == 3) {
+            // split-bf16 MFMA products: X^T split once per product (the
+            // workspace holds it), then the panels straight to LDS
+            const int64_t npad = dense_npad(n);
+            __bf16* xh = (__bf16*)ex.xsplit;
+            __bf16* xl = xh + (size_t)p * npad;
+            k_split_xt<<<dim3((unsigned)(npad / 64), (unsigned)((p + 63) / 64)), 256, 0, s>>>(
+                (const float*)X, xh, xl, n, p, npad, st);
+            const int ncp = (p + kDPN - 1) / kDPN;
+            const unsigned nwp = (unsigned)(((n + kDGM - 1) / kDGM) * ncp);
+            k_dense_bfp<<<nwp, 512, 0, s>>>((const float*)prob->A, xh, xl, npad, (float*)G, n, p,
+                                            ncp, gl, st);
             return;
         }
-        if (dtype == STF_F64 && p > 64) {
-            // float64 arithmetic (a float32 A widened exactly on load), 128 x 128
-            // tiles staged through LDS
+        if (p > 64) {
+            // 128 x 128 tiles staged through LDS (a float32 A is widened
+            // exactly in the float64 form)
             const int nbp = (p + 127) / 128;
             const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
-            if (prob->A_dtype == STF_F32)
+            if (dtype == STF_F32)
+                k_dense_mfma<float, float><<<nwg, 256, 0, s>>>(
+                    (const float*)prob->A, (const float*)X, (float*)G, n, p, nbp, gl, st);
+            else if (prob->A_dtype == STF_F32)
                 k_dense_mfma<double, float><<<nwg, 256, 0, s>>>(
                     (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
             else
@@ -4076,48 +3944,18 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
                     (const double*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
             return;
         }
-        if (dtype == STF_F32 && p > 64) {
-            // float32 MFMA, the same tiling
-            const int nbp = (p + 127) / 128;
-            const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
-            k_dense_mfma<float, float><<<nwg, 256, 0, s>>>((const float*)prob->A, (const float*)X,
-                                                           (float*)G, n, p, nbp, gl, st);
-            return;
-        }
-        if (dtype == STF_F64 && prob->A_dtype == STF_F32) {
-            // float64 arithmetic on a float32 A (widened exactly on load)
-            {
-                const int nbp = (p + 31) / 32;
-                const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
-                k_dense_grad<double, 1, float><<<nwg, 256, 0, s>>>(
-                    (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
-            }
-            return;
-        }
-        // WG tile 128 x 128 for wide p, 32 x 32 otherwise
-        if (p > 64) {
-            const int nbp = (p + 127) / 128;
-            const unsigned nwg = (unsigned)(((n + 127) / 128) * nbp);
-            if (dtype == STF_F64)
-                k_dense_grad<double, 4><<<nwg, 256, 0, s>>>((const double*)prob->A,
-                                                            (const double*)X, (double*)G, n, p,
-                                                            nbp, gl, st);
-            else
-                k_dense_grad<float, 4><<<nwg, 256, 0, s>>>((const float*)prob->A,
-                                                           (const float*)X, (float*)G, n, p,
-                                                           nbp, gl, st);
-        } else {
-            const int nbp = (p + 31) / 32;
-            const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
-            if (dtype == STF_F64)
-                k_dense_grad<double, 1><<<nwg, 256, 0, s>>>((const double*)prob->A,
-                                                            (const double*)X, (double*)G, n, p,
-                                                            nbp, gl, st);
-            else
-                k_dense_grad<float, 1><<<nwg, 256, 0, s>>>((const float*)prob->A,
-                                                           (const float*)X, (float*)G, n, p,
-                                                           nbp, gl, st);
-        }
+        // narrow p: 32 x 32 tiles fed from global memory
+        const int nbp = (p + 31) / 32;
+        const unsigned nwg = (unsigned)(((n + 31) / 32) * nbp);
+        if (dtype == STF_F32)
+            k_dense_grad<float, 1><<<nwg, 256, 0, s>>>((const float*)prob->A, (const float*)X,
+                                                       (float*)G, n, p, nbp, gl, st);
+        else if (prob->A_dtype == STF_F32)
+            k_dense_grad<double, 1, float><<<nwg, 256, 0, s>>>(
+                (const float*)prob->A, (const double*)X, (double*)G, n, p, nbp, gl, st);
+        else
+            k_dense_grad<double, 1><<<nwg, 256, 0, s>>>((const double*)prob->A, (const double*)X,
+                                                        (double*)G, n, p, nbp, gl, st);
         return;
     }
     const double* ph = (prob->alpha != 0.0) ? phi : nullptr;
