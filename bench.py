@@ -218,6 +218,7 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "time_to_kkt_s_per_start": ttk_all,
         "iters_to_kkt_per_start": [r["iters"] for r in runs],
         "switch_iter_per_start": [r.get("switch_iter", -1) for r in runs],
+        "restarted_per_start": [int(r.get("restarted", 0)) for r in runs],
         "kkt_rel_per_start": [r["kkt_rel"] for r in runs],
         "reached_per_start": reached,
         "reached": f"{sum(reached)}/{len(reached)}",

@@ -200,7 +200,13 @@ typedef struct stf_problem {
  *               Barzilai-Borwein quotients; this finishes the descent exactly.
  *               The hand-over also happens, above switch_tol, once 100
  *               iterations have passed without a new smallest stop-test value
- *               (a float32 descent that wanders instead of converging).
+ *               (a float32 descent that wanders instead of converging).  If
+ *               the stop-test value at such a hand-over exceeds the one at X^0
+ *               (the float32 iterate has left the neighbourhood of the
+ *               manifold), the float32 iterate is discarded and the float64
+ *               phase restarts from X^0 (stf_result.restarted = 1): the solve
+ *               then returns what the float64 form returns from X^0 rounded
+ *               to float32.  The workspace keeps a float32 copy of X^0 for it.
  * history     : device, (max_iter + 1) x 4 float64, or NULL: row k receives
  *               { ||G - X Psi||_F (NaN when the stop test was not due),
  *                 ||X^T X - I||_F, eta^k (NaN on the last row), k } as
@@ -249,7 +255,11 @@ typedef struct stf_options {
  *           the eta / nu stage, and UPDATE brackets the reduction of the row
  *           sums of squares into rho (no launch when no term needs rho)
  * switch_iter : iteration at which a float32 / mixed solve continued in
- *           float64 (see switch_tol), or -1                                 */
+ *           float64 (see switch_tol), or -1
+ * restarted : 1 when that float64 phase restarted from X^0 (see switch_tol):
+ *           iters then counts the float64 iterations from X^0, after the
+ *           switch_iter discarded float32 ones; history holds the float64
+ *           rows from 0 (later rows of the float32 phase are left); 0 else   */
 #define STF_PROF_HARTREE  0
 #define STF_PROF_GRAD     1
 #define STF_PROF_GRAM     2
@@ -272,6 +282,8 @@ typedef struct stf_result {
     double kernel_ms[8];
     int32_t prof_iters;
     int32_t switch_iter;
+    int32_t restarted;
+    int32_t reserved;
 } stf_result;
 
 /* Bytes of device workspace needed by stf_solve / plam_solve / pcal_solve and
@@ -390,7 +402,8 @@ int pcal_adjoint_v(const stf_problem* prob, const double* Xstar, const double* L
  *            acts as in stf_solve, per problem: in the float32 forms a problem
  *            that reaches it (or stalls) continues in float64 at once while
  *            the others go on in float32 in the same iterations
- *            (stf_result.switch_iter per problem)
+ *            (stf_result.switch_iter per problem); a problem always continues
+ *            from its float32 iterate here (restarted = 0: no restart from X^0)
  *   ws     : device workspace of ws_bytes >= stf_batched_workspace_size()
  *   res    : host array of nprob results (ms_loop / ms_orth: the whole batch)
  * Returns the first STF_E_* met, else STF_MAX_ITER when some problem reached

@@ -82,6 +82,8 @@ class StfResult(ctypes.Structure):
         ("kernel_ms", ctypes.c_double * 8),
         ("prof_iters", ctypes.c_int32),
         ("switch_iter", ctypes.c_int32),
+        ("restarted", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 PROF_NAMES = ["hartree", "grad", "gram", "stage1", "residual", "stage2", "update"]

@@ -94,10 +94,12 @@ Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fus
     if (dt == STF_F64) {
         L.x64 = (size_t)-1;  // X itself
         L.g64 = L.g[0];
+        L.x0keep = (size_t)-1;
     } else {
         L.x64 = take(np * 8);
         L.g64 = take(np * 8);
         L.g64b = take(np * 8);
+        L.x0keep = take(np * 4);
     }
     L.rho = take((size_t)n * 8);
     L.phi = take((size_t)n * 8);
@@ -496,6 +498,10 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
     HIPCHK(hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
     launch_init_state(c.st, s);
     if (prob->kind == STF_KIND_STENCIL3D) launch_dst_init(prob, w.at<double>(w.L.dst), s);
+    // X^0 of the float32 forms is kept for a float64 restart (see below)
+    if (dtype == STF_F32)
+        HIPCHK(hipMemcpyAsync(w.at<float>(w.L.x0keep), X, (size_t)n * p * 4,
+                              hipMemcpyDeviceToDevice, s));
     // the float32 forms iterate on a float64 master copy; X holds its rounding
     if (c.Xm) launch_convert(STF_F64, X, STF_F32, c.Xm, (size_t)n * p, s);
     if (needs_rho(prob))
@@ -585,7 +591,40 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
 
     int hip_err = run_phase(c, 0);
     res->switch_iter = -1;
-    if (!hip_err && hs.done && hs.status == STF_SWITCH) {
+    res->restarted = 0;
+    if (!hip_err && hs.done && hs.status == STF_SWITCH && hs.kkt > hs.kkt0 &&
+        hs.kkt > hp.switch_tol * hs.kkt0) {
+        // A reduced-precision descent that stalled at a point worse than X^0
+        // has left the neighbourhood of the manifold (typically its columns
+        // have collapsed onto a few directions, which float32 iterates cannot
+        // separate again): its iterate is discarded and the float64 phase
+        // starts over from X^0, so that the solve reaches what the float64
+        // form reaches from the same start.
+        res->switch_iter = (int)hs.final_iter;
+        res->restarted = 1;
+        IterCtx c64 = c;
+        c64.dtype = STF_F64;
+        c64.precision = STF_PREC_FP64;
+        c64.X = w.at<double>(w.L.x64);
+        c64.Xm = nullptr;
+        launch_convert(STF_F64, w.at<float>(w.L.x0keep), STF_F32, c64.X, (size_t)n * p, s);
+        if (fused) {
+            c64.xb[0] = c64.X;
+            c64.xb[1] = w.at<double>(w.L.xalt);
+            xb64[0] = c64.xb[0];
+            xb64[1] = c64.xb[1];
+        }
+        c64.g[0] = w.L.g64;
+        c64.g[1] = w.L.g64b;
+        hp.switch_tol = 0.0;
+        if (hipMemcpyAsync(c.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess)
+            hip_err = 1;
+        launch_init_state(c.st, s);
+        if (needs_rho(prob))
+            launch_rowsq(STF_F64, c64.X, n, p, w.at<double>(w.L.rho), c.st, s);
+        if (!hip_err && last_launch()) hip_err = 1;
+        if (!hip_err) hip_err = run_phase(c64, 0);
+    } else if (!hip_err && hs.done && hs.status == STF_SWITCH) {
         // Redo iteration k in float64 from the master iterate: the previous
         // gradL (float32, exact in float64) seeds the Barzilai-Borwein pair.
         const int64_t k = hs.final_iter;

@@ -104,6 +104,7 @@ struct Layout {
     size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
     size_t x64, g64;      // float64 n*p buffers: master iterate (float32 forms) and scratch
     size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
+    size_t x0keep;        // n*p float32 (float32 forms): X^0, kept for a float64 restart
     size_t rho, phi, hscr;
     size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, fpart;  // T1: p x p product-pass partials
     size_t nu, colpart;   // colpart: col_groups(res.nrb) x 2p column-dot partials

@@ -7,6 +7,8 @@ points returns before any device work).
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -50,7 +52,34 @@ def test_struct_layouts_match_header():
     assert L.StfProblem.Glin.offset == 72 and L.StfProblem.B.offset == 80
     assert ctypes.sizeof(L.StfOptions) == 48 + 56
     assert L.StfOptions.beta.offset == 48 and L.StfOptions.history.offset == 96
-    assert ctypes.sizeof(L.StfResult) == 8 + 8 * 8 + 8 * 8 + 8
+    assert ctypes.sizeof(L.StfResult) == 8 + 8 * 8 + 8 * 8 + 16
+    assert L.StfResult.restarted.offset == 144
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None or
+                    not os.path.isdir("/opt/rocm/include"), reason="needs gcc and HIP headers")
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Every field offset and struct size of the binding, against what gcc
+    makes of include/stiefel.h."""
+    structs = {"stf_problem": L.StfProblem, "stf_options": L.StfOptions,
+               "stf_result": L.StfResult}
+    lines = ['#include <stdio.h>', '#include "stiefel.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, f, v = line.split()
+        ct = structs[cname]
+        got = ctypes.sizeof(ct) if f == "sizeof" else getattr(ct, f).offset
+        assert got == int(v), (cname, f, got, v)
 
 
 def _problem(kind=L.KIND_STENCIL1D, n=1000, p=10, grid=None):

@@ -266,6 +266,41 @@ def test_switch_on_stall():
     _check_returned_point(op, res, X64, lam)
 
 
+
+@pytest.mark.parametrize("precision,fused", [("fp32", False), ("mixed", False),
+                                             ("mixed32", False), ("mixed32", True)])
+def test_stall_above_start_restarts_from_x0(precision, fused):
+    """A reduced-precision descent that stalls at a stop-test value above the
+    one at X^0 is discarded, and float64 restarts from X^0.  Constant steps
+    50 times too long (eta = eta0 / 50) keep the stop test at least 1.5 times
+    its X^0 value for 160 iterations in the float64 oracle, so the float32
+    phase hands over on stall at k = 100 with restarted = 1, and the solve is
+    then the float64 form from the float32-rounded X^0, bit for bit (in the
+    two-pass and the single-pass forms)."""
+    prob, x0, _ = W.ks3d(grid=(20, 18, 16), p=100)
+    x0r = x0.astype(np.float32).astype(np.float64)
+    m = 130
+    eta0 = 4.0 + prob.s_bound
+    _, g = _pair(prob, beta=4.0, eta_rule="const", eta_const=eta0 / 50, max_iter=m,
+                 precision=precision)
+    g.switch_tol = 1e-4
+    g.fused = fused
+    g.bb_index = "lagged" if fused else "standard"
+    g.tol = 1e-14
+    res, _, X64, _ = _gpu_solve(prob, x0r, g)
+    _, g64 = _pair(prob, beta=4.0, eta_rule="const", eta_const=eta0 / 50, max_iter=m)
+    g64.fused = fused
+    g64.bb_index = g.bb_index
+    g64.tol = 1e-14
+    res64, X64b, _, _ = _gpu_solve(prob, x0r, g64)
+    print(f"{precision} fused={fused}: hand-over at {res['switch_iter']}, "
+          f"restarted {res['restarted']}, {res['iters']} float64 iterations")
+    assert res["switch_iter"] == 100 and res["restarted"] == 1
+    assert res["iters"] == res64["iters"] == m and res64["restarted"] == 0
+    assert np.array_equal(X64, X64b)
+    assert res["kkt_abs"] == res64["kkt_abs"] and res["kkt_abs"] > res["kkt0"]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
 @pytest.mark.parametrize("grid,p", [((20, 18, 16), 100), ((16, 16, 12), 300)])
 def test_reduced_precision_iterates_wide(precision, grid, p):
