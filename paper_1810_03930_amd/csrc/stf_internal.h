@@ -235,8 +235,8 @@ void launch_stage1(const DevParams* prm, const double* S, const double* W,
                    double* Psi, double* ML, double* Bm, double* feas_part, int p,
                    DevState* st, hipStream_t s, double* lam2 = nullptr);
 // per-tile partials of <B, S B - 2 (W - S M_L)> into part[kkt_partials(p)]
-// (64 x 64 float64 MFMA tiles of one product from p = kPPWide on, else
-// 16 x 16 tiles of two)
+// (64 x 64 float64 MFMA tiles of one product, split over K, from p = kPPWide
+// on, else 16 x 16 tiles of two)
 constexpr int kPPWide = 128;
 int kkt_partials(int p);
 void launch_kkt_products(const double* S, const double* ML, const double* Bm, const double* W,

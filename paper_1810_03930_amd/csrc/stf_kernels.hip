@@ -1527,7 +1527,8 @@ constexpr int kMixRW = 32;
 // for all its row tiles; 256 / RW waves of RW rows x 64 columns walk row tiles
 // of 256 rows.  X fragments come straight from global memory (8 consecutive
 // columns of one row per lane, two 16-byte loads), prefetched one K-step
-// ahead and split into h + m + l in registers; the six products
+// ahead (the first two K-steps of the next row tile during the epilogue) and
+// split into h + m + l in registers; the six products
 // sum_{a+b<=2} X_a M_b give float32-level accuracy.  Epilogue, partials and BB
 // pair as in k_residual (stop test by the p x p identity, so no product with
 // Psi).
@@ -1598,6 +1599,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
     double sss = 0.0, ssy = 0.0, syy = 0.0;
     const bool vec = (p % 4) == 0;
     const uint32_t rowb = (uint32_t)p * 4u;
+    float xa[2][IT][8];
     for (int64_t rt = rb; rt < nrt; rt += nrb) {
         const int64_t r0 = rt * 256 + wave * RW;
         // the wave's rows of X, G and grad L^{k-1} as raw buffers: rows past n
@@ -1611,11 +1613,10 @@ __device__ __forceinline__ void body_residual_bf6_lds(
                                                    FU ? (uint32_t)nvr * rowb : 0u);
         // X fragments (16 rows x 8 consecutive columns per MFMA tile) of two
         // K-chunks in flight: chunk kc is split while kc + 64 is loaded
-        float xa[2][IT][8];
-        auto load_x = [&](int kc, float (&dst)[IT][8]) {
+        auto load_x = [&](int kc, float (&dst)[IT][8], int64_t rbase) {
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
-                const int64_t r = r0 + i * 16 + lr;
+                const int64_t r = rbase + i * 16 + lr;
                 const int c = kc + 8 * g;
                 const float* src = X + (size_t)r * p + c;
                 if (vec && r < n && c + 8 <= p) {
@@ -1643,7 +1644,7 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             bf8 xh[IT], xm[IT], xl[IT];
 #pragma unroll
             for (int i = 0; i < IT; ++i) split3(buf[i], xh[i], xm[i], xl[i]);
-            if (kc + 64 < pk) load_x(kc + 64, buf);
+            if (kc + 64 < pk) load_x(kc + 64, buf, r0);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int o = (j * 16 + lr) * LP + kc + 8 * g;
@@ -1700,11 +1701,19 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             }
         };
         if constexpr (WE) wload(0);
-        load_x(0, xa[0]);
-        if (32 < pk) load_x(32, xa[1]);
+        if (rt == rb) {
+            load_x(0, xa[0], r0);
+            if (32 < pk) load_x(32, xa[1], r0);
+        }
         for (int kc = 0; kc < pk; kc += 64) {
             step(kc, xa[0]);
             if (kc + 32 < pk) step(kc + 32, xa[1]);
+        }
+        // the next row tile's first two K-chunks, in flight during the epilogue
+        if (rt + nrb < nrt) {
+            const int64_t r0n = (rt + nrb) * 256 + wave * RW;
+            load_x(0, xa[0], r0n);
+            if (32 < pk) load_x(32, xa[1], r0n);
         }
 
         // gradL = G - X M_L over G, one 16 x 16 sub-tile per round; the next
@@ -3396,10 +3405,12 @@ __global__ __launch_bounds__(1024) void k_chol_inv_off(const double* __restrict_
 }
 
 // The p x p term of the float64 KKT identity with a single product for wide p:
-// <B, S B - 2 (W - S M_L)> = <B, S (B + 2 M_L)> - 2 <B, W>.  One 64 x 64 tile
-// (bx, by) of S (B + 2 M_L) per workgroup as sixteen 16 x 16 float64 MFMA
-// tiles over 64-deep LDS panels, then the tile's share of the inner product
-// reduced in the workgroup into part[by * gridDim.x + bx].
+// <B, S B - 2 (W - S M_L)> = <B, S (B + 2 M_L)> - 2 <B, W>.  Workgroup
+// (bx, by, kb) forms the kb-th 64-deep term of the 64 x 64 tile (bx, by) of
+// S (B + 2 M_L) (sixteen 16 x 16 float64 MFMA tiles over LDS panels) and its
+// share of the inner product (the -2 <B, W> term with kb = 0), reduced in the
+// workgroup into part[(kb * nt + by) * nt + bx]: nt^3 workgroups, so that the
+// p x p stage spreads over the chip instead of nt^2 workgroups walking K.
 __global__ __launch_bounds__(1024) void k_pp_kkt64(const double* __restrict__ S,
                                                    const double* __restrict__ ML,
                                                    const double* __restrict__ Bm,
@@ -3409,25 +3420,19 @@ __global__ __launch_bounds__(1024) void k_pp_kkt64(const double* __restrict__ S,
     if (st->done) return;
     __shared__ double sa[kCB * kDP], sb[kCB * kDP];
     __shared__ double sh[16];
-    const int bx = blockIdx.x, by = blockIdx.y, nt = gridDim.x;
+    const int bx = blockIdx.x, by = blockIdx.y, kb = blockIdx.z, nt = gridDim.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int ti = wave >> 2, tj = wave & 3;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < nt; ++kb) {
-        __syncthreads();
-        chol_load(sa, S, p, by, kb, false, false);
-        for (int e = threadIdx.x; e < kCB * kCB; e += blockDim.x) {
-            const int r = e / kCB, c = e % kCB;
-            const int gr = kb * kCB + r, gc = bx * kCB + c;
-            sb[r * kDP + c] = (gr < p && gc < p)
-                                  ? Bm[(size_t)gr * p + gc] + 2.0 * ML[(size_t)gr * p + gc]
-                                  : 0.0;
-        }
-        __syncthreads();
-        const d4 t = dst_tile(sa, sb, ti, tj, lr, lk);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += t[q];
+    chol_load(sa, S, p, by, kb, false, false);
+    for (int e = threadIdx.x; e < kCB * kCB; e += blockDim.x) {
+        const int r = e / kCB, c = e % kCB;
+        const int gr = kb * kCB + r, gc = bx * kCB + c;
+        sb[r * kDP + c] = (gr < p && gc < p)
+                              ? Bm[(size_t)gr * p + gc] + 2.0 * ML[(size_t)gr * p + gc]
+                              : 0.0;
     }
+    __syncthreads();
+    const d4 acc = dst_tile(sa, sb, ti, tj, lr, lk);
     double c = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -3435,11 +3440,11 @@ __global__ __launch_bounds__(1024) void k_pp_kkt64(const double* __restrict__ S,
         const int gc = bx * kCB + 16 * tj + lr;
         if (gr < p && gc < p) {
             const size_t e = (size_t)gr * p + gc;
-            c += Bm[e] * (acc[q] - 2.0 * W[e]);
+            c += Bm[e] * (kb == 0 ? acc[q] - 2.0 * W[e] : acc[q]);
         }
     }
     c = block_sum<16>(c, sh);
-    if (threadIdx.x == 0) part[by * nt + bx] = c;
+    if (threadIdx.x == 0) part[((size_t)kb * nt + by) * nt + bx] = c;
 }
 
 // C = A B for p x p float64 matrices, 64 x 64 tiles of float64 MFMA.
@@ -4077,7 +4082,11 @@ void launch_stage1(const DevParams* prm, const double* S, const double* W, doubl
 }
 
 int kkt_partials(int p) {
-    const int t = (p >= kPPWide) ? (p + kCB - 1) / kCB : (p + 15) / 16;
+    if (p >= kPPWide) {
+        const int t = (p + kCB - 1) / kCB;
+        return t * t * t;
+    }
+    const int t = (p + 15) / 16;
     return t * t;
 }
 
@@ -4085,7 +4094,7 @@ void launch_kkt_products(const double* S, const double* ML, const double* Bm, co
                          double* part, int p, DevState* st, hipStream_t s) {
     if (p >= kPPWide) {
         const int t = (p + kCB - 1) / kCB;
-        k_pp_kkt64<<<dim3(t, t), 1024, 0, s>>>(S, ML, Bm, W, part, p, st);
+        k_pp_kkt64<<<dim3(t, t, t), 1024, 0, s>>>(S, ML, Bm, W, part, p, st);
         return;
     }
     dim3 grid((p + 15) / 16, (p + 15) / 16);
