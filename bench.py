@@ -223,9 +223,19 @@ def run_form(dp, x0, precision, steps, warmup, S, torch, ttk=True, starts=()):
         "reached_per_start": reached,
         "reached": f"{sum(reached)}/{len(reached)}",
         "time_to_kkt_s_median": med if np.isfinite(med) else None,
+        # the mean over the starts (None when one did not reach the tolerance)
+        "time_to_kkt_s_mean": float(np.mean(ttk_all)) if all(reached) else None,
         **form_options(precision),
     }
     return out, x_first
+
+
+def faster_on(base, fast):
+    """Number of starts on which `fast` reached the tolerance before `base`."""
+    def t(f, i):
+        return f["time_to_kkt_s_per_start"][i] if f["reached_per_start"][i] else np.inf
+    n = len(base["reached_per_start"])
+    return sum(1 for i in range(n) if t(fast, i) < t(base, i))
 
 
 KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_residual",
@@ -791,6 +801,12 @@ def main():
                                                or not base["time_to_kkt_s_median"]) else
         base["time_to_kkt_s_median"] / fast["time_to_kkt_s_median"],
         "reached": None if args.skip_ttk else {f: forms[f]["reached"] for f in forms},
+        "time_to_kkt_s_mean": None if args.skip_ttk else
+        {f: forms[f]["time_to_kkt_s_mean"] for f in forms},
+        # starts (of the same seeded set) on which the fast form reaches the
+        # tolerance sooner than FP64 (an unreached start counts as infinitely slow)
+        "faster_on_starts": None if args.skip_ttk else
+        f"{faster_on(base, fast)}/{len(base['reached_per_start'])}",
         "iters_per_s": {f: forms[f]["iters_per_s"] for f in forms},
         "result_error_vs_fp64": errors,
         "forms": forms,
