@@ -929,7 +929,6 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
         for (int64_t kb = k0; active && kb < k1; kb += 16) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            if (kb + 16 < k1) issue(kb + 16, dbuf ^ 1);
             const double* zs = ZsD + dbuf * 2048;
             const double* ys = YsD + dbuf * 2048;
             if (csq) {
@@ -945,28 +944,35 @@ __device__ __forceinline__ void body_gram_lds(const T* __restrict__ X,
                     }
                 }
             }
+            // the chunk's operands into registers before the next chunk's
+            // loads are issued (LDS reads after them would wait for them)
+            double a[4][4], b[4][4];
             if (!below) {
 #pragma unroll
-                for (int kk = 0; kk < 16; kk += 4) {
-                    const int k = kk + lk;
+                for (int kq = 0; kq < 4; ++kq) {
+                    const int k = 4 * kq + lk;
                     const int sw = (k & 1) << 3;
-                    double a[4], b[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int col = wi * 64 + i * 16 + lr;
-                        a[i] = zs[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
+                        a[kq][i] = zs[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
                     }
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int col = wj * 64 + j * 16 + lr;
-                        b[j] = ys[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
+                        b[kq][j] = ys[k * 128 + (((col >> 1) ^ sw) << 1) + (col & 1)];
                     }
+                }
+            }
+            if (kb + 16 < k1) issue(kb + 16, dbuf ^ 1);
+            if (!below) {
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            acc[i][j] = Mma<T>::run((T)a[i], (T)b[j], acc[i][j]);
-                }
+                            acc[i][j] = Mma<T>::run((T)a[kq][i], (T)b[kq][j], acc[i][j]);
             }
             dbuf ^= 1;
         }
@@ -2445,7 +2451,10 @@ __device__ __forceinline__ void body_residual(
     constexpr int JT = WTC / 16;       // 16-column MFMA tiles per wave
     // float64: the K-chunks go straight from global memory into two LDS
     // buffers (buffer_load ... lds), so the next chunk is in flight while this
-    // one is used, without staging registers and with one barrier per chunk
+    // one is used, without staging registers and with one barrier per chunk.
+    // A wave reads all of a chunk's operands from LDS before it issues the
+    // next chunk's loads: an LDS read that follows a load into LDS waits for
+    // it (the compiler cannot tell the two buffers apart)
     constexpr bool DL = sizeof(T) == 8 && WC == 2;
     __shared__ T Xs[DL ? 1 : 128 * XS];
     __shared__ T Ms[DL ? 1 : KC * MST];
@@ -2618,32 +2627,36 @@ __device__ __forceinline__ void body_residual(
                 // with the other buffer
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
-                if (kc + 16 < p)
-                    issue(rt, kc + 16, dbuf ^ 1);
-                else if (rt + nrb < nrt)
-                    issue(rt + nrb, 0, dbuf ^ 1);
                 const double* xs = XsD + dbuf * 2048;
                 const double* ms = MsD + dbuf * 1024;
+                // the whole chunk's operands into registers first: LDS reads
+                // issued after the next chunk's loads would wait for them
+                double a[4][4], b[4][JT];
 #pragma unroll
-                for (int kk = 0; kk < 16; kk += 4) {
-                    const int k = kk + lk;
-                    double a[4], b[JT];
+                for (int kq = 0; kq < 4; ++kq) {
+                    const int k = 4 * kq + lk;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int row = wr * 64 + i * 16 + lr;
-                        a[i] = xs[row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1)];
+                        a[kq][i] = xs[row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1)];
                     }
 #pragma unroll
                     for (int j = 0; j < JT; ++j) {
                         const int col = wc * WTC + j * 16 + lr;
-                        b[j] = ms[k * 64 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+                        b[kq][j] = ms[k * 64 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
                     }
+                }
+                if (kc + 16 < p)
+                    issue(rt, kc + 16, dbuf ^ 1);
+                else if (rt + nrb < nrt)
+                    issue(rt + nrb, 0, dbuf ^ 1);
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
                         for (int j = 0; j < JT; ++j)
-                            a1[i][j] = Mma<T>::run((T)a[i], (T)b[j], a1[i][j]);
-                }
+                            a1[i][j] = Mma<T>::run((T)a[kq][i], (T)b[kq][j], a1[i][j]);
                 dbuf ^= 1;
             }
         }
