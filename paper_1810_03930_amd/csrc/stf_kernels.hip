@@ -2104,13 +2104,14 @@ __global__ __launch_bounds__(256, 2) void k_dense_mfma(const TA* __restrict__ A,
     for (int64_t kb = 0; kb < n; kb += 16) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (kb + 16 < n) issue(kb + 16, dbuf ^ 1);
         const TA* as = As + dbuf * AP;
         const T* xs = Xs + dbuf * 2048;
+        // the chunk's operands into registers before the next chunk's loads
+        // are issued (LDS reads after them would wait for them)
+        T a[4][4], b[4][4];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            const int k = kk + lk;
-            T a[4], b[4];
+        for (int kq = 0; kq < 4; ++kq) {
+            const int k = 4 * kq + lk;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = wi * 64 + i * 16 + lr;
@@ -2119,21 +2120,25 @@ __global__ __launch_bounds__(256, 2) void k_dense_mfma(const TA* __restrict__ A,
                     pos = row * 16 + (((k >> 2) ^ ((row >> 2) & 3)) << 2) + (k & 3);
                 else
                     pos = row * 16 + (((k >> 1) ^ ((row >> 1) & 7)) << 1) + (k & 1);
-                a[i] = (T)as[pos];
+                a[kq][i] = (T)as[pos];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int col = wj * 64 + j * 16 + lr;
                 if constexpr (XE == 8)
-                    b[j] = xs[k * 128 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
+                    b[kq][j] = xs[k * 128 + (((col >> 1) ^ ((k & 1) << 3)) << 1) + (col & 1)];
                 else
-                    b[j] = xs[k * 128 + (((col >> 2) ^ ((k & 3) << 2)) << 2) + (col & 3)];
+                    b[kq][j] = xs[k * 128 + (((col >> 2) ^ ((k & 3) << 2)) << 2) + (col & 3)];
             }
+        }
+        if (kb + 16 < n) issue(kb + 16, dbuf ^ 1);
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Mma<T>::run(a[i], b[j], acc[i][j]);
-        }
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = Mma<T>::run(a[kq][i], b[kq][j], acc[i][j]);
         dbuf ^= 1;
     }
 #pragma unroll
@@ -2270,12 +2275,11 @@ __global__ __launch_bounds__(512) void k_dense_bfp(const float* __restrict__ A,
             *(bf8*)&La[0][ar * kDGP + ak] = h;
             *(bf8*)&La[1][ar * kDGP + ak] = l;
         }
-        if (k0 + 32 < n) {
-            issue_x(k0 + 32, dbuf ^ 1);
-            load_a(k0 + 32);
-        }
+        if (k0 + 32 < n) load_a(k0 + 32);
         __syncthreads();
-        bf8 ah[4], al[4];
+        // the step's operands into registers before the next X panels'
+        // loads are issued (LDS reads after them would wait for them)
+        bf8 ah[4], al[4], bh[8], bl[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int o = (wi * 64 + i * 16 + lr) * kDGP + 8 * g;
@@ -2286,14 +2290,18 @@ __global__ __launch_bounds__(512) void k_dense_bfp(const float* __restrict__ A,
         for (int j = 0; j < 8; ++j) {
             const int col = wj * 128 + j * 16 + lr;
             const int o = col * 32 + 8 * (g ^ ((col >> 2) & 3));
-            const bf8 bh = *(const bf8*)&Lx[dbuf][0][o];
-            const bf8 bl = *(const bf8*)&Lx[dbuf][1][o];
+            bh[j] = *(const bf8*)&Lx[dbuf][0][o];
+            bl[j] = *(const bf8*)&Lx[dbuf][1][o];
+        }
+        if (k0 + 32 < n) issue_x(k0 + 32, dbuf ^ 1);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh, acc[i][j]);
+        for (int j = 0; j < 8; ++j) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl, acc[i][j]);
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bh[j], acc[i][j]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh, acc[i][j]);
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = mma_bf(al[i], bh[j], acc[i][j]);
         }
         dbuf ^= 1;
     }
