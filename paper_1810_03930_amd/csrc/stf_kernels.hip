@@ -1652,23 +1652,39 @@ __device__ __forceinline__ void body_residual_bf6_lds(
             for (int i = 0; i < IT; ++i) split3(buf[i], xh[i], xm[i], xl[i]);
             if (kc + 64 < pk) load_x(kc + 64, buf, r0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = (j * 16 + lr) * LP + kc + 8 * g;
-                const bf8 mh = *(const bf8*)&Ms[o];
-                const bf8 mm = *(const bf8*)&Ms[64 * LP + o];
-                const bf8 ml = *(const bf8*)&Ms[2 * 64 * LP + o];
+            for (int j0 = 0; j0 < 4; j0 += 2) {
+                bf8 mh[2], mm[2], ml[2];
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mh, acc[i][j]);
+                for (int u = 0; u < 2; ++u) {
+                    const int o = ((j0 + u) * 16 + lr) * LP + kc + 8 * g;
+                    mh[u] = *(const bf8*)&Ms[o];
+                    mm[u] = *(const bf8*)&Ms[64 * LP + o];
+                    ml[u] = *(const bf8*)&Ms[2 * 64 * LP + o];
+                }
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], mm, acc[i][j]);
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mh, acc[i][j]);
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xh[i], mh[u], acc[i][j0 + u]);
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xh[i], ml, acc[i][j]);
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xl[i], mh, acc[i][j]);
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xh[i], mm[u], acc[i][j0 + u]);
 #pragma unroll
-                for (int i = 0; i < IT; ++i) acc[i][j] = mma_bf(xm[i], mm, acc[i][j]);
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xm[i], mh[u], acc[i][j0 + u]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xh[i], ml[u], acc[i][j0 + u]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xl[i], mh[u], acc[i][j0 + u]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int i = 0; i < IT; ++i) acc[i][j0 + u] = mma_bf(xm[i], mm[u], acc[i][j0 + u]);
             }
         };
         // wide epilogue: 16-byte slices of rows of G, X and gradL^{k-1}
