@@ -2725,11 +2725,12 @@ __device__ __forceinline__ void body_residual(
                     }
             continue;
         }
-        // G, X and gradL^{k-1} of one 16 x 16 sub-tile per round; the next
-        // round's loads are issued before this round's arithmetic
+        // G, X and gradL^{k-1} of one 16 x 16 sub-tile per round; the loads
+        // of the next NB - 1 rounds are in flight during this round's arithmetic
         constexpr int NR = 4 * JT;
-        TG eg[2][4], ep[2][4];
-        T ex[2][4], exp_[XP ? 2 : 1][4];
+        constexpr int NB = 3;  // rounds of loads in flight
+        TG eg[NB][4], ep[NB][4];
+        T ex[NB][4], exp_[XP ? NB : 1][4];
         auto eload = [&](int rr, int sb) {
             const int i = rr / JT, j = rr % JT;
 #pragma unroll
@@ -2743,12 +2744,13 @@ __device__ __forceinline__ void body_residual(
                 if constexpr (XP) exp_[sb][q] = (ok && have_prev) ? Xprev[idx] : (T)0;
             }
         };
-        eload(0, 0);
+#pragma unroll
+        for (int rr = 0; rr < NB - 1 && rr < NR; ++rr) eload(rr, rr);
         double rsq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-            if (rr + 1 < NR) eload(rr + 1, (rr + 1) & 1);
-            const int i = rr / JT, j = rr % JT, sb = rr & 1;
+            if (rr + NB - 1 < NR) eload(rr + NB - 1, (rr + NB - 1) % NB);
+            const int i = rr / JT, j = rr % JT, sb = rr % NB;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = r0 + wr * 64 + i * 16 + Mma<T>::row(lk, q);
