@@ -1168,10 +1168,11 @@ __global__ __launch_bounds__(256) void k_gram_bf3(const float* __restrict__ X,
 // 32-row MFMA step, ~56 per entry: ~5e-7 relative on a chunk's partial, below
 // the 2^-16 of the split); with no float64 accumulators two workgroups fit on
 // a CU.  Partials as in k_gram.
+template <typename TP = double>
 __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
                                                   const float* __restrict__ G, int64_t n, int p,
                                                   int nb, int n_s_tiles, int n_tiles, int wup,
-                                                  int64_t chunk, double* __restrict__ part,
+                                                  int64_t chunk, TP* __restrict__ part,
                                                   const DevState* __restrict__ st, int bid_,
                                                   int nblk_, double* __restrict__ colsq = nullptr) {
     if (st && st->done) return;
@@ -1279,7 +1280,7 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
     }
     if (csq && yok) colsq[((size_t)c * 4 + lh) * p + yc + lc] = sq;
     if (below) return;
-    double* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
+    TP* out = part + ((size_t)c * n_tiles + tile) * (size_t)(128 * 128);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1288,13 +1289,15 @@ __device__ __forceinline__ void body_gram_bf3_lds(const float* __restrict__ X,
             for (int q = 0; q < 4; ++q) {
                 const int ii = wi * 64 + i * 16 + Mma<float>::row(g, q);
                 const int jj = wj * 64 + j * 16 + lr;
-                out[ii * 128 + jj] = (double)acc[i][j][q];
+                out[ii * 128 + jj] = (TP)acc[i][j][q];
             }
 }
+// The chunk partials are float32 sums, stored as float32 (exactly what a
+// float64 copy would hold, in half the bytes).
 __global__ __launch_bounds__(256, 2) void k_gram_bf3_lds(const float* __restrict__ X,
                                                       const float* __restrict__ G, int64_t n,
                                                       int p, int nb, int n_s_tiles, int n_tiles, int wup,
-                                                      int64_t chunk, double* __restrict__ part,
+                                                      int64_t chunk, float* __restrict__ part,
                                                       const DevState* __restrict__ st,
                                                       double* __restrict__ colsq = nullptr) {
     body_gram_bf3_lds(X, G, n, p, nb, n_s_tiles, n_tiles, wup, chunk, part, st, blockIdx.x,
@@ -1941,7 +1944,8 @@ __global__ __launch_bounds__(64 * (256 / RW)) void k_residual_bf6_lds(
 
 // Sum the chunk partials in a fixed order; S is written from its upper blocks
 // (entries with row <= col) and mirrored, so it is exactly symmetric.
-__device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part,
+template <typename TP = double>
+__device__ __forceinline__ void body_gram_reduce(const TP* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
                                                      int n_s_tiles, int wup, int p,
                                                      double* __restrict__ S,
@@ -1985,7 +1989,8 @@ __device__ __forceinline__ void body_gram_reduce(const double* __restrict__ part
     M[(size_t)r * p + c] = sum;
     if (mirrored) M[(size_t)c * p + r] = sum;
 }
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+template <typename TP>
+__global__ __launch_bounds__(256) void k_gram_reduce(const TP* __restrict__ part,
                                                      int nchunks, int n_tiles, int bt, int nb,
                                                      int n_s_tiles, int wup, int p,
                                                      double* __restrict__ S,
@@ -4083,6 +4088,7 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
     if (n_tiles == 0) return;
     GramPlan g2 = gp;
     g2.n_s_tiles = nst;
+    bool fpart = false;  // float32 chunk partials (the LDS split-bf16 pass)
     if (dtype == STF_F32 && precision == STF_PREC_MIXED) {
         const unsigned nwg = (unsigned)(n_tiles * gp.nchunks);
         const float* x = (const float*)X;
@@ -4093,9 +4099,11 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
         else if (gp.wm == 2)
             k_gram_bf3<2><<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
                                               part, st);
-        else
+        else {
             k_gram_bf3_lds<<<nwg, 256, 0, s>>>(x, gg, n, p, gp.nb, nst, n_tiles, wup, gp.chunk,
-                                               part, st, colsq);
+                                               (float*)part, st, colsq);
+            fpart = true;
+        }
     } else if (dtype == STF_F64) {
         if (colsq && gp.wm == 4)
             k_gram_lds<double><<<(unsigned)(n_tiles * gp.nchunks), 256, 0, s>>>(
@@ -4110,8 +4118,12 @@ void launch_gram(int dtype, int precision, const GramPlan& gp, const void* X, co
     }
     if (after_main) (void)hipEventRecord(after_main, s);
     const int64_t tot = (int64_t)n_tiles * gp.bt * gp.bt;
-    k_gram_reduce<<<(unsigned)((tot + 63) / 64), 256, 0, s>>>(part, gp.nchunks, n_tiles, gp.bt,
-                                                                 gp.nb, nst, wup, p, S, W, st);
+    if (fpart)
+        k_gram_reduce<float><<<(unsigned)((tot + 63) / 64), 256, 0, s>>>(
+            (const float*)part, gp.nchunks, n_tiles, gp.bt, gp.nb, nst, wup, p, S, W, st);
+    else
+        k_gram_reduce<double><<<(unsigned)((tot + 63) / 64), 256, 0, s>>>(
+            part, gp.nchunks, n_tiles, gp.bt, gp.nb, nst, wup, p, S, W, st);
 }
 
 void launch_stage1(const DevParams* prm, const double* S, const double* W, double* Psi,
