@@ -242,17 +242,18 @@ KERNEL_NAMES = {"grad": "k_grad_stencil", "gram": "k_gram", "residual": "k_resid
                 "update": "k_update", "hartree": "k_dst_xy + k_dst_z"}
 # the device function that does the work of each timed kernel, per form
 KERNEL_BODY = {("fp64", "residual"): "body_residual", ("fp64", "gram"): "body_gram_lds",
-               ("fp64", "grad"): "body_grad_stencil", ("fp64", "update"): "body_update",
+               ("fp64", "grad"): "body_grad_line", ("fp64", "update"): "body_update",
                ("mixed", "residual"): "body_residual_bf6_lds",
                ("mixed", "gram"): "body_gram_bf3_lds", ("mixed", "grad"): "body_grad_line",
                ("mixed", "update"): "body_update",
                ("mixed32", "residual"): "body_residual_bf6_lds",
                ("mixed32", "gram"): "body_gram_bf3_lds", ("mixed32", "grad"): "body_grad_line",
                ("mixed32", "update"): "k_update_v"}
-# kernels that differ from KERNEL_NAMES in one form (the 3D gradient with a
-# float32 G walks runs of rows)
-KERNEL_NAMES_FORM = {("mixed", "grad"): "k_grad_line", ("fp32", "grad"): "k_grad_line",
-                     ("mixed32", "grad"): "k_grad_line", ("mixed32", "update"): "k_update_v"}
+# kernels that differ from KERNEL_NAMES in one form (the 3D gradient walks
+# runs of rows)
+KERNEL_NAMES_FORM = {("fp64", "grad"): "k_grad_line", ("mixed", "grad"): "k_grad_line",
+                     ("fp32", "grad"): "k_grad_line", ("mixed32", "grad"): "k_grad_line",
+                     ("mixed32", "update"): "k_update_v"}
 
 
 def body_digest(name):

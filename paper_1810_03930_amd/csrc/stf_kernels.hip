@@ -4014,11 +4014,11 @@ void launch_grad(const stf_problem* prob, int dtype, const void* X, void* G, con
         typedef decltype(ti) TI;
         typedef decltype(to) TO;
         constexpr int ND = decltype(nd)::value;
-        // 3D with a float32 G: runs of kRun rows per wave when the rows split into
-        // 16-byte vectors (measured on 64^3 x 256: 0.27 against 0.32 ms for the
-        // one-wave-per-row form; no gain with a float64 G, and the 1D problems are
-        // too short for runs to fill the chip)
-        if constexpr (ND == 6 && sizeof(TO) == 4) {
+        // 3D: runs of kRun rows per wave when the rows split into 16-byte
+        // vectors (measured on 64^3 x 256: 0.27 against 0.32 ms for the
+        // one-wave-per-row form with a float32 G, 0.324 against 0.333 ms with a
+        // float64 G; the 1D problems are too short for runs to fill the chip)
+        if constexpr (ND == 6) {
             constexpr int kRun = 64;
             if (p % (16 / (int)sizeof(TI)) == 0 && !ex.glin && ex.gamma == 0.0) {
                 const int64_t gl = ((n + kRun - 1) / kRun + 3) / 4;
