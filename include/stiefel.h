@@ -259,7 +259,8 @@ typedef struct stf_options {
  * restarted : 1 when that float64 phase restarted from X^0 (see switch_tol):
  *           iters then counts the float64 iterations from X^0, after the
  *           switch_iter discarded float32 ones; history holds the float64
- *           rows from 0 (later rows of the float32 phase are left); 0 else   */
+ *           rows from 0 (later rows of the float32 phase are left); 0 else
+ * reserved  : set to 0                                                       */
 #define STF_PROF_HARTREE  0
 #define STF_PROF_GRAD     1
 #define STF_PROF_GRAM     2
