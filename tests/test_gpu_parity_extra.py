@@ -41,10 +41,15 @@ def _solve(prob, x0, gopt, history=False):
 
 
 @pytest.mark.parametrize("which,precision", [("ks3d", "fp64"), ("quad", "fp64"),
-                                             ("ks3d", "mixed")])
+                                             ("ks3d_wide", "fp64"), ("ks3d", "mixed")])
 def test_stop_test_history_matches_oracle(which, precision):
+    """ks3d_wide: p = 130 takes the p x p stage's wide path (64 x 64 tiles of
+    S (B + 2 M_L) split over K, three of them ragged)."""
     if which == "ks3d":
         prob, x0, _ = W.ks3d(grid=(12, 10, 9), p=10)
+        beta = 4.0
+    elif which == "ks3d_wide":
+        prob, x0, _ = W.ks3d(grid=(20, 18, 16), p=130)
         beta = 4.0
     else:
         prob, x0 = W.quad_tridiag(n=800, p=16)
