@@ -70,7 +70,8 @@ ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fused) {
+Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fused,
+                   bool solver) {
     Layout L;
     memset(&L, 0, sizeof(L));
     const int64_t n = prob->n;
@@ -99,7 +100,7 @@ Layout make_layout(const stf_problem* prob, int precision, bool moptqr, bool fus
         L.x64 = take(np * 8);
         L.g64 = take(np * 8);
         L.g64b = take(np * 8);
-        L.x0keep = take(np * 4);
+        L.x0keep = solver ? take(np * 4) : (size_t)-1;
     }
     L.rho = take((size_t)n * 8);
     L.phi = take((size_t)n * 8);
@@ -454,7 +455,7 @@ static int solve_impl(const stf_problem* prob, void* X, const stf_options* opt, 
 
     Ws w;
     w.base = (char*)ws;
-    w.L = make_layout(prob, opt->precision, moptqr, fused);
+    w.L = make_layout(prob, opt->precision, moptqr, fused, true);
     if (ws_bytes < w.L.total) return STF_E_WORKSPACE;
     memset(res, 0, sizeof(*res));
     const int64_t n = prob->n;
@@ -758,10 +759,11 @@ extern "C" {
 size_t stf_workspace_size(const stf_problem* prob, const stf_options* opt) {
     if (check_problem(prob) != STF_OK) return 0;
     if (opt)
-        return make_layout(prob, opt->precision, opt->variant == STF_MOPTQR, opt->fused != 0)
+        return make_layout(prob, opt->precision, opt->variant == STF_MOPTQR, opt->fused != 0,
+                           true)
             .total;
-    const size_t a = make_layout(prob, STF_PREC_FP64, true, true).total;
-    const size_t b = make_layout(prob, STF_PREC_FP32, false, true).total;
+    const size_t a = make_layout(prob, STF_PREC_FP64, true, true, true).total;
+    const size_t b = make_layout(prob, STF_PREC_FP32, false, true, true).total;
     return a > b ? a : b;
 }
 

@@ -104,7 +104,7 @@ struct Layout {
     size_t g[2];          // G / gradL double buffer, n*p elements of the iteration dtype
     size_t x64, g64;      // float64 n*p buffers: master iterate (float32 forms) and scratch
     size_t g64b;          // second float64 n*p buffer (float32 forms): float64 continuation
-    size_t x0keep;        // n*p float32 (float32 forms): X^0, kept for a float64 restart
+    size_t x0keep;        // n*p float32 (float32 forms, solver layout): X^0 for a float64 restart
     size_t rho, phi, hscr;
     size_t S, W, Psi, ML, Rm, Rinv, Lam, Bm, T1, fpart;  // T1: p x p product-pass partials
     size_t nu, colpart;   // colpart: col_groups(res.nrb) x 2p column-dot partials
@@ -179,8 +179,10 @@ int elem_size(int dtype);
 GramPlan make_gram_plan(int64_t n, int p, int64_t target_wg = 512, bool wup = false);
 ResPlan make_res_plan(int64_t n, int p, int tile, int64_t target_wg = 0);
 // fused: the buffers of the single-pass form (and the second iterate buffer xalt)
+// solver = true: the layout of stf_solve (with the float32 copy of X^0 that
+// a float64 restart needs in the float32 forms)
 Layout make_layout(const stf_problem* prob, int precision, bool moptqr = false,
-                   bool fused = false);
+                   bool fused = false, bool solver = false);
 size_t align256(size_t x);
 
 // A problem's workspace: base address and layout.
