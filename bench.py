@@ -411,11 +411,24 @@ def batched_main(args, torch, S, W):
             rk, rck, _ = S.solve_batched(dps, Xs, opts(prec, MAX_ITER, TOL), workspace=ws,
                                          budgets=budgets, stream=stream)
             torch.cuda.synchronize()
+            # the same solves one problem after another (the single-problem
+            # solver, one graph-replayed loop per problem)
+            reload()
+            log(f"batched {prec}: time to KKT one problem after another")
+            t_serial_kkt = 0.0
+            conv_serial = 0
+            for dp, X, o in zip(dps, Xs, opts(prec, MAX_ITER, TOL)):
+                r, _, _ = S.solve(dp, X, o, stream=stream, raise_on_error=False)
+                t_serial_kkt += r["ms_loop"] + r["ms_orth"]
+                conv_serial += int(r["rc"] == 0)
+            torch.cuda.synchronize()
         conv = sum(1 for r in rk if r["status"] == 0)
         out[prec] = {"aggregate_iters_per_s": agg, "ms_per_batch_iter": msi,
                      "serial_aggregate_iters_per_s": agg_serial,
                      "speedup_vs_serial": agg / agg_serial, "budgets": list(budgets),
                      "time_to_kkt_s": (rk[0]["ms_loop"] + rk[0]["ms_orth"]) / 1000.0,
+                     "serial_time_to_kkt_s": t_serial_kkt / 1000.0,
+                     "serial_converged": conv_serial,
                      "converged": conv, "max_iters": max(r["iters"] for r in rk),
                      "switched": sum(1 for r in rk if r["switch_iter"] >= 0),
                      "worst_kkt_rel": max(r["kkt_rel"] for r in rk)}
